@@ -1,0 +1,54 @@
+"""Condensed KKT system of the pivoting-free IPM (test infrastructure only).
+
+Section 3 (eq. kkt_system) gives the regularised Newton system in
+(d_x, d_s, -d_lambda); eliminating d_s gives the augmented system
+(eq. augmentedKKT) and eliminating d_lambda the primal condensed system
+(eq. kkt_primal):  (H + delta_p I + J' (delta_d I + Lambda^{-1} S)^{-1} J) d_x
+= -r.  The paper leaves the right-hand side unstated ("an appropriate
+right-hand side"); with variable bounds and general complementarity
+targets (t_s, t_l, t_u) the elimination gives
+
+  Sigma_s = lambda / (s + delta_d lambda)        (= (delta_d I + S/Lambda)^-1)
+  Sigma_x = z_l/(x - l) + z_u/(u - x)
+  K       = H + diag(Sigma_x + delta_p) + J' diag(Sigma_s) J
+  r~_d    = r_d - t_l/(x-l) + z_l + t_u/(u-x) - z_u
+  rhs     = -r~_d - J' [Sigma_s (g - t_s/lambda)]
+  d_lam   = Sigma_s (t_s/lambda - g - J d_x)
+  d_s     = J d_x + r_p + delta_d d_lam
+  d_zl    = t_l/(x-l) - z_l - (z_l/(x-l)) d_x
+  d_zu    = t_u/(u-x) - z_u + (z_u/(u-x)) d_x
+Bound terms only exist on finite bounds (masks il, iu).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+
+def sigmas(x, s, lam, zl, zu, xl, xu, il, iu, delta_d):
+    sig_s = lam / (s + delta_d * lam)
+    sig_x = np.zeros_like(x)
+    sig_x[il] += zl[il] / (x[il] - xl[il])
+    sig_x[iu] += zu[iu] / (xu[iu] - x[iu])
+    return sig_s, sig_x
+
+
+def condensed_matrix(H, J, sig_s, sig_x, delta_p):
+    n = H.shape[0]
+    return (H + sp.diags(sig_x + delta_p) + J.T @ sp.diags(sig_s) @ J).tocsr()
+
+
+def condensed_rhs(J, r_d, g, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u):
+    rt = r_d.copy()
+    rt[il] += -t_l[il] / (x[il] - xl[il]) + zl[il]
+    rt[iu] += t_u[iu] / (xu[iu] - x[iu]) - zu[iu]
+    return -rt - J.T @ (sig_s * (g - t_s / lam))
+
+
+def recover(J, dx, g, r_p, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u, delta_d):
+    Jdx = J @ dx
+    dlam = sig_s * (t_s / lam - g - Jdx)
+    ds = Jdx + r_p + delta_d * dlam
+    dzl = np.zeros_like(x)
+    dzu = np.zeros_like(x)
+    dzl[il] = t_l[il] / (x[il] - xl[il]) - zl[il] - zl[il] / (x[il] - xl[il]) * dx[il]
+    dzu[iu] = t_u[iu] / (xu[iu] - x[iu]) - zu[iu] + zu[iu] / (xu[iu] - x[iu]) * dx[iu]
+    return ds, dlam, dzl, dzu

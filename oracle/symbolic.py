@@ -1,0 +1,338 @@
+"""Symbolic analysis of the condensed KKT matrix: fill-reducing ordering,
+elimination tree, column counts and supernodes.
+
+The paper factors P'KP = LDL' (Section 2, LDL^T factorization) with a
+fill-reducing permutation computed once on the CPU and reused (Section 2,
+GPU direct solvers: minimum degree or nested dissection).  It fixes no
+particular ordering, so this module follows one exact rule (the library
+implements the same rule independently and must agree bit for bit):
+
+ORD  Graph G = structure of K without its diagonal.
+     order(S): connected components of G[S] in increasing order of their
+       smallest vertex, each ordered by order_component.
+     order_component(C):
+       |C| <= leaf: exact minimum degree on G[C] (minimum current degree,
+         ties to the smallest vertex; neighbours of the eliminated vertex
+         become a clique).
+       otherwise: root r = pseudo-peripheral vertex (start at the vertex of
+         minimum degree in G[C], move to the minimum-degree vertex of the last
+         BFS level while the BFS height grows; ties to the smallest vertex);
+         BFS levels L_0..L_h from r; if h < 2 the natural (sorted) order;
+         else separator level l in [1, h-1] minimising
+         |L_l| / min(|L_<l|, |L_>l|), then |2l - h|, then l;
+         result order(L_<l) ++ order(L_>l) ++ sorted(L_l).
+     The ND order is then composed with a postorder of the elimination tree
+     (children in increasing index, roots in increasing index).
+SYM  struct(j) = row indices below the diagonal of column j of L;
+     colcount c_j = |struct(j)| + 1; parent(j) = min struct(j) (or -1).
+     Fundamental supernodes: j+1 joins j when parent(j) = j+1,
+     c_j = c_{j+1} + 1 and j is the only child of j+1.
+     Relaxed amalgamation (parameters max_w, small_w, zero fraction num/den):
+     scanning supernodes s left to right, while the supernode c ending just
+     before s is a child of s: with w = w_c + w_s, h = w_c + h_s,
+     total = w*h - w(w-1)/2 and zeros = total - (true entries of c and s),
+     merge c into s if w <= max_w and (w <= small_w or zeros*den <= num*total).
+     Supernode rows = its columns followed by struct(last column).
+
+Plain Python; meant for inputs up to a few tens of thousands of columns.
+"""
+from collections import deque
+
+import numpy as np
+import scipy.sparse as sp
+
+AMALGAMATION_MENU = [(64, 8, 1, 10), (128, 16, 1, 20), (32, 4, 1, 5)]
+ND_LEAF = 64
+
+
+# ----------------------------------------------------------------- pattern
+def kkt_pattern(n, J_rowptr, J_colind, H_rowptr=None, H_colind=None):
+    """Adjacency lists (no self loops) of the structure of
+    K = H + diag + J'J, from CSR patterns of J (m x n) and lower H (n x n)."""
+    m = len(J_rowptr) - 1
+    nnzj = int(J_rowptr[-1])
+    Jb = sp.csr_matrix((np.ones(nnzj), np.asarray(J_colind), np.asarray(J_rowptr)),
+                       shape=(m, n))
+    S = (Jb.T @ Jb).tocsr()
+    if H_rowptr is not None:
+        nnzh = int(H_rowptr[-1])
+        Hb = sp.csr_matrix((np.ones(nnzh), np.asarray(H_colind), np.asarray(H_rowptr)),
+                           shape=(n, n))
+        S = S + Hb + Hb.T
+    return adjacency_from_sym(S.tocsr(), n)
+
+
+def pattern_from_lower_csr(n, rowptr, colind):
+    nnz = int(rowptr[-1])
+    L = sp.csr_matrix((np.ones(nnz), np.asarray(colind), np.asarray(rowptr)), shape=(n, n))
+    return adjacency_from_sym((L + L.T).tocsr(), n)
+
+
+def adjacency_from_sym(S, n):
+    S.sort_indices()
+    adj = []
+    for v in range(n):
+        row = S.indices[S.indptr[v]:S.indptr[v + 1]]
+        adj.append([int(u) for u in row if u != v])
+    return adj
+
+
+# ---------------------------------------------------------------- ordering
+def _components(adj, verts, inset):
+    """Connected components of G[verts] (inset marks membership), each sorted,
+    in increasing order of their smallest vertex."""
+    seen = set()
+    comps = []
+    for v in sorted(verts):
+        if v in seen:
+            continue
+        comp = [v]
+        seen.add(v)
+        q = deque([v])
+        while q:
+            u = q.popleft()
+            for w in adj[u]:
+                if inset[w] and w not in seen:
+                    seen.add(w)
+                    comp.append(w)
+                    q.append(w)
+        comps.append(sorted(comp))
+    return comps
+
+
+def _bfs_levels(adj, root, inset):
+    levels = [[root]]
+    seen = {root}
+    while True:
+        nxt = []
+        for u in levels[-1]:
+            for w in adj[u]:
+                if inset[w] and w not in seen:
+                    seen.add(w)
+                    nxt.append(w)
+        if not nxt:
+            return levels
+        levels.append(nxt)
+
+
+def _min_degree_vertex(cands, deg):
+    return min(cands, key=lambda v: (deg[v], v))
+
+
+def pseudo_peripheral(adj, comp, inset):
+    deg = {v: sum(1 for w in adj[v] if inset[w]) for v in comp}
+    r = _min_degree_vertex(comp, deg)
+    levels = _bfs_levels(adj, r, inset)
+    while True:
+        v = _min_degree_vertex(levels[-1], deg)
+        lv = _bfs_levels(adj, v, inset)
+        if len(lv) > len(levels):
+            r, levels = v, lv
+        else:
+            return r, levels
+
+
+def exact_minimum_degree(adj, comp, inset):
+    nbr = {v: set(w for w in adj[v] if inset[w]) for v in comp}
+    remaining = set(comp)
+    out = []
+    while remaining:
+        v = min(remaining, key=lambda u: (len(nbr[u]), u))
+        out.append(v)
+        clique = nbr[v]
+        for u in clique:
+            nbr[u] |= clique
+            nbr[u].discard(u)
+            nbr[u].discard(v)
+        remaining.discard(v)
+        del nbr[v]
+    return out
+
+
+def _choose_separator(levels):
+    h = len(levels) - 1
+    sizes = [len(L) for L in levels]
+    total = sum(sizes)
+    best = None
+    below = sizes[0]
+    for l in range(1, h):
+        above = total - below - sizes[l]
+        denom = min(below, above)
+        # compare sizes[l]/denom exactly: key as a fraction
+        cand = (sizes[l], denom, abs(2 * l - h), l)
+        if best is None:
+            best = cand
+        else:
+            lhs = cand[0] * best[1]
+            rhs = best[0] * cand[1]
+            if lhs < rhs or (lhs == rhs and (cand[2], cand[3]) < (best[2], best[3])):
+                best = cand
+        below += sizes[l]
+    return best[3]
+
+
+def nested_dissection(adj, n, leaf=ND_LEAF):
+    """ND order as a list: entry k = vertex placed at position k."""
+    out = []
+    inset = [False] * n
+    # work stack of ("order", vertex list) or ("emit", vertex list)
+    stack = [("order", list(range(n)))]
+    while stack:
+        kind, verts = stack.pop()
+        if kind == "emit":
+            out.extend(verts)
+            continue
+        for v in verts:
+            inset[v] = True
+        comps = _components(adj, verts, inset)
+        tasks = []
+        for comp in comps:
+            if len(comp) <= leaf:
+                tasks.append(("emit", exact_minimum_degree(adj, comp, inset)))
+                continue
+            _, levels = pseudo_peripheral(adj, comp, inset)
+            h = len(levels) - 1
+            if h < 2:
+                tasks.append(("emit", sorted(comp)))
+                continue
+            l = _choose_separator(levels)
+            lower = [v for L in levels[:l] for v in L]
+            upper = [v for L in levels[l + 1:] for v in L]
+            tasks.append(("order", sorted(lower)))
+            tasks.append(("order", sorted(upper)))
+            tasks.append(("emit", sorted(levels[l])))
+        for v in verts:
+            inset[v] = False
+        for t in reversed(tasks):
+            stack.append(t)
+    return out
+
+
+# --------------------------------------------------------------- symbolic
+def permuted_lower_columns(adj, perm):
+    """For each column j of P'KP, the sorted row indices i > j."""
+    n = len(perm)
+    pinv = np.empty(n, dtype=np.int64)
+    pinv[np.asarray(perm, dtype=np.int64)] = np.arange(n)
+    cols = []
+    for j in range(n):
+        rows = pinv[np.asarray(adj[perm[j]], dtype=np.int64)]
+        cols.append(np.sort(rows[rows > j]))
+    return cols
+
+
+def symbolic_factor(lower_cols):
+    """Column structures of L (below the diagonal), elimination tree."""
+    n = len(lower_cols)
+    parent = np.full(n, -1, dtype=np.int64)
+    pending = [[] for _ in range(n)]
+    structs = []
+    for j in range(n):
+        parts = [lower_cols[j]] + [s[1:] for s in pending[j]]
+        pending[j] = None
+        st = np.unique(np.concatenate(parts)) if len(parts) > 1 else lower_cols[j]
+        structs.append(st)
+        if len(st):
+            p = int(st[0])
+            parent[j] = p
+            pending[p].append(st)
+    return structs, parent
+
+
+def postorder(parent):
+    n = len(parent)
+    children = [[] for _ in range(n)]
+    roots = []
+    for j in range(n):
+        (roots if parent[j] < 0 else children[parent[j]]).append(j)
+    out = []
+    for r in roots:
+        stack = [(r, 0)]
+        while stack:
+            v, i = stack.pop()
+            if i < len(children[v]):
+                stack.append((v, i + 1))
+                stack.append((children[v][i], 0))
+            else:
+                out.append(v)
+    return out
+
+
+def fundamental_supernodes(parent, cc):
+    n = len(parent)
+    nchild = np.zeros(n, dtype=np.int64)
+    for j in range(n):
+        if parent[j] >= 0:
+            nchild[parent[j]] += 1
+    starts = [0] if n else []
+    for j in range(n - 1):
+        joins = parent[j] == j + 1 and cc[j] == cc[j + 1] + 1 and nchild[j + 1] == 1
+        if not joins:
+            starts.append(j + 1)
+    return starts
+
+
+def amalgamate(starts, parent, cc, menu=AMALGAMATION_MENU[0]):
+    max_w, small_w, num, den = menu
+    n = len(parent)
+    sns = [[s, e - 1] for s, e in zip(starts, starts[1:] + [n])]  # inclusive
+    true_nz = [int(np.sum(cc[a:b + 1])) for a, b in sns]
+    owner = np.empty(n, dtype=np.int64)
+    for k, (a, b) in enumerate(sns):
+        owner[a:b + 1] = k
+    # owner ids must stay valid while the list shrinks: keep ids stable by
+    # giving each supernode a token, mapping columns to tokens.
+    token = list(range(len(sns)))
+    i = 0
+    while i < len(sns):
+        while i > 0:
+            c_first, c_last = sns[i - 1]
+            s_first, s_last = sns[i]
+            p = parent[c_last]
+            if p < 0 or owner[p] != token[i]:
+                break
+            wc = c_last - c_first + 1
+            ws = s_last - s_first + 1
+            hs = ws + int(cc[s_last]) - 1
+            w = wc + ws
+            h = wc + hs
+            if w > max_w:
+                break
+            total = w * h - w * (w - 1) // 2
+            zeros = total - (true_nz[i - 1] + true_nz[i])
+            if not (w <= small_w or zeros * den <= num * total):
+                break
+            owner[c_first:c_last + 1] = token[i]
+            sns[i] = [c_first, s_last]
+            true_nz[i] += true_nz[i - 1]
+            del sns[i - 1], true_nz[i - 1], token[i - 1]
+            i -= 1
+        i += 1
+    return [a for a, _ in sns] + [n]
+
+
+def analyze(adj, n, leaf=ND_LEAF, menu=AMALGAMATION_MENU[0]):
+    """Full symbolic analysis.  Returns a dict with perm (perm[k] = original
+    index at position k), etree, colcount, sn_start, sn_rowptr, sn_rows,
+    nnz_L (true) and flops = sum_j (c_j^2 - 1)."""
+    nd = nested_dissection(adj, n, leaf)
+    cols = permuted_lower_columns(adj, nd)
+    _, par0 = symbolic_factor(cols)
+    post = postorder(par0)
+    perm = [nd[k] for k in post]
+    cols = permuted_lower_columns(adj, perm)
+    structs, parent = symbolic_factor(cols)
+    cc = np.array([len(s) + 1 for s in structs], dtype=np.int64)
+    fund = fundamental_supernodes(parent, cc)
+    sn_start = amalgamate(fund, parent, cc, menu)
+    rowptr = [0]
+    rows = []
+    for a, b in zip(sn_start[:-1], sn_start[1:]):
+        r = np.concatenate([np.arange(a, b), structs[b - 1]]).astype(np.int32)
+        rows.append(r)
+        rowptr.append(rowptr[-1] + len(r))
+    return dict(perm=np.asarray(perm, dtype=np.int32), etree=parent.astype(np.int32),
+                colcount=cc, sn_start=np.asarray(sn_start, dtype=np.int32),
+                sn_rowptr=np.asarray(rowptr, dtype=np.int64),
+                sn_rows=np.concatenate(rows) if rows else np.zeros(0, np.int32),
+                structs=structs, nnz_L=int(cc.sum()), flops=int(np.sum(cc * cc - 1)))

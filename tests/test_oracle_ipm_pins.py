@@ -1,0 +1,182 @@
+"""Pins of the oracle's interior-point solver against results the
+mathematics fixes independently of it (test infrastructure).
+
+P1 vertex enumeration of tiny LPs (an LP optimum is attained at a vertex)
+P2 closed-form QP optima (separable box QP; one-constraint diagonal QP)
+P3 NLP special cases (c = 0 gives x* = 0; small c leaves constraints
+   inactive so x* solves x^3 + c + Lx = 0)
+P7 duality gap and interior invariants along the iteration
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import checker, ipm, model
+from paper_2508_16094_amd import workloads as w
+
+
+def _vertex_enumeration_lp(p):
+    """min c'x over {Ax >= b, l <= x <= u} by enumerating every basis."""
+    A = p.A.to_scipy().toarray()
+    n = p.n
+    G = np.vstack([A, np.eye(n), -np.eye(n)])
+    h = np.concatenate([p.b, p.xl, -p.xu])
+    best = np.inf
+    for rows in itertools.combinations(range(G.shape[0]), n):
+        M = G[list(rows)]
+        if abs(np.linalg.det(M)) < 1e-10:
+            continue
+        x = np.linalg.solve(M, h[list(rows)])
+        if np.all(G @ x >= h - 1e-9):
+            best = min(best, float(p.c @ x))
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_p1_tiny_lp_vertex_enumeration(seed):
+    n, m = 4 + seed % 3, 3 + seed % 4
+    p = w.random_lp(n, m, min(3, m), 777 + seed)
+    f_star = _vertex_enumeration_lp(p)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert abs(r["f"] - f_star) <= 1e-7 * max(1.0, abs(f_star))
+
+
+class _P:
+    pass
+
+
+def _box_qp(n, seed, with_constraint):
+    rng = np.random.default_rng(seed)
+    p = _P()
+    p.n = n
+    q = rng.uniform(0.5, 2.0, n)
+    p.c = rng.standard_normal(n) * 3
+    p.Q = w.CSR(n, n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), q)
+    p.q4 = None
+    p.W = None
+    p.xl = rng.uniform(-2, 0, n)
+    p.xu = p.xl + rng.uniform(0.5, 3.0, n)
+    if with_constraint:
+        a = rng.uniform(0.2, 1.0, n)
+        p.m = 1
+        p.A = w.CSR(1, n, np.array([0, n], dtype=np.int64), np.arange(n, dtype=np.int32), a)
+        x_free = np.clip(-p.c / q, p.xl, p.xu)
+        # choose beta so that the constraint is active at the optimum
+        beta = float(a @ x_free) + 0.3 * float(a @ (p.xu - x_free))
+        p.b = np.array([beta])
+    else:
+        p.m = 0
+        p.A = None
+        p.b = np.zeros(0)
+    return p, q
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p2_separable_box_qp_closed_form(seed):
+    p, q = _box_qp(12, 100 + seed, False)
+    x_star = np.clip(-p.c / q, p.xl, p.xu)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert np.max(np.abs(r["x"] - x_star)) <= 1e-6
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p2_one_constraint_qp_bisection(seed):
+    p, q = _box_qp(15, 200 + seed, True)
+    a = p.A.val
+    beta = p.b[0]
+
+    def x_of(nu):
+        return np.clip((a * nu - p.c) / q, p.xl, p.xu)
+
+    lo, hi = 0.0, 1.0
+    while a @ x_of(hi) < beta:
+        hi *= 2
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if a @ x_of(mid) < beta:
+            lo = mid
+        else:
+            hi = mid
+    nu = 0.5 * (lo + hi)
+    x_star = x_of(nu)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert np.max(np.abs(r["x"] - x_star)) <= 1e-6
+    assert abs(r["lam"][0] - nu) <= 1e-5 * max(1.0, nu)
+
+
+def test_p3_nlp_zero_linear_term():
+    p = w.nlp_grid(12, 12)
+    p.c = np.zeros(p.n)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert np.max(np.abs(r["x"])) <= 1e-5
+    assert abs(r["f"]) <= 1e-9
+    assert np.max(np.abs(r["lam"])) <= 1e-6
+
+
+def test_p3_nlp_inactive_constraints_newton_root():
+    p = w.nlp_grid(14, 10)
+    p.c = 1e-2 * p.c
+    L = model.q_full(p)
+    # independent damped Newton on x^3 + c + Lx = 0
+    x = np.zeros(p.n)
+    for _ in range(100):
+        F = x ** 3 + p.c + L @ x
+        Jm = (L + np.diag(3 * x ** 2)) if False else (L.toarray() + np.diag(3 * x ** 2))
+        dx = np.linalg.solve(Jm, -F)
+        x = x + dx
+        if np.max(np.abs(dx)) < 1e-15:
+            break
+    assert np.all(model.constraints(p, x) > 0)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert np.max(np.abs(r["x"] - x)) <= 1e-6
+
+
+@pytest.mark.parametrize("maker", ["lp", "qp"])
+def test_p7_duality_and_invariants(maker):
+    p = w.lp_small() if maker == "lp" else w.qp_instance(200, 5)
+    r = ipm.solve(p, tol=1e-9)
+    assert r["status"] == ipm.OK
+    d = checker.lp_qp_dual_objective(p, r["x"], r["lam"], r["zl"], r["zu"])
+    assert abs(r["f"] - d) <= 1e-7 * (1 + abs(r["f"]))
+    for h in r["history"]:
+        assert h["min_s"] > 0 and h["min_lam"] > 0 and h["min_z"] > 0
+        assert h["min_xl"] > 0 and h["min_xu"] > 0
+    chk = checker.check(p, r["x"], r["s"], r["lam"], r["zl"], r["zu"])
+    assert chk["P"] <= 1e-9 and chk["D"] <= 1e-9 and chk["C"] <= 1e-9
+
+
+def test_p7_fraction_to_boundary():
+    """s_new >= (1 - tau) s_old componentwise, tau >= 0.99."""
+    p = w.lp_small(1)
+    r = ipm.solve(p, tol=1e-8)
+    assert r["status"] == ipm.OK
+    assert all(0 < h["alpha_p"] <= 1 and 0 < h["alpha_d"] <= 1 for h in r["history"])
+
+
+def test_inertia_correction_path_forced():
+    """A forced non-positive pivot runs the regularisation loop and the
+    solve still converges (delta_w enlarges K's diagonal)."""
+    p = w.qp_instance(120, 2)
+    r = ipm.solve(p, tol=1e-8, force_inertia=True)
+    assert r["status"] == ipm.OK
+    assert all(h["delta_w"] > 0 for h in r["history"])
+
+
+def test_max_iter_status():
+    r = ipm.solve(w.lp_small(), max_iter=2)
+    assert r["status"] == ipm.MAX_ITER and r["iterations"] == 2
+
+
+def test_warm_start_from_solution_converges_fast():
+    p = w.qp_instance(200, 7)
+    cold = ipm.solve(p, tol=1e-8)
+    warm = ipm.solve(p, tol=1e-8, start=(cold["x"], cold["lam"]))
+    assert warm["status"] == ipm.OK
+    assert abs(warm["f"] - cold["f"]) <= 1e-6 * (1 + abs(cold["f"]))
+    assert warm["iterations"] <= cold["iterations"]

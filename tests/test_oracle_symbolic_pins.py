@@ -1,0 +1,153 @@
+"""Pins of the oracle's symbolic analysis (test infrastructure).
+
+P6: dense boolean elimination (brute force) gives the fill, elimination tree,
+column counts and fundamental supernodes; an explicit-matrix minimum degree
+elimination cross-checks the set-based one; hand-derived orders for a path,
+a 3x3 grid, a star, two cliques joined by a separator, and a disconnected
+graph pin the ordering rule (its steps are listed in oracle/symbolic.py).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import symbolic
+
+
+def _adj_from_edges(n, edges):
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        if a != b:
+            adj[a].add(b); adj[b].add(a)
+    return [sorted(s) for s in adj]
+
+
+def _brute_symbolic(adj, perm):
+    n = len(perm)
+    pinv = np.empty(n, int); pinv[perm] = np.arange(n)
+    M = np.zeros((n, n), bool)
+    for v in range(n):
+        for u in adj[v]:
+            M[pinv[v], pinv[u]] = True
+    for k in range(n):
+        R = np.nonzero(M[k + 1:, k])[0] + k + 1
+        M[np.ix_(R, R)] = True
+        M[R, k] = True
+    structs = [np.nonzero(M[j + 1:, j])[0] + j + 1 for j in range(n)]
+    parent = np.array([s[0] if len(s) else -1 for s in structs])
+    cc = np.array([len(s) + 1 for s in structs])
+    return structs, parent, cc
+
+
+def _random_graph(n, seed, p=0.08):
+    rng = np.random.default_rng(seed)
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    return _adj_from_edges(n, edges)
+
+
+@pytest.mark.parametrize("n,seed", [(30, 1), (90, 2), (200, 3), (300, 4)])
+def test_p6_brute_force_structure(n, seed):
+    adj = _random_graph(n, seed, p=3.0 / n)
+    r = symbolic.analyze(adj, n, menu=(1, 0, 0, 1))   # no amalgamation
+    structs, parent, cc = _brute_symbolic(adj, r["perm"])
+    assert sorted(r["perm"].tolist()) == list(range(n))
+    assert np.array_equal(parent, r["etree"])
+    assert np.array_equal(cc, r["colcount"])
+    for a, b in zip(r["structs"], structs):
+        assert np.array_equal(a, b)
+    # fundamental supernodes straight from the definition on the brute data
+    nchild = np.bincount(parent[parent >= 0], minlength=n)
+    starts = [0] + [j + 1 for j in range(n - 1)
+                    if not (parent[j] == j + 1 and cc[j] == cc[j + 1] + 1 and nchild[j + 1] == 1)]
+    assert r["sn_start"].tolist() == starts + [n]
+    # supernode rows = columns + structure of the last column
+    for k in range(len(starts)):
+        a, b = r["sn_start"][k], r["sn_start"][k + 1]
+        rows = r["sn_rows"][r["sn_rowptr"][k]:r["sn_rowptr"][k + 1]]
+        assert rows.tolist() == list(range(a, b)) + structs[b - 1].tolist()
+    # postordered: every subtree is a contiguous range ending at its root
+    size = np.ones(n, int)
+    for j in range(n):
+        if parent[j] >= 0:
+            size[parent[j]] += size[j]
+    for j in range(n):
+        if parent[j] >= 0:
+            assert j >= parent[j] - size[parent[j]] + 1
+
+
+def _md_dense(adj, verts):
+    verts = sorted(verts)
+    idx = {v: k for k, v in enumerate(verts)}
+    M = np.zeros((len(verts), len(verts)), bool)
+    for v in verts:
+        for u in adj[v]:
+            if u in idx:
+                M[idx[v], idx[u]] = True
+    alive = np.ones(len(verts), bool)
+    out = []
+    for _ in verts:
+        deg = np.where(alive, (M & alive[None, :]).sum(1), 10 ** 9)
+        k = int(np.argmin(deg))            # argmin takes the smallest index on ties
+        out.append(verts[k])
+        nb = np.nonzero(M[k] & alive)[0]
+        M[np.ix_(nb, nb)] = True
+        M[nb, nb] = False
+        alive[k] = False
+    return out
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_p6_minimum_degree_cross_check(seed):
+    n = 40 + seed * 5
+    adj = _random_graph(n, 50 + seed, p=0.1)
+    inset = [True] * n
+    got = symbolic.exact_minimum_degree(adj, list(range(n)), inset)
+    assert got == _md_dense(adj, range(n))
+
+
+def test_p6_path_hand_derived():
+    n = 200
+    adj = _adj_from_edges(n, [(i, i + 1) for i in range(n - 1)])
+    nd = symbolic.nested_dissection(adj, n)
+    expect = (list(range(0, 49)) + list(range(50, 99)) + [49]
+              + list(range(100, 149)) + list(range(150, 200)) + [149, 99])
+    assert nd == expect
+    r = symbolic.analyze(adj, n)
+    assert r["perm"].tolist() == expect
+
+
+def test_p6_grid3x3_hand_derived():
+    edges = []
+    for i in range(3):
+        for j in range(3):
+            if i < 2: edges.append((3 * i + j, 3 * i + j + 3))
+            if j < 2: edges.append((3 * i + j, 3 * i + j + 1))
+    adj = _adj_from_edges(9, edges)
+    assert symbolic.nested_dissection(adj, 9) == [0, 2, 6, 8, 1, 3, 4, 5, 7]
+    r = symbolic.analyze(adj, 9)
+    assert r["perm"].tolist() == [8, 6, 0, 2, 1, 3, 4, 5, 7]
+
+
+def test_p6_star_hand_derived():
+    n = 100
+    adj = _adj_from_edges(n, [(0, i) for i in range(1, n)])
+    r = symbolic.analyze(adj, n)
+    assert r["perm"].tolist() == list(range(1, n)) + [0]
+    assert r["sn_start"].tolist() == list(range(0, 93)) + [100]
+
+
+def test_p6_two_cliques_and_separator_hand_derived():
+    A = list(range(0, 40)); B = list(range(42, 82)); S = [40, 41]
+    edges = [(a, b) for X in (A, B) for a in X for b in X if a < b]
+    edges += [(s, v) for s in S for v in A + B] + [(40, 41)]
+    adj = _adj_from_edges(82, edges)
+    assert symbolic.nested_dissection(adj, 82) == [0] + B + list(range(1, 42))
+    r = symbolic.analyze(adj, 82)
+    assert r["perm"].tolist() == B + list(range(0, 42))
+
+
+def test_p6_disconnected_components_in_order():
+    # path 3-0-6 and a star centred at 4 with leaves 1, 2, 5, 7, 8; both are
+    # leaf components, ordered by minimum degree with smallest-index ties
+    adj = _adj_from_edges(9, [(3, 0), (0, 6), (4, 1), (4, 2), (4, 5), (4, 7), (4, 8)])
+    nd = symbolic.nested_dissection(adj, 9)
+    assert nd == [3, 0, 6, 1, 2, 5, 7, 4, 8]
