@@ -1,0 +1,229 @@
+/*
+ * pdipm — C ABI of the MI355X (gfx950) hot path of a pivoting-free
+ * primal-dual interior-point method (arXiv 2508.16094).
+ *
+ * Problem class (Section 1, problem (1), with variable bounds):
+ *     minimise   f(x) = c'x + 1/2 x'Qx + sum_i q4_i x_i^4 / 4
+ *     subject to g(x) = A x - b - W (x o x) >= 0,    xl <= x <= xu
+ * Derivatives evaluated on fixed sparsity patterns (Section 4):
+ *     J = A - 2 W diag(x),   H = Q + diag(3 q4 o x^2) + 2 diag(W' lambda).
+ * Per iteration the library forms the primal condensed KKT matrix
+ * (Section 3, eq. kkt_primal)
+ *     K = H + diag(Sigma_x + delta_p) + J' diag(Sigma_s) J,
+ *     Sigma_s = lambda / (s + delta_d lambda),
+ * factors P'KP = LL' with no pivoting (Section 2: SPD systems need none; the
+ * ordering P is computed once on the host), and runs the triangular solves.
+ *
+ * Conventions
+ *  - CSR arrays are 0-based, column indices sorted and unique per row;
+ *    row pointers are int64, column indices int32.  Q is given by its lower
+ *    triangle (diagonal included).
+ *  - Host pointers (h_) are read during the call only; the caller keeps
+ *    ownership.  Device pointers (d_) are HIP device addresses on the device
+ *    current at create time.
+ *  - Device memory is never allocated by the library: every handle works
+ *    inside one caller-owned workspace (ipm_set_workspace) that must outlive
+ *    the handle.  Work runs on the caller's stream (ipm_set_stream, default 0).
+ *  - Every call returns an int status (PDIPM_* below); no exception crosses
+ *    the ABI.  ipm_last_error() gives the message of the last failure.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PDIPM_H
+#define PDIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PDIPM_OK 0                /* optimal / success */
+#define PDIPM_MAX_ITER 1          /* iteration limit, best iterate returned */
+#define PDIPM_TIME_LIMIT 2        /* wall-time limit, best iterate returned */
+#define PDIPM_STALLED 3           /* line search failed, best iterate returned */
+#define PDIPM_ERR_INVALID_ARG -1  /* bad input; message in ipm_last_error */
+#define PDIPM_ERR_OUT_OF_MEMORY -2 /* workspace missing or too small */
+#define PDIPM_ERR_NOT_PD -3       /* non-positive pivot (info->first_bad_col) */
+#define PDIPM_ERR_NUMERICAL -4    /* NaN/Inf, or regularisation above 1e40 */
+#define PDIPM_ERR_DEVICE -5       /* HIP runtime error; text in ipm_last_error */
+#define PDIPM_ERR_NOT_ANALYZED -6 /* kkt_analyze / workspace not done yet */
+
+#define PDIPM_FP64 0              /* factor and solve in FP64 */
+#define PDIPM_FP32 1              /* FP32 factor + FP64 iterative refinement */
+
+#define PDIPM_HOST 0
+#define PDIPM_DEVICE 1
+
+typedef struct pdipm_csr {
+  int64_t nrows, ncols;
+  const int64_t* rowptr; /* [nrows+1]; NULL = empty matrix */
+  const int32_t* colind; /* [nnz] */
+  const double* val;     /* [nnz] */
+} pdipm_csr;
+
+typedef struct ipm_problem_desc {
+  int64_t n, m;
+  const double* c;  /* [n], required */
+  const double* b;  /* [m], required when m > 0 */
+  pdipm_csr A;      /* m x n, may be empty */
+  pdipm_csr W;      /* m x n, entries >= 0 (keeps g concave), may be empty */
+  pdipm_csr Q;      /* n x n lower triangle, may be empty */
+  const double* q4; /* [n] or NULL */
+  const double* xl; /* [n] or NULL (= -inf); -INFINITY allowed */
+  const double* xu; /* [n] or NULL (= +inf); +INFINITY allowed */
+} ipm_problem_desc;
+
+typedef struct ipm_options {
+  double tol;            /* P, D, C tolerance, default 1e-6 */
+  int32_t max_iter;      /* default 500 */
+  double max_wall_time;  /* seconds, default 900 */
+  double delta_p;        /* primal regularisation, default 1e-8 */
+  double delta_d;        /* dual regularisation, default 1e-8 */
+  int32_t precision;     /* PDIPM_FP64 or PDIPM_FP32 (workspace sized for it) */
+  int32_t ir_max;        /* refinement steps per solve, default 10 */
+  double ir_tol;         /* relative residual target of refinement, 1e-12 */
+  int32_t nd_leaf;       /* minimum-degree leaf size of the ordering, 64 */
+  int32_t amalg_menu;    /* supernode amalgamation rule 0, 1, 2 (-1 = none) */
+  int32_t print_level;   /* 0 silent, 1 per-iteration line on stderr */
+  int32_t fp64_fallback; /* FP32 form: reserve FP64 space for refactoring */
+} ipm_options;
+
+typedef struct kkt_symbolic_stats {
+  int64_t n;             /* order of K */
+  int64_t nnz_K;         /* entries of the lower triangle of K */
+  int64_t nnz_L;         /* entries of L (structural, diagonal included) */
+  int64_t nnz_L_stored;  /* entries of the supernodal panels (relaxed) */
+  int64_t n_super;       /* supernodes */
+  int64_t max_front;     /* largest front order */
+  int64_t n_levels;      /* levels of the supernodal elimination tree */
+  int64_t n_triples;     /* J'SJ products summed by the assembly */
+  double flops;          /* sum_j (c_j^2 - 1), the factorisation's work */
+  double update_bytes;   /* bytes of front update matrices (per precision) */
+} kkt_symbolic_stats;
+
+typedef struct kkt_factor_info {
+  int32_t status;
+  int64_t first_bad_col; /* permuted column of the first bad pivot, or -1 */
+  double ms;             /* device time of the factorisation */
+  double flops;
+} kkt_factor_info;
+
+typedef struct kkt_solve_info {
+  int32_t ir_steps;      /* refinement corrections applied */
+  double residual;       /* ||rhs - K x||_inf / ||rhs||_inf after the solve */
+  int32_t fallback;      /* 0 none, 1 FP64 refactor */
+  double ms;
+} kkt_solve_info;
+
+typedef struct ipm_start {
+  const double* x;       /* [n] predicted primal point */
+  const double* lam;     /* [m] predicted multipliers */
+  int32_t memspace;      /* PDIPM_HOST or PDIPM_DEVICE */
+} ipm_start;
+
+typedef struct ipm_result {
+  int32_t status;
+  int32_t iterations;
+  double f, P, D, C, mu;
+  double ms_total, ms_eval, ms_assemble, ms_factor, ms_solve;
+  int32_t ir_steps;       /* refinement corrections over the solve */
+  int32_t fp64_refactors; /* FP32 form: refactorisations in FP64 */
+  int32_t inertia_corrections;
+  double max_ir_residual; /* worst relative KKT residual after refinement */
+} ipm_result;
+
+typedef struct ipm_handle ipm_handle;
+
+void ipm_default_options(ipm_options* opts);
+const char* ipm_status_string(int status);
+const char* ipm_last_error(const ipm_handle* h); /* NULL h: last create error */
+
+/* Create a solver for problem (1) from host CSR data (all arrays copied).
+ * Builds the J and H patterns and the K pattern and runs the symbolic
+ * analysis (Section 2: ordering once on the CPU).  Options NULL = defaults. */
+int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle** out);
+
+/* Standalone KKT handle for an explicit SPD matrix given by the lower CSR
+ * pattern of K (n x n); values come later through kkt_set_values. */
+int kkt_create_csr(int64_t n, const int64_t* h_rowptr, const int32_t* h_colind,
+                   const ipm_options* opts, ipm_handle** out);
+
+/* Symbolic statistics (host only; the analysis itself runs at create). */
+int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* out);
+
+/* Export the symbolic analysis (host arrays sized from kkt_analyze):
+ * perm[n] (perm[k] = original index at position k), etree[n] (permuted,
+ * -1 root), colcount[n], sn_start[n_super+1], sn_rowptr[n_super+1],
+ * sn_rows[sn_rowptr[n_super]] (permuted rows, own columns first). */
+int kkt_get_symbolic(ipm_handle* h, int32_t* perm, int32_t* etree, int64_t* colcount,
+                     int32_t* sn_start, int64_t* sn_rowptr, int32_t* sn_rows);
+
+/* Lower CSR pattern of K in the original numbering (host arrays
+ * rowptr[n+1], colind[nnz_K]); kkt_get_values uses this order. */
+int kkt_get_pattern(ipm_handle* h, int64_t* rowptr, int32_t* colind);
+
+/* Device workspace: query its size, hand it over (caller-owned, 256-byte
+ * aligned, outlives the handle), select the stream (a hipStream_t). */
+int ipm_workspace_query(ipm_handle* h, size_t* bytes);
+int ipm_set_workspace(ipm_handle* h, void* d_ws, size_t bytes);
+int ipm_set_stream(ipm_handle* h, void* stream);
+
+/* Standalone: K values on the device in the order of kkt_create_csr's
+ * pattern (lower triangle, FP64). */
+int kkt_set_values(ipm_handle* h, const double* d_kval);
+
+/* Assemble K for the point (x, lambda) with the given Sigma_s [m] and
+ * Sigma_x [n] (device vectors): evaluates J and H on their patterns and sums
+ * H + diag(Sigma_x + delta_p) + J' diag(Sigma_s) J into the supernodal
+ * panels in the given precision. */
+int kkt_assemble(ipm_handle* h, const double* d_x, const double* d_lam,
+                 const double* d_sig_s, const double* d_sig_x, int precision);
+
+/* Read back the assembled (not yet factored) K in kkt_get_pattern order. */
+int kkt_get_values(ipm_handle* h, double* h_kval);
+
+/* Numeric factorisation of the current K values (P'KP = LL', no pivoting).
+ * Returns PDIPM_ERR_NOT_PD with info->first_bad_col on a pivot <= 0. */
+int kkt_factor(ipm_handle* h, int precision, kkt_factor_info* info);
+
+/* Export the factor: supernode by supernode, each panel column-major
+ * (rows = its sn_rows, columns = its columns), as FP64 on the host;
+ * total length nnz_L_stored. */
+int kkt_get_factor(ipm_handle* h, double* h_lval);
+
+/* Solve K x = rhs with the current factor (device FP64 vectors, original
+ * numbering).  With an FP32 factor, FP64 iterative refinement against the
+ * assembled (or set) K runs up to ir_max steps. */
+int kkt_solve(ipm_handle* h, const double* d_rhs, double* d_x, kkt_solve_info* info);
+
+/* Evaluate the model at (x, lambda) on the device: f (host scalar),
+ * grad f [n], g [m], J values in J's CSR order, H values in H's lower CSR
+ * order (Section 4: derivative kernels on fixed patterns).  NULL outputs are
+ * skipped. */
+int ipm_evaluate(ipm_handle* h, const double* d_x, const double* d_lam, double* h_f,
+                 double* d_grad, double* d_g, double* d_jval, double* d_hval);
+
+/* Patterns used by ipm_evaluate: J = union of A and W (m x n), H = lower of
+ * Q plus the diagonal (n x n).  Sizes through ipm_pattern_sizes. */
+int ipm_pattern_sizes(ipm_handle* h, int64_t* nnz_j, int64_t* nnz_h);
+int ipm_get_patterns(ipm_handle* h, int64_t* j_rowptr, int32_t* j_colind,
+                     int64_t* h_rowptr, int32_t* h_colind);
+
+/* Run the interior-point method to tolerance.  start NULL = cold start
+ * (x from the bounds, s = max(g, 1), lambda = 1, z = 1); a start is pushed
+ * into the interior first. */
+int ipm_solve(ipm_handle* h, const ipm_start* start, ipm_result* res);
+
+/* Copy the final iterate to caller buffers (memspace PDIPM_HOST/DEVICE);
+ * NULL pointers are skipped. */
+int ipm_get_solution(ipm_handle* h, double* x, double* s, double* lam, double* zl, double* zu,
+                     int memspace);
+
+void ipm_destroy(ipm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDIPM_H */

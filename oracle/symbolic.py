@@ -20,6 +20,9 @@ ORD  Graph G = structure of K without its diagonal.
          BFS levels L_0..L_h from r; if h < 2 the natural (sorted) order;
          else separator level l in [1, h-1] minimising
          |L_l| / min(|L_<l|, |L_>l|), then |2l - h|, then l;
+         if the largest connected component left after removing L_l keeps
+         more than 7/8 of C the separator is rejected and C is ordered
+         naturally (such graphs fill in densely under any order);
          result order(L_<l) ++ order(L_>l) ++ sorted(L_l).
      The ND order is then composed with a postorder of the elimination tree
      (children in increasing index, roots in increasing index).
@@ -41,7 +44,7 @@ from collections import deque
 import numpy as np
 import scipy.sparse as sp
 
-AMALGAMATION_MENU = [(64, 8, 1, 10), (128, 16, 1, 20), (32, 4, 1, 5)]
+AMALGAMATION_MENU = [(1 << 30, 8, 1, 10), (128, 16, 1, 20), (64, 8, 1, 10)]
 ND_LEAF = 64
 
 
@@ -198,6 +201,14 @@ def nested_dissection(adj, n, leaf=ND_LEAF):
             l = _choose_separator(levels)
             lower = [v for L in levels[:l] for v in L]
             upper = [v for L in levels[l + 1:] for v in L]
+            for v in levels[l]:
+                inset[v] = False
+            biggest = max(len(c) for c in _components(adj, lower + upper, inset))
+            for v in levels[l]:
+                inset[v] = True
+            if 8 * biggest > 7 * len(comp):
+                tasks.append(("emit", sorted(comp)))
+                continue
             tasks.append(("order", sorted(lower)))
             tasks.append(("order", sorted(upper)))
             tasks.append(("emit", sorted(levels[l])))

@@ -1,0 +1,890 @@
+// C ABI of the interior-point hot path: handles, workspace, factorisation,
+// triangular solves with FP64 refinement, and the predictor-corrector loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+#include "pdipm.h"
+
+using namespace pdipm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Region {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+template <typename T>
+size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
+
+}  // namespace
+
+struct ipm_handle {
+  int device = 0;
+  hipStream_t stream = 0;
+  ipm_options opt{};
+  bool standalone = false;
+  HostProblem hp;
+  Graph graph;
+  Symbolic sym;
+  KMap km;
+  Plan plan64, plan32;
+  bool need64 = true, need32 = false;
+  // standalone: symmetric map of K's lower pattern
+  std::vector<int64_t> ksp, kss;
+  std::vector<int32_t> ksc;
+  std::string err;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  bool ws_ready = false;
+  struct Off {
+    size_t c, b, q4, xl, xu, jp, jc, ja, jw, jtp, jtr, jte, hp, hc, hq, hdiag, hsp, hsc, hss;
+    size_t kmrow, kmc, kmh, kmtp, kmtk, kmta, kmtb, kmpos, ksp, ksc, kss, kval;
+    size_t sfirst, sw, sh, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
+    size_t gemm64, potrf64, gemm32, potrf32, ext, small;
+    size_t panel, ubuf, inv, bad, partials, xperm, uvec;
+    size_t vec[48];
+  } o{};
+  DevProblem dp{};
+  DevPlan dpl64{}, dpl32{};
+  DevKMap dk{};
+  void* panel = nullptr;
+  void* ubuf = nullptr;
+  void* inv = nullptr;
+  int* bad = nullptr;
+  double* partials = nullptr;
+  double* xperm = nullptr;
+  double* uvec = nullptr;
+  double* kval = nullptr;
+  IpmVecs v{}, tv{};
+  double *dxa, *dsa, *dla, *dzla, *dzua, *dx, *ds, *dl, *dzl, *dzu, *ts, *tl, *tu, *rhs, *ir_r, *ir_c,
+      *ir_kx, *xhat, *lamhat;
+  // factor state
+  int assembled_prec = -1, factor_prec = -1;
+  bool values_set = false, factored = false;
+  double cur_delta_p = 0;  // delta_p used by the last assembly
+  // result
+  bool solved = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+int fail(ipm_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((h), PDIPM_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void finish_analysis(ipm_handle* h) {
+  build_plan(h->sym, 8, &h->plan64);
+  build_plan(h->sym, 4, &h->plan32);
+  map_k_to_panels(h->sym, h->plan64, &h->km);
+  if (h->standalone) {
+    // symmetric pattern of the stored lower K for products K v
+    const int64_t n = h->km.n;
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t e = 0; e < (int64_t)h->km.kc.size(); ++e) {
+      int32_t i = h->km.krow[e], j = h->km.kc[e];
+      cnt[i + 1]++;
+      if (i != j) cnt[j + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    h->ksp = cnt;
+    h->ksc.resize(cnt[n]);
+    h->kss.resize(cnt[n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t e = 0; e < (int64_t)h->km.kc.size(); ++e) {
+      int32_t i = h->km.krow[e], j = h->km.kc[e];
+      int64_t q = fill[i]++;
+      h->ksc[q] = j; h->kss[q] = e;
+      if (i != j) { q = fill[j]++; h->ksc[q] = i; h->kss[q] = e; }
+    }
+  }
+}
+
+void layout(ipm_handle* h) {
+  Region r;
+  auto& o = h->o;
+  const HostProblem& p = h->hp;
+  const int64_t n = h->sym.n, m = h->standalone ? 0 : p.m;
+  if (!h->standalone) {
+    o.c = r.take(bytes_of(p.c)); o.b = r.take(bytes_of(p.b)); o.q4 = r.take(bytes_of(p.q4));
+    o.xl = r.take(bytes_of(p.xl)); o.xu = r.take(bytes_of(p.xu));
+    o.jp = r.take(bytes_of(p.jp)); o.jc = r.take(bytes_of(p.jc)); o.ja = r.take(bytes_of(p.ja));
+    o.jw = r.take(bytes_of(p.jw)); o.jtp = r.take(bytes_of(p.jtp)); o.jtr = r.take(bytes_of(p.jtr));
+    o.jte = r.take(bytes_of(p.jte)); o.hp = r.take(bytes_of(p.hp)); o.hc = r.take(bytes_of(p.hc));
+    o.hq = r.take(bytes_of(p.hq)); o.hdiag = r.take(bytes_of(p.hdiag)); o.hsp = r.take(bytes_of(p.hsp));
+    o.hsc = r.take(bytes_of(p.hsc)); o.hss = r.take(bytes_of(p.hss));
+    o.kmh = r.take(bytes_of(h->km.kh)); o.kmtp = r.take(bytes_of(h->km.tp));
+    o.kmtk = r.take(bytes_of(h->km.tk)); o.kmta = r.take(bytes_of(h->km.ta)); o.kmtb = r.take(bytes_of(h->km.tb));
+  } else {
+    o.ksp = r.take(bytes_of(h->ksp)); o.ksc = r.take(bytes_of(h->ksc)); o.kss = r.take(bytes_of(h->kss));
+  }
+  o.kmrow = r.take(bytes_of(h->km.krow)); o.kmc = r.take(bytes_of(h->km.kc)); o.kmpos = r.take(bytes_of(h->km.pos));
+  o.kval = r.take(h->km.kc.size() * 8);
+  const Plan& P = h->plan64;
+  o.sfirst = r.take(bytes_of(P.sfirst)); o.sw = r.take(bytes_of(P.sw)); o.sh = r.take(bytes_of(P.sh));
+  o.cptr = r.take(bytes_of(P.child_ptr)); o.child = r.take(bytes_of(P.child)); o.rel = r.take(bytes_of(P.rel));
+  o.lsn = r.take(bytes_of(P.level_sn)); o.snrows = r.take(bytes_of(h->sym.sn_rows));
+  o.perm = r.take(bytes_of(h->sym.perm)); o.spanel = r.take(bytes_of(P.spanel)); o.su = r.take(bytes_of(P.su));
+  o.srow = r.take(bytes_of(P.srow)); o.suv = r.take(bytes_of(P.suv));
+  o.ext = r.take(bytes_of(P.ext)); o.small = r.take(bytes_of(P.small));
+  if (h->need64) { o.gemm64 = r.take(bytes_of(h->plan64.gemm)); o.potrf64 = r.take(bytes_of(h->plan64.potrf)); }
+  if (h->need32) { o.gemm32 = r.take(bytes_of(h->plan32.gemm)); o.potrf32 = r.take(bytes_of(h->plan32.potrf)); }
+  const size_t es = h->need64 ? 8 : 4;
+  o.panel = r.take((size_t)P.panel_elems * es);
+  o.ubuf = r.take((size_t)std::max<int64_t>(1, P.u_elems) * es);
+  size_t inv64 = h->need64 ? (size_t)h->plan64.inv_elems * 8 : 0;
+  size_t inv32 = h->need32 ? (size_t)h->plan32.inv_elems * 4 : 0;
+  o.inv = r.take(std::max(inv64, inv32));
+  o.bad = r.take(64);
+  o.partials = r.take((8 * RED_BLOCKS + 16) * sizeof(double));
+  o.xperm = r.take(n * 8);
+  o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
+  // vectors: 0..47 (n or m sized)
+  const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
+  const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
+  const int64_t sizes[48] = {
+      nv, mv, mv, nv, nv,          // 0 x, 1 s, 2 lam, 3 zl, 4 zu
+      nv, nv, mv, jn, hn,          // 5 gf, 6 qx, 7 g, 8 jv, 9 hv
+      nv, mv, mv, nv,              // 10 rd, 11 rp, 12 sig_s, 13 sig_x
+      nv, mv, nv, mv,              // 14 tmp_n, 15 tmp_m, 16 tmp_n2, 17 tmp_m2
+      nv, mv, mv, nv, nv,          // 18..22 trial x, s, lam, zl, zu
+      nv, nv, mv, jn, nv, mv,      // 23 gf, 24 qx, 25 g, 26 jv, 27 rd, 28 rp
+      nv, mv, mv, nv, nv,          // 29..33 affine dx, ds, dlam, dzl, dzu
+      nv, mv, mv, nv, nv,          // 34..38 dx, ds, dlam, dzl, dzu
+      mv, nv, nv, nv,              // 39 ts, 40 tl, 41 tu, 42 rhs
+      nv, nv, nv, nv, mv};         // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
+  for (int i = 0; i < 48; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+  h->ws_need = r.off;
+}
+
+template <typename T>
+T* at(ipm_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
+
+int upload(ipm_handle* h, size_t off, const void* src, size_t bytes) {
+  if (bytes == 0) return PDIPM_OK;
+  HIPCHK(h, hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, h->stream));
+  return PDIPM_OK;
+}
+
+#define UP(off, vec) do { int rc_ = upload(h, h->o.off, vec.data(), bytes_of(vec)); if (rc_) return rc_; } while (0)
+
+int bind_workspace(ipm_handle* h) {
+  auto& o = h->o;
+  const HostProblem& p = h->hp;
+  if (!h->standalone) {
+    UP(c, p.c); UP(b, p.b); UP(q4, p.q4); UP(xl, p.xl); UP(xu, p.xu); UP(jp, p.jp); UP(jc, p.jc);
+    UP(ja, p.ja); UP(jw, p.jw); UP(jtp, p.jtp); UP(jtr, p.jtr); UP(jte, p.jte); UP(hp, p.hp); UP(hc, p.hc);
+    UP(hq, p.hq); UP(hdiag, p.hdiag); UP(hsp, p.hsp); UP(hsc, p.hsc); UP(hss, p.hss);
+    UP(kmh, h->km.kh); UP(kmtp, h->km.tp); UP(kmtk, h->km.tk); UP(kmta, h->km.ta); UP(kmtb, h->km.tb);
+  } else {
+    UP(ksp, h->ksp); UP(ksc, h->ksc); UP(kss, h->kss);
+  }
+  UP(kmrow, h->km.krow); UP(kmc, h->km.kc); UP(kmpos, h->km.pos);
+  const Plan& P = h->plan64;
+  UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(cptr, P.child_ptr); UP(child, P.child);
+  UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
+  UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv); UP(ext, P.ext); UP(small, P.small);
+  if (h->need64) { UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); }
+  if (h->need32) { UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  // device views
+  DevProblem& d = h->dp;
+  d.n = p.n; d.m = p.m; d.nnz_j = (int64_t)p.jc.size(); d.nnz_h = (int64_t)p.hc.size();
+  if (!h->standalone) {
+    d.c = at<double>(h, o.c); d.b = at<double>(h, o.b); d.q4 = p.q4.empty() ? nullptr : at<double>(h, o.q4);
+    d.xl = at<double>(h, o.xl); d.xu = at<double>(h, o.xu);
+    d.jp = at<int64_t>(h, o.jp); d.jc = at<int32_t>(h, o.jc); d.ja = at<double>(h, o.ja); d.jw = at<double>(h, o.jw);
+    d.jtp = at<int64_t>(h, o.jtp); d.jtr = at<int32_t>(h, o.jtr); d.jte = at<int32_t>(h, o.jte);
+    d.hp = at<int64_t>(h, o.hp); d.hc = at<int32_t>(h, o.hc); d.hq = at<double>(h, o.hq);
+    d.hdiag = at<int64_t>(h, o.hdiag); d.hsp = at<int64_t>(h, o.hsp); d.hsc = at<int32_t>(h, o.hsc);
+    d.hss = at<int32_t>(h, o.hss);
+  }
+  DevKMap& k = h->dk;
+  k.nk = (int64_t)h->km.kc.size();
+  k.krow = at<int32_t>(h, o.kmrow); k.kc = at<int32_t>(h, o.kmc); k.pos = at<int64_t>(h, o.kmpos);
+  if (!h->standalone) {
+    k.kh = at<int32_t>(h, o.kmh); k.tp = at<int64_t>(h, o.kmtp); k.tk = at<int32_t>(h, o.kmtk);
+    k.ta = at<int32_t>(h, o.kmta); k.tb = at<int32_t>(h, o.kmtb);
+  }
+  for (int prec = 0; prec < 2; ++prec) {
+    DevPlan& q = prec == 0 ? h->dpl64 : h->dpl32;
+    const Plan& PP = prec == 0 ? h->plan64 : h->plan32;
+    q.ns = PP.ns; q.n = PP.n; q.nb = PP.nb; q.small_h = PP.small_h;
+    q.sfirst = at<int32_t>(h, o.sfirst); q.sw = at<int32_t>(h, o.sw); q.sh = at<int32_t>(h, o.sh);
+    q.child_ptr = at<int32_t>(h, o.cptr); q.child = at<int32_t>(h, o.child); q.rel = at<int32_t>(h, o.rel);
+    q.level_sn = at<int32_t>(h, o.lsn); q.sn_rows = at<int32_t>(h, o.snrows); q.perm = at<int32_t>(h, o.perm);
+    q.spanel = at<int64_t>(h, o.spanel); q.su = at<int64_t>(h, o.su); q.srow = at<int64_t>(h, o.srow);
+    q.suv = at<int64_t>(h, o.suv); q.ext = at<ExtAddDesc>(h, o.ext); q.small = at<int32_t>(h, o.small);
+    q.gemm = at<GemmDesc>(h, prec == 0 ? o.gemm64 : o.gemm32);
+    q.potrf = at<PotrfDesc>(h, prec == 0 ? o.potrf64 : o.potrf32);
+  }
+  h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;
+  h->bad = at<int>(h, o.bad); h->partials = at<double>(h, o.partials);
+  h->xperm = at<double>(h, o.xperm); h->uvec = at<double>(h, o.uvec); h->kval = at<double>(h, o.kval);
+  double* V[48];
+  for (int i = 0; i < 48; ++i) V[i] = at<double>(h, o.vec[i]);
+  IpmVecs& v = h->v;
+  v.x = V[0]; v.s = V[1]; v.lam = V[2]; v.zl = V[3]; v.zu = V[4]; v.gf = V[5]; v.qx = V[6]; v.g = V[7];
+  v.jv = V[8]; v.hv = V[9]; v.rd = V[10]; v.rp = V[11]; v.sig_s = V[12]; v.sig_x = V[13];
+  v.tmp_n = V[14]; v.tmp_m = V[15]; v.tmp_n2 = V[16]; v.tmp_m2 = V[17];
+  IpmVecs& t = h->tv;
+  t = v;
+  t.x = V[18]; t.s = V[19]; t.lam = V[20]; t.zl = V[21]; t.zu = V[22]; t.gf = V[23]; t.qx = V[24]; t.g = V[25];
+  t.jv = V[26]; t.rd = V[27]; t.rp = V[28];
+  h->dxa = V[29]; h->dsa = V[30]; h->dla = V[31]; h->dzla = V[32]; h->dzua = V[33];
+  h->dx = V[34]; h->ds = V[35]; h->dl = V[36]; h->dzl = V[37]; h->dzu = V[38];
+  h->ts = V[39]; h->tl = V[40]; h->tu = V[41]; h->rhs = V[42];
+  h->ir_r = V[43]; h->ir_c = V[44]; h->ir_kx = V[45]; h->xhat = V[46]; h->lamhat = V[47];
+  h->ws_ready = true;
+  h->assembled_prec = h->factor_prec = -1;
+  h->factored = h->values_set = false;
+  return PDIPM_OK;
+}
+
+int read_back(ipm_handle* h, const double* dev, double* host, int count) {
+  HIPCHK(h, hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+double* red_out(ipm_handle* h) { return h->partials + 8 * RED_BLOCKS; }
+
+// ------------------------------------------------------------- factor
+int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
+  const Plan& P = prec == PDIPM_FP64 ? h->plan64 : h->plan32;
+  const DevPlan& D = prec == PDIPM_FP64 ? h->dpl64 : h->dpl32;
+  const size_t es = prec == PDIPM_FP64 ? 8 : 4;
+  int big = INT_MAX;
+  HIPCHK(h, hipMemcpyAsync(h->bad, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  launch_fill_bytes0(h->ubuf, (int64_t)std::max<int64_t>(1, P.u_elems) * es, h->stream);
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  for (const Op& op : P.ops) {
+    if (prec == PDIPM_FP64)
+      launch_factor_op<double>(op, D, (double*)h->panel, (double*)h->ubuf, (double*)h->inv, h->bad, h->stream);
+    else
+      launch_factor_op<float>(op, D, (float*)h->panel, (float*)h->ubuf, (float*)h->inv, h->bad, h->stream);
+  }
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  HIPCHK(h, hipGetLastError());
+  int badcol = INT_MAX;
+  HIPCHK(h, hipMemcpyAsync(&badcol, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  h->factor_prec = prec;
+  h->factored = badcol == INT_MAX;
+  if (info) {
+    info->status = h->factored ? PDIPM_OK : PDIPM_ERR_NOT_PD;
+    info->first_bad_col = h->factored ? -1 : badcol;
+    info->ms = ms;
+    info->flops = h->sym.flops;
+  }
+  return h->factored ? PDIPM_OK : fail(h, PDIPM_ERR_NOT_PD, "non-positive pivot at permuted column " + std::to_string(badcol));
+}
+
+void trisolve(ipm_handle* h, const double* rhs, double* out) {
+  const int prec = h->factor_prec;
+  const Plan& P = prec == PDIPM_FP64 ? h->plan64 : h->plan32;
+  const DevPlan& D = prec == PDIPM_FP64 ? h->dpl64 : h->dpl32;
+  launch_permute_in(D, rhs, h->xperm, h->stream);
+  for (int l = 0; l < P.nlevels; ++l) {
+    if (prec == PDIPM_FP64)
+      launch_fwd_level<double>(D, P.level_ptr[l], P.level_ptr[l + 1], (const double*)h->panel, h->xperm, h->uvec, h->stream);
+    else
+      launch_fwd_level<float>(D, P.level_ptr[l], P.level_ptr[l + 1], (const float*)h->panel, h->xperm, h->uvec, h->stream);
+  }
+  for (int l = P.nlevels - 1; l >= 0; --l) {
+    if (prec == PDIPM_FP64)
+      launch_bwd_level<double>(D, P.level_ptr[l], P.level_ptr[l + 1], (const double*)h->panel, h->xperm, h->stream);
+    else
+      launch_bwd_level<float>(D, P.level_ptr[l], P.level_ptr[l + 1], (const float*)h->panel, h->xperm, h->stream);
+  }
+  launch_permute_out(D, h->xperm, out, h->stream);
+}
+
+void kmul(ipm_handle* h, const double* x, double* out) {
+  if (h->standalone)
+    launch_k_mul_stored(h->sym.n, nullptr, nullptr, at<int64_t>(h, h->o.ksp), at<int32_t>(h, h->o.ksc),
+                        at<int64_t>(h, h->o.kss), h->kval, x, out, h->stream);
+  else
+    launch_k_mul_free(h->dp, h->v.jv, h->v.hv, h->v.sig_s, h->v.sig_x, h->cur_delta_p, x, out, h->v.tmp_m2,
+                      h->v.tmp_n2, h->stream);
+}
+
+// Solve with the current factor; FP64 refinement when the factor is FP32.
+int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info* info) {
+  const int64_t n = h->sym.n;
+  trisolve(h, rhs, out);
+  int steps = 0;
+  double rel = 0;
+  const bool refine = h->factor_prec == PDIPM_FP32;
+  if (refine || info) {
+    double prev = INFINITY;
+    for (int it = 0;; ++it) {
+      kmul(h, out, h->ir_kx);
+      launch_residual_norms(n, rhs, h->ir_kx, h->ir_r, h->partials, h->stream);
+      double nr[2];
+      int rc = read_back(h, red_out(h), nr, 2);
+      if (rc) return rc;
+      rel = nr[1] > 0 ? nr[0] / nr[1] : nr[0];
+      if (!refine || rel <= h->opt.ir_tol || it >= h->opt.ir_max || !(rel < 0.5 * prev)) break;
+      prev = rel;
+      trisolve(h, h->ir_r, h->ir_c);
+      launch_add(n, out, h->ir_c, h->stream);
+      ++steps;
+    }
+  }
+  if (info) { info->ir_steps = steps; info->residual = rel; info->fallback = 0; }
+  if (!std::isfinite(rel)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
+  return PDIPM_OK;
+}
+
+template <typename T>
+void assemble_into(ipm_handle* h, double delta_p) {
+  const size_t es = sizeof(T);
+  launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
+  launch_assemble<T>(h->dk, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, (T*)h->panel, h->kval, h->stream);
+}
+
+int assemble(ipm_handle* h, int prec, double delta_p) {
+  if (prec == PDIPM_FP64 && !h->need64) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace has no FP64 factor space");
+  if (prec == PDIPM_FP32 && !h->need32) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace has no FP32 plan");
+  if (prec == PDIPM_FP64) assemble_into<double>(h, delta_p);
+  else assemble_into<float>(h, delta_p);
+  h->cur_delta_p = delta_p;
+  h->assembled_prec = prec;
+  h->factored = false;
+  return PDIPM_OK;
+}
+
+int check_ready(ipm_handle* h) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (!h->ws_ready) return fail(h, PDIPM_ERR_NOT_ANALYZED, "workspace not set");
+  return PDIPM_OK;
+}
+
+// ------------------------------------------------------------ IPM loop
+struct Scalars { double maxrp, maxg, maxrd, maxgf, comp, f, nonfinite; };
+
+int evaluate_point(ipm_handle* h, IpmVecs& v, bool hess) {
+  const DevProblem& P = h->dp;
+  if (h->hp.kind == KIND_NLP) launch_jac_eval(P, v.x, v.jv, h->stream);
+  launch_constraints(P, v.x, v.g, h->stream);
+  launch_gradient(P, v.x, v.qx, v.gf, h->stream);
+  if (hess && h->hp.kind == KIND_NLP) launch_hess_eval(P, v.x, v.lam, v.hv, h->stream);
+  launch_residuals(P, v, h->stream);
+  return PDIPM_OK;
+}
+
+int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
+  using clk = std::chrono::steady_clock;
+  const auto t_start = clk::now();
+  const DevProblem& P = h->dp;
+  IpmVecs& v = h->v;
+  const int64_t n = P.n, m = P.m;
+  const int kind = h->hp.kind;
+  int64_t nbnd = 0;
+  for (int64_t i = 0; i < n; ++i) nbnd += std::isfinite(h->hp.xl[i]) + std::isfinite(h->hp.xu[i]);
+  const double nc = (double)(m + nbnd);
+  const ipm_options& O = h->opt;
+  const int prec = O.precision;
+  ipm_result R{};
+  auto ms_since = [&](clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); };
+  // constant derivatives for LP/QP
+  if (kind != KIND_NLP) {
+    launch_copy(P.nnz_j, v.jv, P.ja, h->stream);
+    launch_copy(P.nnz_h, v.hv, P.hq, h->stream);
+    launch_copy(P.nnz_j, h->tv.jv, P.ja, h->stream);
+  }
+  if (st) {
+    const hipMemcpyKind kd = st->memspace == PDIPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(h, hipMemcpyAsync(h->xhat, st->x, n * 8, kd, h->stream));
+    if (m) HIPCHK(h, hipMemcpyAsync(h->lamhat, st->lam, m * 8, kd, h->stream));
+    launch_push_start(P, v, h->xhat, h->lamhat, 0, h->stream);
+    launch_sum_sl(P, v, h->partials, h->stream);
+    double sl;
+    int rc = read_back(h, red_out(h), &sl, 1);
+    if (rc) return rc;
+    launch_push_duals(P, v, std::max(1e-4, sl / std::max<int64_t>(1, m)), h->stream);
+  } else {
+    launch_init_point(P, v, h->stream);
+  }
+  double delta_w_last = 0.0;
+  int status = PDIPM_MAX_ITER;
+  int it = 0;
+  double Pm = 0, Dm = 0, Cm = 0, mu = 0, f = 0;
+  while (true) {
+    auto te = clk::now();
+    evaluate_point(h, v, true);
+    launch_stats_iter(P, v, h->partials, h->stream);
+    double s7[7];
+    int rc = read_back(h, red_out(h), s7, 7);
+    if (rc) return rc;
+    R.ms_eval += ms_since(te);
+    Scalars S{s7[0], s7[1], s7[2], s7[3], s7[4], s7[5], s7[6]};
+    f = S.f;
+    Pm = S.maxrp / (1.0 + S.maxg);
+    Dm = S.maxrd / (1.0 + S.maxgf);
+    Cm = S.comp / (1.0 + std::fabs(f));
+    mu = nc > 0 ? S.comp / nc : 0.0;
+    if (O.print_level > 0)
+      fprintf(stderr, "it %3d f %+.10e P %.2e D %.2e C %.2e mu %.2e\n", it, f, Pm, Dm, Cm, mu);
+    if (S.nonfinite > 0 || !std::isfinite(f)) { status = PDIPM_ERR_NUMERICAL; break; }
+    if (Pm <= O.tol && Dm <= O.tol && Cm <= O.tol) { status = PDIPM_OK; break; }
+    if (it >= O.max_iter) { status = PDIPM_MAX_ITER; break; }
+    if (ms_since(t_start) > O.max_wall_time * 1e3) { status = PDIPM_TIME_LIMIT; break; }
+    launch_sigmas(P, v, O.delta_d, h->stream);
+    // assemble + factor, with inertia correction on a non-positive pivot
+    int fprec = prec;
+    double delta_w = 0.0;
+    auto ta = clk::now();
+    rc = assemble(h, fprec, O.delta_p);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    R.ms_assemble += ms_since(ta);
+    kkt_factor_info fi{};
+    rc = factor_now(h, fprec, &fi);
+    R.ms_factor += fi.ms;
+    if (rc == PDIPM_ERR_NOT_PD) {
+      delta_w = delta_w_last == 0.0 ? 1e-4 : std::max(1e-20, delta_w_last / 3.0);
+      const bool first = delta_w_last == 0.0;
+      while (true) {
+        rc = assemble(h, fprec, O.delta_p + delta_w);
+        if (rc) return rc;
+        rc = factor_now(h, fprec, &fi);
+        R.ms_factor += fi.ms;
+        if (rc == PDIPM_OK) { delta_w_last = delta_w; break; }
+        if (rc != PDIPM_ERR_NOT_PD) return rc;
+        delta_w *= first ? 100.0 : 8.0;
+        if (delta_w > 1e40) { status = PDIPM_ERR_NUMERICAL; break; }
+      }
+      if (status == PDIPM_ERR_NUMERICAL) break;
+      R.inertia_corrections++;
+    } else if (rc) {
+      return rc;
+    }
+    auto ts0 = clk::now();
+    kkt_solve_info si{};
+    auto direction = [&](const double* tsv, const double* tlv, const double* tuv, double* dx, double* ds,
+                         double* dl, double* dzl, double* dzu) -> int {
+      launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
+      int r2 = solve_refined(h, h->rhs, dx, &si);
+      if (r2) return r2;
+      R.ir_steps += si.ir_steps;
+      R.max_ir_residual = std::max(R.max_ir_residual, si.residual);
+      launch_recover(P, v, dx, tsv, tlv, tuv, O.delta_d, ds, dl, dzl, dzu, h->stream);
+      return PDIPM_OK;
+    };
+    rc = direction(nullptr, nullptr, nullptr, h->dxa, h->dsa, h->dla, h->dzla, h->dzua);
+    if (rc) return rc;
+    launch_step_limits(P, v, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, h->partials, h->stream);
+    double lim[2];
+    if ((rc = read_back(h, red_out(h), lim, 2))) return rc;
+    double apa = std::min(1.0, lim[0]), ada = std::min(1.0, lim[1]);
+    if (kind != KIND_LP) apa = ada = std::min(apa, ada);
+    launch_mu_aff(P, v, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, apa, ada, h->partials, h->stream);
+    double maff;
+    if ((rc = read_back(h, red_out(h), &maff, 1))) return rc;
+    maff /= nc;
+    const double sigma = mu > 0 ? std::min(1.0, std::pow(maff / mu, 3.0)) : 0.0;
+    const double smu = sigma * mu;
+    launch_targets(P, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, smu, h->ts, h->tl, h->tu, h->stream);
+    rc = direction(h->ts, h->tl, h->tu, h->dx, h->ds, h->dl, h->dzl, h->dzu);
+    if (rc) return rc;
+    launch_step_limits(P, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->partials, h->stream);
+    if ((rc = read_back(h, red_out(h), lim, 2))) return rc;
+    R.ms_solve += ms_since(ts0);
+    const double tau = std::max(0.99, 1.0 - mu);
+    double ap = std::min(1.0, tau * lim[0]), ad = std::min(1.0, tau * lim[1]);
+    if (kind != KIND_LP) ap = ad = std::min(ap, ad);
+    if (kind == KIND_NLP) {
+      launch_phi(P, v, smu, h->partials, h->stream);
+      double phi0;
+      if ((rc = read_back(h, red_out(h), &phi0, 1))) return rc;
+      phi0 = std::sqrt(phi0);
+      double a = ap;
+      bool ok = false;
+      for (int k = 0; k < 31; ++k) {
+        launch_axpy_point(P, h->tv, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, a, a, h->stream);
+        evaluate_point(h, h->tv, false);
+        launch_phi(P, h->tv, smu, h->partials, h->stream);
+        double phi1;
+        if ((rc = read_back(h, red_out(h), &phi1, 1))) return rc;
+        if (std::sqrt(phi1) <= (1.0 - 1e-4 * a) * phi0) { ok = true; break; }
+        a *= 0.5;
+      }
+      if (!ok) { status = PDIPM_STALLED; break; }
+      ap = ad = a;
+    }
+    launch_axpy_point(P, v, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, ap, ad, h->stream);
+    ++it;
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  R.status = status;
+  R.iterations = it;
+  R.f = f; R.P = Pm; R.D = Dm; R.C = Cm; R.mu = mu;
+  R.ms_total = ms_since(t_start);
+  h->solved = true;
+  if (res) *res = R;
+  return status;
+}
+
+}  // namespace
+
+// ================================================================= ABI
+extern "C" {
+
+void ipm_default_options(ipm_options* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->max_iter = 500;
+  o->max_wall_time = 900.0;
+  o->delta_p = 1e-8;
+  o->delta_d = 1e-8;
+  o->precision = PDIPM_FP64;
+  o->ir_max = 10;
+  o->ir_tol = 1e-12;
+  o->nd_leaf = 64;
+  o->amalg_menu = 0;
+  o->print_level = 0;
+  o->fp64_fallback = 0;
+}
+
+const char* ipm_status_string(int s) {
+  switch (s) {
+    case PDIPM_OK: return "optimal";
+    case PDIPM_MAX_ITER: return "iteration limit";
+    case PDIPM_TIME_LIMIT: return "time limit";
+    case PDIPM_STALLED: return "stalled";
+    case PDIPM_ERR_INVALID_ARG: return "invalid argument";
+    case PDIPM_ERR_OUT_OF_MEMORY: return "workspace too small";
+    case PDIPM_ERR_NOT_PD: return "not positive definite";
+    case PDIPM_ERR_NUMERICAL: return "numerical failure";
+    case PDIPM_ERR_DEVICE: return "device error";
+    case PDIPM_ERR_NOT_ANALYZED: return "not analyzed";
+    default: return "unknown";
+  }
+}
+
+const char* ipm_last_error(const ipm_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** out) {
+  try {
+    h->need64 = h->opt.precision == PDIPM_FP64 || h->opt.fp64_fallback;
+    h->need32 = h->opt.precision == PDIPM_FP32;
+    analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym);
+    finish_analysis(h);
+    layout(h);
+    hipGetDevice(&h->device);
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    delete h;
+    return PDIPM_ERR_INVALID_ARG;
+  }
+  (void)opts;
+  *out = h;
+  return PDIPM_OK;
+}
+
+int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle** out) {
+  if (!out) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ipm_handle* h = new (std::nothrow) ipm_handle();
+  if (!h) return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (opts) h->opt = *opts; else ipm_default_options(&h->opt);
+  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+  }
+  std::string e = build_problem(prob, &h->hp);
+  if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
+  try {
+    build_graph_from_problem(h->hp, &h->graph);
+    build_kmap_problem(h->hp, &h->km);
+  } catch (const std::exception& ex) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());
+  }
+  return finish_create(h, opts, out);
+}
+
+int kkt_create_csr(int64_t n, const int64_t* rp, const int32_t* ci, const ipm_options* opts, ipm_handle** out) {
+  if (!out) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || n >= (1ll << 31) || !rp || !ci) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "bad K pattern");
+  if (rp[0] != 0) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "rowptr[0] != 0");
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "rowptr not monotone");
+    bool diag = false;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] > i) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "entry outside the lower triangle");
+      if (e > rp[i] && ci[e - 1] >= ci[e]) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "columns not sorted");
+      diag |= ci[e] == i;
+    }
+    if (!diag) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "every row needs its diagonal entry");
+  }
+  ipm_handle* h = new (std::nothrow) ipm_handle();
+  if (!h) return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (opts) h->opt = *opts; else ipm_default_options(&h->opt);
+  h->standalone = true;
+  h->hp.n = n;
+  h->hp.m = 0;
+  build_graph_from_lower(n, rp, ci, &h->graph);
+  build_kmap_lower(n, rp, ci, &h->km);
+  return finish_create(h, opts, out);
+}
+
+int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* s) {
+  if (!h || !s) return PDIPM_ERR_INVALID_ARG;
+  s->n = h->sym.n;
+  s->nnz_K = (int64_t)h->km.kc.size();
+  s->nnz_L = h->sym.nnz_L;
+  s->nnz_L_stored = h->plan64.panel_elems;
+  s->n_super = h->sym.nsuper();
+  s->max_front = h->plan64.max_front;
+  s->n_levels = h->plan64.nlevels;
+  s->n_triples = (int64_t)h->km.tk.size();
+  s->flops = h->sym.flops;
+  s->update_bytes = (double)h->plan64.u_elems * (h->need64 ? 8 : 4);
+  return PDIPM_OK;
+}
+
+int kkt_get_symbolic(ipm_handle* h, int32_t* perm, int32_t* etree, int64_t* cc, int32_t* sn_start,
+                     int64_t* sn_rowptr, int32_t* sn_rows) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  const Symbolic& s = h->sym;
+  if (perm) memcpy(perm, s.perm.data(), bytes_of(s.perm));
+  if (etree) memcpy(etree, s.etree.data(), bytes_of(s.etree));
+  if (cc) memcpy(cc, s.colcount.data(), bytes_of(s.colcount));
+  if (sn_start) memcpy(sn_start, s.sn_start.data(), bytes_of(s.sn_start));
+  if (sn_rowptr) memcpy(sn_rowptr, s.sn_rowptr.data(), bytes_of(s.sn_rowptr));
+  if (sn_rows) memcpy(sn_rows, s.sn_rows.data(), bytes_of(s.sn_rows));
+  return PDIPM_OK;
+}
+
+int kkt_get_pattern(ipm_handle* h, int64_t* rp, int32_t* ci) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (rp) memcpy(rp, h->km.kp.data(), bytes_of(h->km.kp));
+  if (ci) memcpy(ci, h->km.kc.data(), bytes_of(h->km.kc));
+  return PDIPM_OK;
+}
+
+int ipm_workspace_query(ipm_handle* h, size_t* bytes) {
+  if (!h || !bytes) return PDIPM_ERR_INVALID_ARG;
+  *bytes = h->ws_need;
+  return PDIPM_OK;
+}
+
+int ipm_set_stream(ipm_handle* h, void* stream) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  h->stream = (hipStream_t)stream;
+  return PDIPM_OK;
+}
+
+int ipm_set_workspace(ipm_handle* h, void* ws, size_t bytes) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (!ws || bytes < h->ws_need)
+    return fail(h, PDIPM_ERR_OUT_OF_MEMORY, "workspace needs " + std::to_string(h->ws_need) + " bytes");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  h->ws = (char*)ws;
+  h->ws_bytes = bytes;
+  if (!h->ev0) {
+    HIPCHK(h, hipEventCreate(&h->ev0));
+    HIPCHK(h, hipEventCreate(&h->ev1));
+  }
+  return bind_workspace(h);
+}
+
+int kkt_set_values(ipm_handle* h, const double* d_kval) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->standalone) return fail(h, PDIPM_ERR_INVALID_ARG, "kkt_set_values needs a kkt_create_csr handle");
+  HIPCHK(h, hipMemcpyAsync(h->kval, d_kval, h->km.kc.size() * 8, hipMemcpyDeviceToDevice, h->stream));
+  h->values_set = true;
+  h->factored = false;
+  return PDIPM_OK;
+}
+
+int kkt_assemble(ipm_handle* h, const double* x, const double* lam, const double* sig_s, const double* sig_x,
+                 int prec) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (h->standalone) return fail(h, PDIPM_ERR_INVALID_ARG, "kkt_assemble needs an ipm_create handle");
+  const DevProblem& P = h->dp;
+  IpmVecs& v = h->v;
+  launch_copy(P.n, v.x, x, h->stream);
+  launch_copy(P.m, v.lam, lam, h->stream);
+  launch_copy(P.m, v.sig_s, sig_s, h->stream);
+  launch_copy(P.n, v.sig_x, sig_x, h->stream);
+  launch_jac_eval(P, v.x, v.jv, h->stream);
+  launch_hess_eval(P, v.x, v.lam, v.hv, h->stream);
+  rc = assemble(h, prec, h->opt.delta_p);
+  if (rc) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+int kkt_get_values(ipm_handle* h, double* out) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  HIPCHK(h, hipMemcpyAsync(out, h->kval, h->km.kc.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+int kkt_factor(ipm_handle* h, int prec, kkt_factor_info* info) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (prec != PDIPM_FP64 && prec != PDIPM_FP32) return fail(h, PDIPM_ERR_INVALID_ARG, "bad precision");
+  if ((prec == PDIPM_FP64 && !h->need64) || (prec == PDIPM_FP32 && !h->need32))
+    return fail(h, PDIPM_ERR_INVALID_ARG, "the workspace was not sized for this precision");
+  if (h->standalone) {
+    if (!h->values_set) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no K values set");
+    const size_t es = prec == PDIPM_FP64 ? 8 : 4;
+    launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
+    if (prec == PDIPM_FP64) launch_set_values<double>(h->dk, h->kval, (double*)h->panel, h->stream);
+    else launch_set_values<float>(h->dk, h->kval, (float*)h->panel, h->stream);
+  } else if (h->assembled_prec != prec) {
+    return fail(h, PDIPM_ERR_INVALID_ARG, "assemble K in this precision first (kkt_assemble)");
+  }
+  return factor_now(h, prec, info);
+}
+
+int kkt_get_factor(ipm_handle* h, double* out) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (h->factor_prec < 0) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no factor");
+  const int64_t ne = h->plan64.panel_elems;
+  if (h->factor_prec == PDIPM_FP64) {
+    HIPCHK(h, hipMemcpyAsync(out, h->panel, ne * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tmp(ne);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->panel, ne * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < ne; ++i) out[i] = tmp[i];
+  }
+  return PDIPM_OK;
+}
+
+int kkt_solve(ipm_handle* h, const double* rhs, double* x, kkt_solve_info* info) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->factored) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no valid factor");
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  kkt_solve_info si{};
+  rc = solve_refined(h, rhs, x, &si);
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  float ms = 0;
+  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  si.ms = ms;
+  if (info) *info = si;
+  return rc;
+}
+
+int ipm_evaluate(ipm_handle* h, const double* x, const double* lam, double* f, double* grad, double* g,
+                 double* jval, double* hval) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (h->standalone) return fail(h, PDIPM_ERR_INVALID_ARG, "needs an ipm_create handle");
+  const DevProblem& P = h->dp;
+  IpmVecs& v = h->v;
+  launch_copy(P.n, v.x, x, h->stream);
+  launch_copy(P.m, v.lam, lam, h->stream);
+  launch_jac_eval(P, v.x, v.jv, h->stream);
+  launch_constraints(P, v.x, v.g, h->stream);
+  launch_gradient(P, v.x, v.qx, v.gf, h->stream);
+  launch_hess_eval(P, v.x, v.lam, v.hv, h->stream);
+  if (f) {
+    // objective through the iteration statistics (rd/rp contents are irrelevant here)
+    launch_fill_f64(v.zl, P.n, 0.0, h->stream);
+    launch_fill_f64(v.zu, P.n, 0.0, h->stream);
+    launch_residuals(P, v, h->stream);
+    launch_stats_iter(P, v, h->partials, h->stream);
+    double s7[7];
+    if ((rc = read_back(h, red_out(h), s7, 7))) return rc;
+    *f = s7[5];
+  }
+  if (grad) HIPCHK(h, hipMemcpyAsync(grad, v.gf, P.n * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (g && P.m) HIPCHK(h, hipMemcpyAsync(g, v.g, P.m * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (jval && P.nnz_j) HIPCHK(h, hipMemcpyAsync(jval, v.jv, P.nnz_j * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (hval) HIPCHK(h, hipMemcpyAsync(hval, v.hv, P.nnz_h * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+int ipm_pattern_sizes(ipm_handle* h, int64_t* nj, int64_t* nh) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (nj) *nj = (int64_t)h->hp.jc.size();
+  if (nh) *nh = (int64_t)h->hp.hc.size();
+  return PDIPM_OK;
+}
+
+int ipm_get_patterns(ipm_handle* h, int64_t* jrp, int32_t* jci, int64_t* hrp, int32_t* hci) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (jrp) memcpy(jrp, h->hp.jp.data(), bytes_of(h->hp.jp));
+  if (jci) memcpy(jci, h->hp.jc.data(), bytes_of(h->hp.jc));
+  if (hrp) memcpy(hrp, h->hp.hp.data(), bytes_of(h->hp.hp));
+  if (hci) memcpy(hci, h->hp.hc.data(), bytes_of(h->hp.hc));
+  return PDIPM_OK;
+}
+
+int ipm_solve(ipm_handle* h, const ipm_start* st, ipm_result* res) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (h->standalone) return fail(h, PDIPM_ERR_INVALID_ARG, "needs an ipm_create handle");
+  return run_ipm(h, st, res);
+}
+
+int ipm_get_solution(ipm_handle* h, double* x, double* s, double* lam, double* zl, double* zu, int memspace) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  const hipMemcpyKind k = memspace == PDIPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const IpmVecs& v = h->v;
+  const int64_t n = h->dp.n, m = h->dp.m;
+  if (x) HIPCHK(h, hipMemcpyAsync(x, v.x, n * 8, k, h->stream));
+  if (s && m) HIPCHK(h, hipMemcpyAsync(s, v.s, m * 8, k, h->stream));
+  if (lam && m) HIPCHK(h, hipMemcpyAsync(lam, v.lam, m * 8, k, h->stream));
+  if (zl) HIPCHK(h, hipMemcpyAsync(zl, v.zl, n * 8, k, h->stream));
+  if (zu) HIPCHK(h, hipMemcpyAsync(zu, v.zu, n * 8, k, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+void ipm_destroy(ipm_handle* h) {
+  if (!h) return;
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,474 @@
+// Problem ingestion, K pattern and assembly map, supernodal plan (host).
+#include "host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <sstream>
+#include <stdexcept>
+#include <tuple>
+
+#include "pdipm.h"
+
+namespace pdipm {
+
+namespace {
+
+std::string check_csr(const pdipm_csr& a, int64_t nr, int64_t nc, const char* name, bool lower) {
+  if (!a.rowptr) return "";
+  std::ostringstream os;
+  if (a.nrows != nr || a.ncols != nc) {
+    os << name << ": shape " << a.nrows << "x" << a.ncols << " expected " << nr << "x" << nc;
+    return os.str();
+  }
+  if (a.rowptr[0] != 0) return std::string(name) + ": rowptr[0] != 0";
+  for (int64_t i = 0; i < nr; ++i) {
+    if (a.rowptr[i + 1] < a.rowptr[i]) return std::string(name) + ": rowptr not monotone";
+    for (int64_t e = a.rowptr[i]; e < a.rowptr[i + 1]; ++e) {
+      int32_t j = a.colind[e];
+      if (j < 0 || j >= nc) return std::string(name) + ": column index out of range";
+      if (e > a.rowptr[i] && a.colind[e - 1] >= j)
+        return std::string(name) + ": columns not sorted or duplicated";
+      if (lower && j > i) return std::string(name) + ": entry above the diagonal";
+      if (!std::isfinite(a.val[e])) return std::string(name) + ": non-finite value";
+    }
+  }
+  return "";
+}
+
+}  // namespace
+
+std::string build_problem(const ipm_problem_desc* d, HostProblem* p) {
+  if (!d) return "problem is NULL";
+  if (d->n <= 0 || d->m < 0) return "n must be positive and m non-negative";
+  if (d->n >= (1ll << 31) || d->m >= (1ll << 31)) return "n and m must fit int32";
+  if (!d->c) return "c is required";
+  if (d->m > 0 && !d->b) return "b is required when m > 0";
+  const int64_t n = d->n, m = d->m;
+  std::string e;
+  if (!(e = check_csr(d->A, m, n, "A", false)).empty()) return e;
+  if (!(e = check_csr(d->W, m, n, "W", false)).empty()) return e;
+  if (!(e = check_csr(d->Q, n, n, "Q", true)).empty()) return e;
+  p->n = n;
+  p->m = m;
+  p->c.assign(d->c, d->c + n);
+  p->b.assign(d->b ? d->b : d->c, d->b ? d->b + m : d->c);
+  if (!d->b) p->b.clear();
+  for (double v : p->c)
+    if (!std::isfinite(v)) return "non-finite c";
+  for (double v : p->b)
+    if (!std::isfinite(v)) return "non-finite b";
+  p->xl.assign(n, -INFINITY);
+  p->xu.assign(n, INFINITY);
+  if (d->xl) p->xl.assign(d->xl, d->xl + n);
+  if (d->xu) p->xu.assign(d->xu, d->xu + n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (std::isnan(p->xl[i]) || std::isnan(p->xu[i]) || p->xl[i] == INFINITY || p->xu[i] == -INFINITY)
+      return "invalid bound";
+    if (!(p->xl[i] < p->xu[i])) return "lower bound must be below upper bound";
+  }
+  p->has_q4 = false;
+  if (d->q4) {
+    p->q4.assign(d->q4, d->q4 + n);
+    for (double v : p->q4) {
+      if (!std::isfinite(v) || v < 0) return "q4 must be finite and non-negative";
+      if (v != 0) p->has_q4 = true;
+    }
+  }
+  if (!p->has_q4) p->q4.clear();
+  p->has_w = d->W.rowptr && d->W.rowptr[m] > 0;
+  if (p->has_w)
+    for (int64_t e2 = 0; e2 < d->W.rowptr[m]; ++e2)
+      if (d->W.val[e2] < 0) return "W must be non-negative";
+  bool has_q = d->Q.rowptr && d->Q.rowptr[n] > 0;
+  p->kind = (p->has_w || p->has_q4) ? KIND_NLP : (has_q ? KIND_QP : KIND_LP);
+  // J union pattern
+  p->jp.assign(m + 1, 0);
+  p->jc.clear(); p->ja.clear(); p->jw.clear();
+  for (int64_t k = 0; k < m; ++k) {
+    int64_t ea = d->A.rowptr ? d->A.rowptr[k] : 0, eA = d->A.rowptr ? d->A.rowptr[k + 1] : 0;
+    int64_t ew = d->W.rowptr ? d->W.rowptr[k] : 0, eW = d->W.rowptr ? d->W.rowptr[k + 1] : 0;
+    while (ea < eA || ew < eW) {
+      int32_t ca = ea < eA ? d->A.colind[ea] : INT32_MAX;
+      int32_t cw = ew < eW ? d->W.colind[ew] : INT32_MAX;
+      int32_t cmin = std::min(ca, cw);
+      p->jc.push_back(cmin);
+      p->ja.push_back(ca == cmin ? d->A.val[ea++] : 0.0);
+      p->jw.push_back(cw == cmin ? d->W.val[ew++] : 0.0);
+    }
+    p->jp[k + 1] = (int64_t)p->jc.size();
+  }
+  if ((int64_t)p->jc.size() >= (1ll << 31)) return "J has too many entries";
+  // transpose of J
+  p->jtp.assign(n + 1, 0);
+  for (int32_t j : p->jc) p->jtp[j + 1]++;
+  for (int64_t j = 0; j < n; ++j) p->jtp[j + 1] += p->jtp[j];
+  p->jtr.resize(p->jc.size());
+  p->jte.resize(p->jc.size());
+  {
+    std::vector<int64_t> fill(p->jtp.begin(), p->jtp.end() - 1);
+    for (int64_t k = 0; k < m; ++k)
+      for (int64_t e2 = p->jp[k]; e2 < p->jp[k + 1]; ++e2) {
+        int64_t q = fill[p->jc[e2]]++;
+        p->jtr[q] = (int32_t)k;
+        p->jte[q] = (int32_t)e2;
+      }
+  }
+  // H lower pattern = lower(Q) plus the diagonal
+  p->hp.assign(n + 1, 0);
+  p->hc.clear(); p->hq.clear();
+  p->hdiag.assign(n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    bool diag_done = false;
+    if (d->Q.rowptr) {
+      for (int64_t e2 = d->Q.rowptr[i]; e2 < d->Q.rowptr[i + 1]; ++e2) {
+        int32_t j = d->Q.colind[e2];
+        if (j == i) { p->hdiag[i] = (int64_t)p->hc.size(); diag_done = true; }
+        p->hc.push_back(j);
+        p->hq.push_back(d->Q.val[e2]);
+      }
+    }
+    if (!diag_done) {
+      p->hdiag[i] = (int64_t)p->hc.size();
+      p->hc.push_back((int32_t)i);
+      p->hq.push_back(0.0);
+    }
+    p->hp[i + 1] = (int64_t)p->hc.size();
+  }
+  // symmetric pattern of H with sources
+  {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e2 = p->hp[i]; e2 < p->hp[i + 1]; ++e2) {
+        cnt[i + 1]++;
+        if (p->hc[e2] != i) cnt[p->hc[e2] + 1]++;
+      }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    p->hsp = cnt;
+    p->hsc.resize(cnt[n]);
+    p->hss.resize(cnt[n]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    // entries (i, j<=i) go to row i; (j, i) for j<i go to row j.  Rows come
+    // out sorted because row i first receives the transposed entries from
+    // rows < i... collect then sort per row.
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e2 = p->hp[i]; e2 < p->hp[i + 1]; ++e2) {
+        int32_t j = p->hc[e2];
+        int64_t q = fill[i]++;
+        p->hsc[q] = j; p->hss[q] = (int32_t)e2;
+        if (j != i) { q = fill[j]++; p->hsc[q] = (int32_t)i; p->hss[q] = (int32_t)e2; }
+      }
+    for (int64_t i = 0; i < n; ++i) {
+      std::vector<std::pair<int32_t, int32_t>> row;
+      for (int64_t q = p->hsp[i]; q < p->hsp[i + 1]; ++q) row.push_back({p->hsc[q], p->hss[q]});
+      std::sort(row.begin(), row.end());
+      for (size_t t = 0; t < row.size(); ++t) {
+        p->hsc[p->hsp[i] + t] = row[t].first;
+        p->hss[p->hsp[i] + t] = row[t].second;
+      }
+    }
+  }
+  return "";
+}
+
+void build_graph_from_problem(const HostProblem& p, Graph* g) {
+  const int64_t n = p.n;
+  g->n = n;
+  g->ptr.assign(n + 1, 0);
+  g->adj.clear();
+  std::vector<int32_t> mark(n, -1), row;
+  for (int64_t j = 0; j < n; ++j) {
+    row.clear();
+    mark[j] = (int32_t)j;
+    for (int64_t q = p.jtp[j]; q < p.jtp[j + 1]; ++q) {
+      int32_t k = p.jtr[q];
+      for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
+        int32_t i = p.jc[e];
+        if (mark[i] != j) { mark[i] = (int32_t)j; row.push_back(i); }
+      }
+    }
+    for (int64_t q = p.hsp[j]; q < p.hsp[j + 1]; ++q) {
+      int32_t i = p.hsc[q];
+      if (mark[i] != j) { mark[i] = (int32_t)j; row.push_back(i); }
+    }
+    std::sort(row.begin(), row.end());
+    g->adj.insert(g->adj.end(), row.begin(), row.end());
+    g->ptr[j + 1] = (int64_t)g->adj.size();
+  }
+}
+
+void build_graph_from_lower(int64_t n, const int64_t* rp, const int32_t* ci, Graph* g) {
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+      if (ci[e] != i) { cnt[i + 1]++; cnt[ci[e] + 1]++; }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  g->n = n;
+  g->ptr = cnt;
+  g->adj.resize(cnt[n]);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+      if (ci[e] != i) { g->adj[fill[i]++] = ci[e]; g->adj[fill[ci[e]]++] = (int32_t)i; }
+  for (int64_t i = 0; i < n; ++i) std::sort(g->adj.begin() + g->ptr[i], g->adj.begin() + g->ptr[i + 1]);
+}
+
+void build_kmap_problem(const HostProblem& p, KMap* km) {
+  const int64_t n = p.n;
+  km->n = n;
+  km->kp.assign(n + 1, 0);
+  km->kc.clear(); km->krow.clear(); km->kh.clear(); km->tk.clear(); km->ta.clear(); km->tb.clear();
+  km->tp.assign(1, 0);
+  struct Item { int32_t j, k, a, b; };
+  std::vector<Item> items;
+  std::vector<std::pair<int32_t, int32_t>> hrow;
+  for (int64_t i = 0; i < n; ++i) {
+    items.clear();
+    for (int64_t q = p.jtp[i]; q < p.jtp[i + 1]; ++q) {
+      int32_t k = p.jtr[q], a = p.jte[q];
+      for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
+        int32_t j = p.jc[e];
+        if (j > i) break;
+        items.push_back({j, k, a, (int32_t)e});
+      }
+    }
+    std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+      return x.j != y.j ? x.j < y.j : x.k < y.k;
+    });
+    // merge with the H row (lower, sorted; includes the diagonal)
+    size_t t = 0;
+    int64_t eh = p.hp[i];
+    while (t < items.size() || eh < p.hp[i + 1]) {
+      int32_t jt = t < items.size() ? items[t].j : INT32_MAX;
+      int32_t jh = eh < p.hp[i + 1] ? p.hc[eh] : INT32_MAX;
+      int32_t j = std::min(jt, jh);
+      km->kc.push_back(j);
+      km->krow.push_back((int32_t)i);
+      km->kh.push_back(jh == j ? (int32_t)eh++ : -1);
+      while (t < items.size() && items[t].j == j) {
+        km->tk.push_back(items[t].k);
+        km->ta.push_back(items[t].a);
+        km->tb.push_back(items[t].b);
+        ++t;
+      }
+      km->tp.push_back((int64_t)km->tk.size());
+    }
+    km->kp[i + 1] = (int64_t)km->kc.size();
+  }
+}
+
+void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km) {
+  km->n = n;
+  km->kp.assign(rp, rp + n + 1);
+  km->kc.assign(ci, ci + rp[n]);
+  km->krow.resize(rp[n]);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) km->krow[e] = (int32_t)i;
+  km->kh.clear(); km->tk.clear(); km->ta.clear(); km->tb.clear();
+  km->tp.clear();
+}
+
+void build_plan(const Symbolic& s, int esize, Plan* pl) {
+  Plan& P = *pl;
+  P = Plan();
+  P.esize = esize;
+  P.nb = esize == 8 ? 64 : 128;
+  P.small_h = 64;
+  const int64_t ns = s.nsuper();
+  P.ns = ns;
+  P.n = s.n;
+  P.sfirst.resize(ns); P.sw.resize(ns); P.sh.resize(ns); P.sparent.assign(ns, -1);
+  P.slevel.assign(ns, 0); P.spanel.resize(ns); P.su.resize(ns); P.srow.resize(ns + 1); P.suv.resize(ns);
+  std::vector<int32_t> col2sn(s.n);
+  for (int64_t k = 0; k < ns; ++k) {
+    P.sfirst[k] = s.sn_start[k];
+    P.sw[k] = s.sn_start[k + 1] - s.sn_start[k];
+    P.sh[k] = (int32_t)(s.sn_rowptr[k + 1] - s.sn_rowptr[k]);
+    P.srow[k] = s.sn_rowptr[k];
+    for (int32_t j = s.sn_start[k]; j < s.sn_start[k + 1]; ++j) col2sn[j] = (int32_t)k;
+  }
+  P.srow[ns] = s.sn_rowptr[ns];
+  int64_t off = 0, uoff = 0, uvoff = 0;
+  for (int64_t k = 0; k < ns; ++k) {
+    P.spanel[k] = off;
+    off += (int64_t)P.sh[k] * P.sw[k];
+    int64_t hu = P.sh[k] - P.sw[k];
+    P.su[k] = uoff;
+    uoff += hu * hu;
+    P.suv[k] = uvoff;
+    uvoff += hu;
+    P.max_front = std::max<int64_t>(P.max_front, P.sh[k]);
+    int32_t last = s.sn_start[k + 1] - 1;
+    if (s.etree[last] >= 0) P.sparent[k] = col2sn[s.etree[last]];
+  }
+  P.panel_elems = off;
+  P.u_elems = uoff;
+  P.uv_elems = uvoff;
+  P.update_bytes = (double)uoff * esize;
+  // children (increasing) and levels
+  P.child_ptr.assign(ns + 1, 0);
+  for (int64_t k = 0; k < ns; ++k)
+    if (P.sparent[k] >= 0) P.child_ptr[P.sparent[k] + 1]++;
+  for (int64_t k = 0; k < ns; ++k) P.child_ptr[k + 1] += P.child_ptr[k];
+  P.child.resize(P.child_ptr[ns]);
+  {
+    std::vector<int32_t> fill(P.child_ptr.begin(), P.child_ptr.end() - 1);
+    for (int64_t k = 0; k < ns; ++k)
+      if (P.sparent[k] >= 0) P.child[fill[P.sparent[k]]++] = (int32_t)k;
+  }
+  for (int64_t k = 0; k < ns; ++k)
+    if (P.sparent[k] >= 0) P.slevel[P.sparent[k]] = std::max(P.slevel[P.sparent[k]], P.slevel[k] + 1);
+  P.nlevels = 0;
+  for (int64_t k = 0; k < ns; ++k) P.nlevels = std::max(P.nlevels, P.slevel[k] + 1);
+  P.level_ptr.assign(P.nlevels + 1, 0);
+  for (int64_t k = 0; k < ns; ++k) P.level_ptr[P.slevel[k] + 1]++;
+  for (int l = 0; l < P.nlevels; ++l) P.level_ptr[l + 1] += P.level_ptr[l];
+  P.level_sn.resize(ns);
+  {
+    std::vector<int32_t> fill(P.level_ptr.begin(), P.level_ptr.end() - 1);
+    for (int64_t k = 0; k < ns; ++k) P.level_sn[fill[P.slevel[k]]++] = (int32_t)k;
+  }
+  // relative row positions in the parent front
+  P.rel.assign(s.sn_rows.size(), -1);
+  for (int64_t k = 0; k < ns; ++k) {
+    int32_t par = P.sparent[k];
+    if (par < 0) continue;
+    const int32_t* pr = s.sn_rows.data() + s.sn_rowptr[par];
+    int64_t ph = s.sn_rowptr[par + 1] - s.sn_rowptr[par];
+    int64_t q = 0;
+    for (int64_t e = s.sn_rowptr[k] + P.sw[k]; e < s.sn_rowptr[k + 1]; ++e) {
+      int32_t r = s.sn_rows[e];
+      while (q < ph && pr[q] < r) ++q;
+      if (q >= ph || pr[q] != r) throw std::runtime_error("child row missing from parent front");
+      P.rel[e] = (int32_t)q;
+    }
+  }
+  // launch schedule, level by level
+  const int nb = P.nb;
+  int64_t max_inv_fronts = 0;
+  for (int l = 0; l < P.nlevels; ++l) {
+    std::vector<int32_t> large;
+    int64_t small_begin = (int64_t)P.small.size();
+    for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+      int32_t k = P.level_sn[q];
+      if (P.sh[k] <= P.small_h) P.small.push_back(k);
+      else large.push_back(k);
+    }
+    if (!large.empty()) {
+      int64_t zb = (int64_t)P.ext.size();
+      for (int32_t k : large) {
+        if (P.child_ptr[k + 1] == P.child_ptr[k]) continue;
+        for (int32_t t0 = 0; t0 < P.sh[k]; t0 += 16)
+          P.ext.push_back({k, t0, std::min<int32_t>(t0 + 16, P.sh[k]), 0});
+      }
+      if ((int64_t)P.ext.size() > zb)
+        P.ops.push_back({OP_EXTEND_ADD, zb, (int64_t)P.ext.size(), (int64_t)P.ext.size() - zb});
+    }
+    if ((int64_t)P.small.size() > small_begin)
+      P.ops.push_back({OP_SMALL, small_begin, (int64_t)P.small.size(), (int64_t)P.small.size() - small_begin});
+    if (large.empty()) continue;
+    int32_t maxw = 0;
+    for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
+    const int tm = esize == 8 ? 64 : 128;  // gemm tile
+    for (int32_t c0 = 0; c0 < maxw; c0 += nb) {
+      int64_t pb = (int64_t)P.potrf.size();
+      int64_t slot = 0;
+      std::vector<int64_t> slot_of(large.size(), -1);
+      for (size_t q = 0; q < large.size(); ++q) {
+        int32_t k = large[q];
+        if (P.sw[k] <= c0) continue;
+        int32_t bw = std::min(nb, P.sw[k] - c0);
+        PotrfDesc d;
+        d.d_off = P.spanel[k] + (int64_t)c0 * P.sh[k] + c0;
+        d.inv_off = slot * (int64_t)nb * nb;
+        d.ld = P.sh[k];
+        d.bw = bw;
+        d.col0 = P.sfirst[k] + c0;
+        d.pad = 0;
+        slot_of[q] = slot++;
+        P.potrf.push_back(d);
+      }
+      max_inv_fronts = std::max(max_inv_fronts, slot);
+      P.ops.push_back({OP_POTRF, pb, (int64_t)P.potrf.size(), (int64_t)P.potrf.size() - pb});
+      // TRSM: rows below the diagonal block, in place, C = A * Dinv^T
+      int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
+      for (size_t q = 0; q < large.size(); ++q) {
+        int32_t k = large[q];
+        if (slot_of[q] < 0) continue;
+        int32_t bw = std::min(nb, P.sw[k] - c0);
+        int32_t M = P.sh[k] - c0 - bw;
+        if (M <= 0) continue;
+        GemmDesc g{};
+        g.c_off = P.spanel[k] + (int64_t)c0 * P.sh[k] + c0 + bw;
+        g.a_off = g.c_off;
+        g.b_off = slot_of[q] * (int64_t)nb * nb;
+        g.ldc = P.sh[k]; g.lda = P.sh[k]; g.ldb = nb;
+        g.M = M; g.N = bw; g.K = bw;
+        g.c_buf = 0; g.b_buf = 1; g.mode = 1; g.lower = 0;
+        g.tiles_m = (M + tm - 1) / tm; g.tiles_n = 1;
+        g.tile_begin = tiles;
+        tiles += (int64_t)g.tiles_m * g.tiles_n;
+        P.gemm.push_back(g);
+      }
+      if (tiles) P.ops.push_back({OP_TRSM, gb, (int64_t)P.gemm.size(), tiles});
+      // update: trailing panel columns and the update matrix
+      gb = (int64_t)P.gemm.size();
+      tiles = 0;
+      for (size_t q = 0; q < large.size(); ++q) {
+        int32_t k = large[q];
+        if (slot_of[q] < 0) continue;
+        int32_t h = P.sh[k], w = P.sw[k];
+        int32_t bw = std::min(nb, w - c0);
+        int32_t r0 = c0 + bw;
+        if (w - r0 > 0) {
+          GemmDesc g{};
+          g.c_off = P.spanel[k] + (int64_t)r0 * h + r0;
+          g.a_off = P.spanel[k] + (int64_t)c0 * h + r0;
+          g.b_off = g.a_off;
+          g.ldc = h; g.lda = h; g.ldb = h;
+          g.M = h - r0; g.N = w - r0; g.K = bw;
+          g.c_buf = 0; g.b_buf = 0; g.mode = 0; g.lower = 1;
+          g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
+          g.tile_begin = tiles;
+          tiles += (int64_t)g.tiles_m * g.tiles_n;
+          P.gemm.push_back(g);
+        }
+        if (h - w > 0) {
+          GemmDesc g{};
+          g.c_off = P.su[k];
+          g.a_off = P.spanel[k] + (int64_t)c0 * h + w;
+          g.b_off = g.a_off;
+          g.ldc = h - w; g.lda = h; g.ldb = h;
+          g.M = h - w; g.N = h - w; g.K = bw;
+          g.c_buf = 1; g.b_buf = 0; g.mode = 0; g.lower = 1;
+          g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
+          g.tile_begin = tiles;
+          tiles += (int64_t)g.tiles_m * g.tiles_n;
+          P.gemm.push_back(g);
+        }
+      }
+      if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
+    }
+  }
+  P.inv_elems = std::max<int64_t>(1, max_inv_fronts) * nb * nb;
+}
+
+void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {
+  const int64_t nk = (int64_t)km->kc.size();
+  km->pos.resize(nk);
+  std::vector<int32_t> col2sn(s.n);
+  for (int64_t k = 0; k < P.ns; ++k)
+    for (int32_t j = s.sn_start[k]; j < s.sn_start[k + 1]; ++j) col2sn[j] = (int32_t)k;
+  for (int64_t e = 0; e < nk; ++e) {
+    int32_t a = s.pinv[km->krow[e]], b = s.pinv[km->kc[e]];
+    int32_t r = std::max(a, b), c = std::min(a, b);
+    int32_t k = col2sn[c];
+    const int32_t* rows = s.sn_rows.data() + s.sn_rowptr[k];
+    int64_t h = s.sn_rowptr[k + 1] - s.sn_rowptr[k];
+    const int32_t* it = std::lower_bound(rows, rows + h, r);
+    if (it == rows + h || *it != r) throw std::runtime_error("K entry outside the factor structure");
+    km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sh[k] + (it - rows);
+  }
+}
+
+}  // namespace pdipm

@@ -1,0 +1,114 @@
+// Host-side structures: problem data on fixed patterns, the K pattern with
+// its assembly map, and the numeric plan of the supernodal factorisation.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pdipm.h"
+#include "symbolic.hpp"
+
+namespace pdipm {
+
+enum Kind { KIND_LP = 0, KIND_QP = 1, KIND_NLP = 2 };
+
+// Problem (1) with bounds, stored on the patterns the derivative kernels use.
+struct HostProblem {
+  int64_t n = 0, m = 0;
+  int kind = KIND_LP;
+  std::vector<double> c, b, q4, xl, xu;  // q4 empty when absent; bounds +-inf
+  bool has_q4 = false, has_w = false;
+  // J = A - 2 W diag(x) on the union pattern of A and W (m x n, CSR)
+  std::vector<int64_t> jp;
+  std::vector<int32_t> jc;
+  std::vector<double> ja, jw;
+  // J transposed: for column j the rows k (ascending) and J entry indices
+  std::vector<int64_t> jtp;
+  std::vector<int32_t> jtr, jte;
+  // H lower pattern (original numbering): Q's lower triangle plus the full
+  // diagonal; hq = Q values (0 on added diagonal entries); hdiag[i] = index
+  std::vector<int64_t> hp;
+  std::vector<int32_t> hc;
+  std::vector<double> hq;
+  std::vector<int64_t> hdiag;
+  // symmetric H pattern for products H v: column indices and source entry
+  std::vector<int64_t> hsp;
+  std::vector<int32_t> hsc, hss;
+};
+
+// Lower CSR pattern of K (original numbering) and the assembly map:
+//   K(e) = H(kh[e]) + [row == col](Sigma_x + delta_p)
+//        + sum_{t in tp[e]..tp[e+1]} Sigma_s[tk[t]] J[ta[t]] J[tb[t]]
+struct KMap {
+  int64_t n = 0;
+  std::vector<int64_t> kp;
+  std::vector<int32_t> kc, krow, kh;
+  std::vector<int64_t> tp;
+  std::vector<int32_t> tk, ta, tb;
+  std::vector<int64_t> pos;  // element offset of the entry in the panels
+};
+
+// Launch descriptors (offsets are element offsets in the named buffers).
+struct GemmDesc {          // C (-)= A * B^T on an M x N block, K inner
+  int64_t c_off, a_off, b_off;
+  int32_t ldc, lda, ldb;
+  int32_t M, N, K;
+  int32_t c_buf;           // 0 panels, 1 update matrices
+  int32_t b_buf;           // 0 panels, 1 inverse-diagonal scratch
+  int32_t mode;            // 0 subtract (lower masked when lower=1), 1 set
+  int32_t lower;
+  int32_t tiles_m, tiles_n;
+  int64_t tile_begin;      // first tile of this descriptor in its launch
+};
+
+struct PotrfDesc {         // factor the bw x bw diagonal block, write inverse
+  int64_t d_off;           // panel offset of the block's (0,0)
+  int64_t inv_off;         // scratch offset of the inverse (ld = nb)
+  int32_t ld, bw;
+  int32_t col0;            // permuted column of the block's first column
+  int32_t pad;
+};
+
+struct ExtAddDesc {        // parent front, target front columns [t0, t1)
+  int32_t sn, t0, t1, pad;
+};
+
+enum OpType { OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE };
+
+struct Op {
+  int type;
+  int64_t begin, end;      // descriptor range in the pool of its type
+  int64_t grid;            // workgroups
+};
+
+struct Plan {
+  int64_t ns = 0, n = 0;
+  int nb = 64;             // panel block width of the blocked path
+  int small_h = 64;        // fronts with h <= small_h use the one-workgroup path
+  int esize = 8;           // bytes per panel element (8 FP64, 4 FP32)
+  std::vector<int32_t> sfirst, sw, sh, sparent, slevel;
+  std::vector<int64_t> spanel, su, srow, suv;  // panel / U / row / update-vector offsets
+  std::vector<int32_t> child_ptr, child;
+  std::vector<int32_t> rel;           // parallel to sn_rows: row position in the parent
+  int nlevels = 0;
+  std::vector<int32_t> level_ptr, level_sn;  // supernodes by level
+  int64_t panel_elems = 0, u_elems = 0, uv_elems = 0;
+  int64_t inv_elems = 0;              // inverse-diagonal scratch
+  int64_t max_front = 0;
+  std::vector<Op> ops;
+  std::vector<GemmDesc> gemm;
+  std::vector<PotrfDesc> potrf;
+  std::vector<ExtAddDesc> ext;
+  std::vector<int32_t> small;
+  double update_bytes = 0;
+};
+
+std::string build_problem(const ::ipm_problem_desc* d, HostProblem* p);
+void build_graph_from_problem(const HostProblem& p, Graph* g);
+void build_graph_from_lower(int64_t n, const int64_t* rp, const int32_t* ci, Graph* g);
+void build_kmap_problem(const HostProblem& p, KMap* km);
+void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km);
+void build_plan(const Symbolic& s, int precision_bytes, Plan* plan);
+void map_k_to_panels(const Symbolic& s, const Plan& plan, KMap* km);
+
+}  // namespace pdipm

@@ -1,0 +1,1033 @@
+// gfx950 kernels of the interior-point hot path.
+//
+// Every reduction is two-pass with a fixed partition (no floating-point
+// atomics), assembly and extend-add sum in a fixed order, so repeated runs
+// give bitwise-identical results.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace pdipm {
+
+namespace {
+
+constexpr int BS = 256;
+
+inline int64_t blocks_for(int64_t n, int bs = BS) {
+  int64_t b = (n + bs - 1) / bs;
+  return b < 1 ? 1 : b;
+}
+
+__device__ inline bool has_lo(double l) { return l > -INFINITY; }
+__device__ inline bool has_hi(double u) { return u < INFINITY; }
+
+__device__ inline double red_init(int op) {
+  return op == RED_SUM ? 0.0 : (op == RED_MAX ? -INFINITY : INFINITY);
+}
+__device__ inline double red_comb(int op, double a, double b) {
+  return op == RED_SUM ? a + b : (op == RED_MAX ? fmax(a, b) : fmin(a, b));
+}
+
+// Reduce v[0..nq) over the block and store one partial per quantity.
+template <int NQ>
+__device__ void block_reduce_store(double (&v)[NQ], const RedSpec& spec, double* partials) {
+  __shared__ double sh[NQ][BS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double x = v[q];
+    for (int off = 32; off > 0; off >>= 1) x = red_comb(spec.op[q], x, __shfl_down(x, off, 64));
+    if (lane == 0) sh[q][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double x = sh[q][0];
+      for (int w = 1; w < BS / 64; ++w) x = red_comb(spec.op[q], x, sh[q][w]);
+      partials[(int64_t)q * gridDim.x + blockIdx.x] = x;
+    }
+  }
+}
+
+__global__ void k_finalize(const double* partials, int nblocks, RedSpec spec, double* out) {
+  __shared__ double sh[BS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < spec.nq; ++q) {
+    double x = red_init(spec.op[q]);
+    for (int b = threadIdx.x; b < nblocks; b += BS) x = red_comb(spec.op[q], x, partials[(int64_t)q * nblocks + b]);
+    for (int off = 32; off > 0; off >>= 1) x = red_comb(spec.op[q], x, __shfl_down(x, off, 64));
+    if (lane == 0) sh[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double y = sh[0];
+      for (int w = 1; w < BS / 64; ++w) y = red_comb(spec.op[q], y, sh[w]);
+      out[q] = y;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) p[i] = v;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) p[i] = 0u;
+}
+
+// ------------------------------------------------------------ evaluation
+__global__ void k_jac_eval(int64_t nnz, const double* ja, const double* jw, const int32_t* jc,
+                           const double* x, double* jv) {
+  int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (e < nnz) jv[e] = ja[e] - 2.0 * jw[e] * x[jc[e]];
+}
+
+__global__ void k_constraints(int64_t m, const int64_t* jp, const int32_t* jc, const double* ja,
+                              const double* jw, const double* x, const double* b, double* g) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k >= m) return;
+  double acc = 0.0;
+  for (int64_t e = jp[k]; e < jp[k + 1]; ++e) {
+    double xc = x[jc[e]];
+    acc += (ja[e] - jw[e] * xc) * xc;
+  }
+  g[k] = acc - b[k];
+}
+
+__global__ void k_gradient(int64_t n, const int64_t* hsp, const int32_t* hsc, const int32_t* hss,
+                           const double* hq, const double* c, const double* q4, const double* x,
+                           double* qx, double* gf) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int64_t q = hsp[i]; q < hsp[i + 1]; ++q) acc += hq[hss[q]] * x[hsc[q]];
+  qx[i] = acc;
+  double xi = x[i];
+  gf[i] = c[i] + acc + (q4 ? q4[i] * xi * xi * xi : 0.0);
+}
+
+__global__ void k_hess_eval(int64_t n, const int64_t* hp, const int64_t* hdiag, const double* hq,
+                            const double* q4, const int64_t* jtp, const int32_t* jtr,
+                            const int32_t* jte, const double* jw, const double* x, const double* lam,
+                            double* hv) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = hp[i]; e < hp[i + 1]; ++e) hv[e] = hq[e];
+  double wl = 0.0;
+  for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) wl += jw[jte[q]] * lam[jtr[q]];
+  double xi = x[i];
+  hv[hdiag[i]] += (q4 ? 3.0 * q4[i] * xi * xi : 0.0) + 2.0 * wl;
+}
+
+__global__ void k_jt_mul(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
+                         const double* jv, const double* y, double* out) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) acc += jv[jte[q]] * y[jtr[q]];
+  out[i] = acc;
+}
+
+__global__ void k_j_mul(int64_t m, const int64_t* jp, const int32_t* jc, const double* jv,
+                        const double* v, double* out) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k >= m) return;
+  double acc = 0.0;
+  for (int64_t e = jp[k]; e < jp[k + 1]; ++e) acc += jv[e] * v[jc[e]];
+  out[k] = acc;
+}
+
+__global__ void k_h_mul(int64_t n, const int64_t* hsp, const int32_t* hsc, const int32_t* hss,
+                        const double* hv, const double* v, double* out) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int64_t q = hsp[i]; q < hsp[i + 1]; ++q) acc += hv[hss[q]] * v[hsc[q]];
+  out[i] = acc;
+}
+
+// ------------------------------------------------------------ assembly
+// One thread per entry of K's lower pattern: fixed-order segmented sum of
+// the J' Sigma_s J products plus the Hessian and diagonal terms.
+template <typename T>
+__global__ void k_assemble(DevKMap K, const double* hv, const double* jv, const double* sig_s,
+                           const double* sig_x, double delta_p, T* panel, double* kval) {
+  int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (e >= K.nk) return;
+  double v = 0.0;
+  int32_t h = K.kh[e];
+  if (h >= 0) v = hv[h];
+  int32_t r = K.krow[e];
+  if (r == K.kc[e]) v += sig_x[r] + delta_p;
+  for (int64_t t = K.tp[e]; t < K.tp[e + 1]; ++t) v += sig_s[K.tk[t]] * jv[K.ta[t]] * jv[K.tb[t]];
+  panel[K.pos[e]] = (T)v;
+  if (kval) kval[e] = v;
+}
+
+template <typename T>
+__global__ void k_set_values(DevKMap K, const double* kval, T* panel) {
+  int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (e < K.nk) panel[K.pos[e]] = (T)kval[e];
+}
+
+__global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc, const int64_t* kss,
+                               const double* kval, const double* v, double* out) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int64_t q = ksp[i]; q < ksp[i + 1]; ++q) acc += kval[kss[q]] * v[ksc[q]];
+  out[i] = acc;
+}
+
+// ------------------------------------------------------- factorisation
+// Small fronts (h <= 64): the whole front in LDS; children's update
+// matrices are added in child order, then w columns are eliminated and the
+// panel and the new update matrix are written back.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* panel, T* ubuf, int* bad) {
+  constexpr int LD = 65;
+  __shared__ T F[64 * LD];
+  const int32_t S = P.small[d0 + blockIdx.x];
+  const int h = P.sh[S], w = P.sw[S];
+  const int64_t poff = P.spanel[S];
+  for (int idx = threadIdx.x; idx < h * h; idx += BS) {
+    int i = idx % h, j = idx / h;
+    F[i + j * LD] = (j < w && i >= j) ? panel[poff + i + (int64_t)j * h] : (T)0;
+  }
+  __syncthreads();
+  for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
+    const int32_t c = P.child[q];
+    const int hu = P.sh[c] - P.sw[c];
+    const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
+    const T* U = ubuf + P.su[c];
+    for (int idx = threadIdx.x; idx < hu * hu; idx += BS) {
+      int i = idx % hu, j = idx / hu;
+      if (i >= j) F[rc[i] + rc[j] * LD] += U[i + (int64_t)j * hu];
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < w; ++k) {
+    if (threadIdx.x == 0) {
+      T d = F[k + k * LD];
+      if (!(d > (T)0) || !isfinite((double)d)) {
+        atomicMin(bad, P.sfirst[S] + k);
+        d = (T)1;
+      }
+      F[k + k * LD] = sqrt(d);
+    }
+    __syncthreads();
+    const T piv = F[k + k * LD];
+    for (int i = k + 1 + threadIdx.x; i < h; i += BS) F[i + k * LD] /= piv;
+    __syncthreads();
+    const int r = h - k - 1;
+    for (int idx = threadIdx.x; idx < r * r; idx += BS) {
+      int i = k + 1 + idx % r, j = k + 1 + idx / r;
+      if (i >= j) F[i + j * LD] -= F[i + k * LD] * F[j + k * LD];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < h * w; idx += BS) {
+    int i = idx % h, j = idx / h;
+    if (i >= j) panel[poff + i + (int64_t)j * h] = F[i + j * LD];
+  }
+  const int hu = h - w;
+  T* U = ubuf + P.su[S];
+  for (int idx = threadIdx.x; idx < hu * hu; idx += BS) {
+    int i = idx % hu, j = idx / hu;
+    if (i >= j) U[i + (int64_t)j * hu] = F[(w + i) + (w + j) * LD];
+  }
+}
+
+// Extend-add for large fronts: a workgroup owns front columns [t0, t1) of
+// parent S and adds every child's update matrix entries landing there, one
+// child after the other.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* panel, T* ubuf) {
+  const ExtAddDesc d = P.ext[d0 + blockIdx.x];
+  const int32_t S = d.sn;
+  const int hP = P.sh[S], wP = P.sw[S];
+  T* pan = panel + P.spanel[S];
+  T* UP = ubuf + P.su[S];
+  const int64_t ldu = hP - wP;
+  for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
+    const int32_t c = P.child[q];
+    const int hu = P.sh[c] - P.sw[c];
+    const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
+    const T* U = ubuf + P.su[c];
+    int lo = 0, hi = hu;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (rc[mid] < d.t0) lo = mid + 1; else hi = mid; }
+    int jlo = lo;
+    hi = hu;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (rc[mid] < d.t1) lo = mid + 1; else hi = mid; }
+    int jhi = lo;
+    for (int j = jlo; j < jhi; ++j) {
+      const int tj = rc[j];
+      for (int i = j + threadIdx.x; i < hu; i += BS) {
+        const int ti = rc[i];
+        const T v = U[i + (int64_t)j * hu];
+        if (tj < wP) pan[ti + (int64_t)tj * hP] += v;
+        else UP[(ti - wP) + (int64_t)(tj - wP) * ldu] += v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Diagonal block Cholesky in LDS plus the inverse of the factor (used by
+// the triangular solve of the panel below it as a product).
+template <typename T, int NB>
+__global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
+  __shared__ T D[NB * (NB + 1)];
+  __shared__ T I[NB * (NB + 1)];
+  constexpr int LD = NB + 1;
+  const PotrfDesc d = P.potrf[d0 + blockIdx.x];
+  const int bw = d.bw;
+  T* g = panel + d.d_off;
+  for (int idx = threadIdx.x; idx < bw * bw; idx += BS) {
+    int i = idx % bw, j = idx / bw;
+    D[i + j * LD] = i >= j ? g[i + (int64_t)j * d.ld] : (T)0;
+  }
+  __syncthreads();
+  for (int k = 0; k < bw; ++k) {
+    if (threadIdx.x == 0) {
+      T v = D[k + k * LD];
+      if (!(v > (T)0) || !isfinite((double)v)) {
+        atomicMin(bad, d.col0 + k);
+        v = (T)1;
+      }
+      D[k + k * LD] = sqrt(v);
+    }
+    __syncthreads();
+    const T piv = D[k + k * LD];
+    for (int i = k + 1 + threadIdx.x; i < bw; i += BS) D[i + k * LD] /= piv;
+    __syncthreads();
+    const int r = bw - k - 1;
+    for (int idx = threadIdx.x; idx < r * r; idx += BS) {
+      int i = k + 1 + idx % r, j = k + 1 + idx / r;
+      if (i >= j) D[i + j * LD] -= D[i + k * LD] * D[j + k * LD];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < bw * bw; idx += BS) {
+    int i = idx % bw, j = idx / bw;
+    if (i >= j) g[i + (int64_t)j * d.ld] = D[i + j * LD];
+  }
+  // inverse of the lower factor, one column per thread
+  for (int j = threadIdx.x; j < bw; j += BS) {
+    for (int i = 0; i < j; ++i) I[i + j * LD] = (T)0;
+    I[j + j * LD] = (T)1 / D[j + j * LD];
+    for (int i = j + 1; i < bw; ++i) {
+      T s = 0;
+      for (int k = j; k < i; ++k) s += D[i + k * LD] * I[k + j * LD];
+      I[i + j * LD] = -s / D[i + i * LD];
+    }
+  }
+  __syncthreads();
+  T* o = inv + d.inv_off;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += BS) {
+    int i = idx % NB, j = idx / NB;
+    o[i + (int64_t)j * NB] = (i < bw && j < bw) ? I[i + j * LD] : (T)0;
+  }
+}
+
+__device__ inline int64_t find_desc(const GemmDesc* g, int64_t d0, int64_t d1, int64_t bid) {
+  int64_t lo = d0, hi = d1 - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (g[mid].tile_begin <= bid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup, each of the
+// four waves owns a 32x32 quadrant (2x2 MFMA blocks).
+__global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, double* panel,
+                                                 double* ubuf, const double* inv) {
+  constexpr int TM = 64, KC = 16, LDS_LD = TM + 2;
+  __shared__ double As[KC * LDS_LD];
+  __shared__ double Bs[KC * LDS_LD];
+  const int64_t bid = blockIdx.x;
+  const GemmDesc d = P.gemm[find_desc(P.gemm, d0, d1, bid)];
+  const int64_t t = bid - d.tile_begin;
+  const int i0 = (int)(t % d.tiles_m) * TM, j0 = (int)(t / d.tiles_m) * TM;
+  if (d.lower && i0 + TM - 1 < j0) return;
+  double* C = (d.c_buf ? ubuf : panel) + d.c_off;
+  const double* A = panel + d.a_off;
+  const double* B = (d.b_buf ? inv : panel) + d.b_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < d.K; k0 += KC) {
+#pragma unroll
+    for (int r = 0; r < (TM * KC) / BS; ++r) {
+      const int idx = tid + r * BS;
+      const int ii = idx % TM, kk = idx / TM;
+      const int gk = k0 + kk;
+      const int gi = i0 + ii, gj = j0 + ii;
+      As[kk * LDS_LD + ii] = (gi < d.M && gk < d.K) ? A[gi + (int64_t)gk * d.lda] : 0.0;
+      Bs[kk * LDS_LD + ii] = (gj < d.N && gk < d.K) ? B[gj + (int64_t)gk * d.ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[(kk + (lane >> 4)) * LDS_LD + wm + q * 16 + (lane & 15)];
+        b[q] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wm + x * 16 + 4 * r + (lane >> 4);
+        const int j = j0 + wn + y * 16 + (lane & 15);
+        if (i < d.M && j < d.N && (!d.lower || i >= j)) {
+          double* cp = C + i + (int64_t)j * d.ldc;
+          if (d.mode == 0) *cp -= acc[x][y][r];
+          else *cp = acc[x][y][r];
+        }
+      }
+}
+
+// C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
+// per workgroup, each wave a 64x64 quadrant (2x2 MFMA blocks).
+__global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, float* panel,
+                                                 float* ubuf, const float* inv) {
+  constexpr int TM = 128, KC = 16, LDS_LD = TM + 4;
+  __shared__ float As[KC * LDS_LD];
+  __shared__ float Bs[KC * LDS_LD];
+  const int64_t bid = blockIdx.x;
+  const GemmDesc d = P.gemm[find_desc(P.gemm, d0, d1, bid)];
+  const int64_t t = bid - d.tile_begin;
+  const int i0 = (int)(t % d.tiles_m) * TM, j0 = (int)(t / d.tiles_m) * TM;
+  if (d.lower && i0 + TM - 1 < j0) return;
+  float* C = (d.c_buf ? ubuf : panel) + d.c_off;
+  const float* A = panel + d.a_off;
+  const float* B = (d.b_buf ? inv : panel) + d.b_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  for (int k0 = 0; k0 < d.K; k0 += KC) {
+#pragma unroll
+    for (int r = 0; r < (TM * KC) / BS; ++r) {
+      const int idx = tid + r * BS;
+      const int ii = idx % TM, kk = idx / TM;
+      const int gk = k0 + kk;
+      const int gi = i0 + ii, gj = j0 + ii;
+      As[kk * LDS_LD + ii] = (gi < d.M && gk < d.K) ? A[gi + (int64_t)gk * d.lda] : 0.0f;
+      Bs[kk * LDS_LD + ii] = (gj < d.N && gk < d.K) ? B[gj + (int64_t)gk * d.ldb] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      float a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[(kk + (lane >> 5)) * LDS_LD + wm + q * 32 + (lane & 31)];
+        b[q] = Bs[(kk + (lane >> 5)) * LDS_LD + wn + q * 32 + (lane & 31)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = i0 + wm + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + wn + y * 32 + (lane & 31);
+        if (i < d.M && j < d.N && (!d.lower || i >= j)) {
+          float* cp = C + i + (int64_t)j * d.ldc;
+          if (d.mode == 0) *cp -= acc[x][y][r];
+          else *cp = acc[x][y][r];
+        }
+      }
+}
+
+// --------------------------------------------------- triangular solves
+__global__ void k_permute_in(int64_t n, const int32_t* perm, const double* rhs, double* xp) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k < n) xp[k] = rhs[perm[k]];
+}
+__global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, double* x) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k < n) x[perm[k]] = xp[k];
+}
+
+// Forward solve of one level: each supernode gathers its children's update
+// vectors, eliminates its columns and leaves its own update vector.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_fwd_level(DevPlan P, int32_t q0, const T* panel, double* xp,
+                                                 double* uvec) {
+  const int32_t S = P.level_sn[q0 + blockIdx.x];
+  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
+  const int64_t uo = P.suv[S];
+  const T* L = panel + P.spanel[S];
+  for (int i = threadIdx.x; i < h - w; i += BS) uvec[uo + i] = 0.0;
+  __syncthreads();
+  for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
+    const int32_t c = P.child[q];
+    const int hu = P.sh[c] - P.sw[c];
+    const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
+    const double* uc = uvec + P.suv[c];
+    for (int i = threadIdx.x; i < hu; i += BS) {
+      const int r = rc[i];
+      if (r < w) xp[f + r] += uc[i];
+      else uvec[uo + r - w] += uc[i];
+    }
+    __syncthreads();
+  }
+  // row i is owned by thread i % BS; y_j = t_j / L_jj is formed on the fly
+  for (int j = 0; j < w; ++j) {
+    const double yj = xp[f + j] / (double)L[j + (int64_t)j * h];
+    for (int i = j + 1 + threadIdx.x; i < h; i += BS) {
+      const double l = (double)L[i + (int64_t)j * h];
+      if (i < w) xp[f + i] -= l * yj;
+      else uvec[uo + i - w] -= l * yj;
+    }
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < w; j += BS) xp[f + j] /= (double)L[j + (int64_t)j * h];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_bwd_level(DevPlan P, int32_t q0, const T* panel, double* xp) {
+  const int32_t S = P.level_sn[q0 + blockIdx.x];
+  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
+  const int hu = h - w;
+  const T* L = panel + P.spanel[S];
+  const int32_t* rows = P.sn_rows + P.srow[S];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < w; j += BS / 64) {
+    double s = 0.0;
+    for (int i = lane; i < hu; i += 64) s += (double)L[(w + i) + (int64_t)j * h] * xp[rows[w + i]];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) xp[f + j] -= s;
+  }
+  __syncthreads();
+  for (int j = w - 1; j >= 0; --j) {
+    const double zj = xp[f + j] / (double)L[j + (int64_t)j * h];
+    for (int i = threadIdx.x; i < j; i += BS) xp[f + i] -= (double)L[j + (int64_t)i * h] * zj;
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < w; j += BS) xp[f + j] /= (double)L[j + (int64_t)j * h];
+}
+
+// -------------------------------------------------------- IPM vectors
+__global__ void k_residuals(DevProblem P, const double* jtl, const double* gf, const double* zl,
+                            const double* zu, const double* g, const double* s, double* rd, double* rp) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.n) rd[i] = gf[i] - jtl[i] - (has_lo(P.xl[i]) ? zl[i] : 0.0) + (has_hi(P.xu[i]) ? zu[i] : 0.0);
+  if (i < P.m) rp[i] = g[i] - s[i];
+}
+
+// Per-iteration statistics: max|r_p|, max|g|, max|r_d|, max|grad f|,
+// complementarity sum, objective sum, count of non-finite values.
+__global__ void k_stats_iter(DevProblem P, IpmVecs v, double* partials) {
+  RedSpec spec{7, {RED_MAX, RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_SUM, RED_SUM}};
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int64_t N = P.n > P.m ? P.n : P.m;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    if (i < P.m) {
+      a[0] = fmax(a[0], fabs(v.rp[i]));
+      a[1] = fmax(a[1], fabs(v.g[i]));
+      a[4] += v.s[i] * v.lam[i];
+      if (!isfinite(v.rp[i]) || !isfinite(v.lam[i])) a[6] += 1;
+    }
+    if (i < P.n) {
+      const double x = v.x[i];
+      a[2] = fmax(a[2], fabs(v.rd[i]));
+      a[3] = fmax(a[3], fabs(v.gf[i]));
+      if (has_lo(P.xl[i])) a[4] += (x - P.xl[i]) * v.zl[i];
+      if (has_hi(P.xu[i])) a[4] += (P.xu[i] - x) * v.zu[i];
+      a[5] += P.c[i] * x + 0.5 * x * v.qx[i] + (P.q4 ? 0.25 * P.q4[i] * x * x * x * x : 0.0);
+      if (!isfinite(v.rd[i]) || !isfinite(x)) a[6] += 1;
+    }
+  }
+  block_reduce_store<7>(a, spec, partials);
+}
+
+__global__ void k_sigmas(DevProblem P, IpmVecs v, double dd) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.m) v.sig_s[i] = v.lam[i] / (v.s[i] + dd * v.lam[i]);
+  if (i < P.n) {
+    double sx = 0.0;
+    if (has_lo(P.xl[i])) sx += v.zl[i] / (v.x[i] - P.xl[i]);
+    if (has_hi(P.xu[i])) sx += v.zu[i] / (P.xu[i] - v.x[i]);
+    v.sig_x[i] = sx;
+  }
+}
+
+__global__ void k_rhs_m(DevProblem P, IpmVecs v, const double* ts, double* wm) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k < P.m) wm[k] = v.sig_s[k] * (v.g[k] - (ts ? ts[k] / v.lam[k] : 0.0));
+}
+
+__global__ void k_rhs_n(DevProblem P, IpmVecs v, const double* jtw, const double* tl, const double* tu,
+                        double* rhs) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= P.n) return;
+  double rt = v.rd[i];
+  if (has_lo(P.xl[i])) rt += -(tl ? tl[i] : 0.0) / (v.x[i] - P.xl[i]) + v.zl[i];
+  if (has_hi(P.xu[i])) rt += (tu ? tu[i] : 0.0) / (P.xu[i] - v.x[i]) - v.zu[i];
+  rhs[i] = -rt - jtw[i];
+}
+
+__global__ void k_recover_m(DevProblem P, IpmVecs v, const double* jdx, const double* ts, double dd,
+                            double* ds, double* dlam) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k >= P.m) return;
+  const double dl = v.sig_s[k] * ((ts ? ts[k] / v.lam[k] : 0.0) - v.g[k] - jdx[k]);
+  dlam[k] = dl;
+  ds[k] = jdx[k] + v.rp[k] + dd * dl;
+}
+
+__global__ void k_recover_n(DevProblem P, IpmVecs v, const double* dx, const double* tl, const double* tu,
+                            double* dzl, double* dzu) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= P.n) return;
+  if (has_lo(P.xl[i])) {
+    const double gap = v.x[i] - P.xl[i];
+    dzl[i] = (tl ? tl[i] : 0.0) / gap - v.zl[i] - v.zl[i] / gap * dx[i];
+  } else {
+    dzl[i] = 0.0;
+  }
+  if (has_hi(P.xu[i])) {
+    const double gap = P.xu[i] - v.x[i];
+    dzu[i] = (tu ? tu[i] : 0.0) / gap - v.zu[i] + v.zu[i] / gap * dx[i];
+  } else {
+    dzu[i] = 0.0;
+  }
+}
+
+__device__ inline void ratio(double& a, double val, double d) {
+  if (d < 0.0) a = fmin(a, -val / d);
+}
+
+// Largest steps keeping (s, x-l, u-x) and (lambda, z_l, z_u) non-negative.
+__global__ void k_step_limits(DevProblem P, IpmVecs v, const double* dx, const double* ds,
+                              const double* dlam, const double* dzl, const double* dzu, double* partials) {
+  RedSpec spec{2, {RED_MIN, RED_MIN}};
+  double a[2] = {INFINITY, INFINITY};
+  const int64_t N = P.n > P.m ? P.n : P.m;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    if (i < P.m) {
+      ratio(a[0], v.s[i], ds[i]);
+      ratio(a[1], v.lam[i], dlam[i]);
+    }
+    if (i < P.n) {
+      if (has_lo(P.xl[i])) { ratio(a[0], v.x[i] - P.xl[i], dx[i]); ratio(a[1], v.zl[i], dzl[i]); }
+      if (has_hi(P.xu[i])) { ratio(a[0], P.xu[i] - v.x[i], -dx[i]); ratio(a[1], v.zu[i], dzu[i]); }
+    }
+  }
+  block_reduce_store<2>(a, spec, partials);
+}
+
+__global__ void k_mu_aff(DevProblem P, IpmVecs v, const double* dx, const double* ds, const double* dlam,
+                         const double* dzl, const double* dzu, double ap, double ad, double* partials) {
+  RedSpec spec{1, {RED_SUM}};
+  double a[1] = {0.0};
+  const int64_t N = P.n > P.m ? P.n : P.m;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    if (i < P.m) a[0] += (v.s[i] + ap * ds[i]) * (v.lam[i] + ad * dlam[i]);
+    if (i < P.n) {
+      if (has_lo(P.xl[i])) a[0] += (v.x[i] - P.xl[i] + ap * dx[i]) * (v.zl[i] + ad * dzl[i]);
+      if (has_hi(P.xu[i])) a[0] += (P.xu[i] - v.x[i] - ap * dx[i]) * (v.zu[i] + ad * dzu[i]);
+    }
+  }
+  block_reduce_store<1>(a, spec, partials);
+}
+
+__global__ void k_targets(DevProblem P, const double* dx, const double* ds, const double* dlam,
+                          const double* dzl, const double* dzu, double smu, double* ts, double* tl,
+                          double* tu) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.m) ts[i] = smu - ds[i] * dlam[i];
+  if (i < P.n) {
+    tl[i] = has_lo(P.xl[i]) ? smu - dx[i] * dzl[i] : 0.0;
+    tu[i] = has_hi(P.xu[i]) ? smu + dx[i] * dzu[i] : 0.0;
+  }
+}
+
+__global__ void k_axpy_point(DevProblem P, IpmVecs dst, IpmVecs src, const double* dx, const double* ds,
+                             const double* dlam, const double* dzl, const double* dzu, double ap, double ad) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.m) {
+    dst.s[i] = src.s[i] + ap * ds[i];
+    dst.lam[i] = src.lam[i] + ad * dlam[i];
+  }
+  if (i < P.n) {
+    dst.x[i] = src.x[i] + ap * dx[i];
+    dst.zl[i] = has_lo(P.xl[i]) ? src.zl[i] + ad * dzl[i] : 0.0;
+    dst.zu[i] = has_hi(P.xu[i]) ? src.zu[i] + ad * dzu[i] : 0.0;
+  }
+}
+
+// Squared residual norm of the perturbed KKT conditions (NLP line search).
+__global__ void k_phi(DevProblem P, IpmVecs v, double smu, double* partials) {
+  RedSpec spec{1, {RED_SUM}};
+  double a[1] = {0.0};
+  const int64_t N = P.n > P.m ? P.n : P.m;
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    if (i < P.m) {
+      const double c = v.s[i] * v.lam[i] - smu;
+      a[0] += v.rp[i] * v.rp[i] + c * c;
+    }
+    if (i < P.n) {
+      a[0] += v.rd[i] * v.rd[i];
+      if (has_lo(P.xl[i])) { const double c = (v.x[i] - P.xl[i]) * v.zl[i] - smu; a[0] += c * c; }
+      if (has_hi(P.xu[i])) { const double c = (P.xu[i] - v.x[i]) * v.zu[i] - smu; a[0] += c * c; }
+    }
+  }
+  block_reduce_store<1>(a, spec, partials);
+}
+
+__global__ void k_init_point(DevProblem P, IpmVecs v) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.n) {
+    const bool lo = has_lo(P.xl[i]), hi = has_hi(P.xu[i]);
+    double x = 0.0;
+    if (lo && hi) x = 0.5 * (P.xl[i] + P.xu[i]);
+    else if (lo) x = P.xl[i] + 1.0;
+    else if (hi) x = P.xu[i] - 1.0;
+    v.x[i] = x;
+    v.zl[i] = lo ? 1.0 : 0.0;
+    v.zu[i] = hi ? 1.0 : 0.0;
+  }
+  if (i < P.m) v.lam[i] = 1.0;
+}
+
+__global__ void k_slack_from_g(DevProblem P, IpmVecs v, int warm) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k >= P.m) return;
+  const double g = v.g[k];
+  v.s[k] = warm ? fmax(g, 1e-2 * fmax(1.0, fabs(g))) : fmax(g, 1.0);
+}
+
+// Interior push of a supplied point (bound-push rule of Waechter-Biegler).
+__global__ void k_push_x(DevProblem P, IpmVecs v, const double* xhat, const double* lamhat) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < P.n) {
+    const bool lo = has_lo(P.xl[i]), hi = has_hi(P.xu[i]);
+    const double width = (lo && hi) ? P.xu[i] - P.xl[i] : INFINITY;
+    double x = xhat[i];
+    if (lo) x = fmax(x, P.xl[i] + fmin(1e-2 * fmax(1.0, fabs(P.xl[i])), 1e-2 * width));
+    if (hi) x = fmin(x, P.xu[i] - fmin(1e-2 * fmax(1.0, fabs(P.xu[i])), 1e-2 * width));
+    v.x[i] = x;
+  }
+  if (i < P.m) v.lam[i] = fmax(lamhat[i], 1e-2);
+}
+
+__global__ void k_push_duals(DevProblem P, IpmVecs v, double mu_w) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i >= P.n) return;
+  v.zl[i] = has_lo(P.xl[i]) ? mu_w / (v.x[i] - P.xl[i]) : 0.0;
+  v.zu[i] = has_hi(P.xu[i]) ? mu_w / (P.xu[i] - v.x[i]) : 0.0;
+}
+
+__global__ void k_sum_sl(DevProblem P, IpmVecs v, double* partials) {
+  RedSpec spec{1, {RED_SUM}};
+  double a[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < P.m; i += (int64_t)gridDim.x * BS)
+    a[0] += v.s[i] * v.lam[i];
+  block_reduce_store<1>(a, spec, partials);
+}
+
+// K v = H v + (Sigma_x + delta_p) v + J'(Sigma_s (J v)), second part
+__global__ void k_kfree_m(int64_t m, const double* sig_s, double* jv_tmp) {
+  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (k < m) jv_tmp[k] *= sig_s[k];
+}
+__global__ void k_kfree_n(int64_t n, const double* hv_v, const double* jt, const double* sig_x, double dp,
+                          const double* v, double* out) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) out[i] = hv_v[i] + jt[i] + (sig_x[i] + dp) * v[i];
+}
+
+__global__ void k_residual_norms(int64_t n, const double* rhs, const double* kx, double* r, double* partials) {
+  RedSpec spec{2, {RED_MAX, RED_MAX}};
+  double a[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double ri = rhs[i] - kx[i];
+    r[i] = ri;
+    a[0] = fmax(a[0], fabs(ri));
+    a[1] = fmax(a[1], fabs(rhs[i]));
+    if (!isfinite(ri)) a[0] = INFINITY;
+  }
+  block_reduce_store<2>(a, spec, partials);
+}
+
+__global__ void k_add(int64_t n, double* x, const double* c) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) x[i] += c[i];
+}
+__global__ void k_copy(int64_t n, double* d, const double* s) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+inline int red_grid(int64_t N) {
+  int64_t b = blocks_for(N);
+  return (int)(b < RED_BLOCKS ? b : RED_BLOCKS);
+}
+
+}  // namespace
+
+// ============================================================ wrappers
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = blocks_for(n);
+  if (g > 65536) g = 65536;
+  k_fill_f64<<<(unsigned)g, BS, 0, s>>>(p, n, v);
+}
+void launch_fill_bytes0(void* p, int64_t bytes, hipStream_t s) {
+  int64_t n = bytes / 4;
+  if (n <= 0) return;
+  int64_t g = blocks_for(n);
+  if (g > 65536) g = 65536;
+  k_zero_u32<<<(unsigned)g, BS, 0, s>>>((uint32_t*)p, n);
+}
+void launch_finalize(const double* partials, int nblocks, RedSpec spec, double* out, hipStream_t s) {
+  k_finalize<<<1, BS, 0, s>>>(partials, nblocks, spec, out);
+}
+
+void launch_jac_eval(const DevProblem& P, const double* x, double* jv, hipStream_t s) {
+  if (P.nnz_j == 0) return;
+  k_jac_eval<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.ja, P.jw, P.jc, x, jv);
+}
+void launch_constraints(const DevProblem& P, const double* x, double* g, hipStream_t s) {
+  if (P.m == 0) return;
+  k_constraints<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, P.ja, P.jw, x, P.b, g);
+}
+void launch_gradient(const DevProblem& P, const double* x, double* qx, double* gf, hipStream_t s) {
+  k_gradient<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, P.hq, P.c, P.q4, x, qx, gf);
+}
+void launch_hess_eval(const DevProblem& P, const double* x, const double* lam, double* hv, hipStream_t s) {
+  k_hess_eval<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hp, P.hdiag, P.hq, P.q4, P.jtp, P.jtr, P.jte,
+                                                        P.jw, x, lam, hv);
+}
+void launch_jt_mul(const DevProblem& P, const double* jv, const double* y, double* out, hipStream_t s) {
+  k_jt_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, y, out);
+}
+void launch_j_mul(const DevProblem& P, const double* jv, const double* v, double* out, hipStream_t s) {
+  if (P.m == 0) return;
+  k_j_mul<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, jv, v, out);
+}
+void launch_h_mul(const DevProblem& P, const double* hv, const double* v, double* out, hipStream_t s) {
+  k_h_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, hv, v, out);
+}
+
+template <typename T>
+void launch_assemble(const DevKMap& K, const double* hv, const double* jv, const double* sig_s,
+                     const double* sig_x, double delta_p, T* panel, double* kval, hipStream_t s) {
+  k_assemble<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, hv, jv, sig_s, sig_x, delta_p, panel, kval);
+}
+template void launch_assemble<double>(const DevKMap&, const double*, const double*, const double*,
+                                      const double*, double, double*, double*, hipStream_t);
+template void launch_assemble<float>(const DevKMap&, const double*, const double*, const double*,
+                                     const double*, double, float*, double*, hipStream_t);
+template <typename T>
+void launch_set_values(const DevKMap& K, const double* kval, T* panel, hipStream_t s) {
+  k_set_values<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, panel);
+}
+template void launch_set_values<double>(const DevKMap&, const double*, double*, hipStream_t);
+template void launch_set_values<float>(const DevKMap&, const double*, float*, hipStream_t);
+
+void launch_k_mul_stored(int64_t n, const int64_t*, const int32_t*, const int64_t* ksp, const int32_t* ksc,
+                         const int64_t* kss, const double* kval, const double* v, double* out, hipStream_t s) {
+  k_k_mul_stored<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, ksp, ksc, kss, kval, v, out);
+}
+
+template <typename T>
+void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv, int* bad, hipStream_t s) {
+  if (op.grid <= 0) return;
+  const unsigned g = (unsigned)op.grid;
+  switch (op.type) {
+    case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf); break;
+    case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad); break;
+    case OP_POTRF:
+      if constexpr (sizeof(T) == 8) k_potrf<T, 64><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
+      else k_potrf<T, 128><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
+      break;
+    case OP_TRSM:
+    case OP_UPDATE:
+      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g, BS, 0, s>>>(P, op.begin, op.end, panel, ubuf, inv);
+      else k_gemm_f32<<<g, BS, 0, s>>>(P, op.begin, op.end, panel, ubuf, inv);
+      break;
+  }
+}
+template void launch_factor_op<double>(const Op&, const DevPlan&, double*, double*, double*, int*, hipStream_t);
+template void launch_factor_op<float>(const Op&, const DevPlan&, float*, float*, float*, int*, hipStream_t);
+
+void launch_permute_in(const DevPlan& P, const double* rhs, double* xp, hipStream_t s) {
+  k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, xp);
+}
+void launch_permute_out(const DevPlan& P, const double* xp, double* x, hipStream_t s) {
+  k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, x);
+}
+template <typename T>
+void launch_fwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xp, double* uvec,
+                      hipStream_t s) {
+  if (q1 > q0) k_fwd_level<T><<<(unsigned)(q1 - q0), BS, 0, s>>>(P, q0, panel, xp, uvec);
+}
+template void launch_fwd_level<double>(const DevPlan&, int32_t, int32_t, const double*, double*, double*, hipStream_t);
+template void launch_fwd_level<float>(const DevPlan&, int32_t, int32_t, const float*, double*, double*, hipStream_t);
+template <typename T>
+void launch_bwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xp, hipStream_t s) {
+  if (q1 > q0) k_bwd_level<T><<<(unsigned)(q1 - q0), BS, 0, s>>>(P, q0, panel, xp);
+}
+template void launch_bwd_level<double>(const DevPlan&, int32_t, int32_t, const double*, double*, hipStream_t);
+template void launch_bwd_level<float>(const DevPlan&, int32_t, int32_t, const float*, double*, hipStream_t);
+
+void launch_residuals(const DevProblem& P, IpmVecs& v, hipStream_t s) {
+  // J' lambda into tmp_n
+  launch_jt_mul(P, v.jv, v.lam, v.tmp_n, s);
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_residuals<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v.tmp_n, v.gf, v.zl, v.zu, v.g, v.s, v.rd, v.rp);
+}
+void launch_stats_iter(const DevProblem& P, IpmVecs& v, double* partials, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  int g = red_grid(N);
+  k_stats_iter<<<g, BS, 0, s>>>(P, v, partials);
+  RedSpec spec{7, {RED_MAX, RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_SUM, RED_SUM}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_sigmas(const DevProblem& P, IpmVecs& v, double dd, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_sigmas<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, dd);
+}
+void launch_rhs(const DevProblem& P, IpmVecs& v, const double* ts, const double* tl, const double* tu,
+                double* rhs, hipStream_t s) {
+  if (P.m > 0) k_rhs_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, ts, v.tmp_m);
+  launch_jt_mul(P, v.jv, v.tmp_m, v.tmp_n, s);
+  k_rhs_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, v.tmp_n, tl, tu, rhs);
+}
+void launch_recover(const DevProblem& P, IpmVecs& v, const double* dx, const double* ts, const double* tl,
+                    const double* tu, double dd, double* ds, double* dlam, double* dzl, double* dzu,
+                    hipStream_t s) {
+  if (P.m > 0) {
+    launch_j_mul(P, v.jv, dx, v.tmp_m, s);
+    k_recover_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, v.tmp_m, ts, dd, ds, dlam);
+  }
+  k_recover_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, dx, tl, tu, dzl, dzu);
+}
+void launch_step_limits(const DevProblem& P, IpmVecs& v, const double* dx, const double* ds, const double* dlam,
+                        const double* dzl, const double* dzu, double* partials, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  int g = red_grid(N);
+  k_step_limits<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, partials);
+  RedSpec spec{2, {RED_MIN, RED_MIN}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_mu_aff(const DevProblem& P, IpmVecs& v, const double* dx, const double* ds, const double* dlam,
+                   const double* dzl, const double* dzu, double ap, double ad, double* partials, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  int g = red_grid(N);
+  k_mu_aff<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, ap, ad, partials);
+  RedSpec spec{1, {RED_SUM}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_targets(const DevProblem& P, const double* dx, const double* ds, const double* dlam,
+                    const double* dzl, const double* dzu, double smu, double* ts, double* tl, double* tu,
+                    hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_targets<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dx, ds, dlam, dzl, dzu, smu, ts, tl, tu);
+}
+void launch_axpy_point(const DevProblem& P, IpmVecs& dst, const IpmVecs& src, const double* dx, const double* ds,
+                       const double* dlam, const double* dzl, const double* dzu, double ap, double ad,
+                       hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_axpy_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dst, src, dx, ds, dlam, dzl, dzu, ap, ad);
+}
+void launch_phi(const DevProblem& P, IpmVecs& v, double smu, double* partials, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  int g = red_grid(N);
+  k_phi<<<g, BS, 0, s>>>(P, v, smu, partials);
+  RedSpec spec{1, {RED_SUM}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_init_point(const DevProblem& P, IpmVecs& v, hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_init_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v);
+  launch_constraints(P, v.x, v.g, s);
+  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 0);
+}
+void launch_push_start(const DevProblem& P, IpmVecs& v, const double* xhat, const double* lamhat, double,
+                       hipStream_t s) {
+  int64_t N = P.n > P.m ? P.n : P.m;
+  k_push_x<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, xhat, lamhat);
+  launch_constraints(P, v.x, v.g, s);
+  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 1);
+}
+void launch_push_duals(const DevProblem& P, IpmVecs& v, double mu_w, hipStream_t s) {
+  k_push_duals<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, mu_w);
+}
+void launch_sum_sl(const DevProblem& P, IpmVecs& v, double* partials, hipStream_t s) {
+  int g = red_grid(P.m > 0 ? P.m : 1);
+  k_sum_sl<<<g, BS, 0, s>>>(P, v, partials);
+  RedSpec spec{1, {RED_SUM}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_k_mul_free(const DevProblem& P, const double* jv, const double* hv, const double* sig_s,
+                       const double* sig_x, double dp, const double* v, double* out, double* tmp_m,
+                       double* tmp_n, hipStream_t s) {
+  // out <- H v ; tmp_m <- Sigma_s J v ; tmp_n <- J' tmp_m ; out <- out + tmp_n + (Sigma_x + dp) v
+  launch_h_mul(P, hv, v, out, s);
+  if (P.m > 0) {
+    launch_j_mul(P, jv, v, tmp_m, s);
+    k_kfree_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, sig_s, tmp_m);
+    launch_jt_mul(P, jv, tmp_m, tmp_n, s);
+  } else {
+    launch_fill_f64(tmp_n, P.n, 0.0, s);
+  }
+  k_kfree_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, out, tmp_n, sig_x, dp, v, out);
+}
+void launch_residual_norms(int64_t n, const double* rhs, const double* kx, double* r, double* partials,
+                           hipStream_t s) {
+  int g = red_grid(n);
+  k_residual_norms<<<g, BS, 0, s>>>(n, rhs, kx, r, partials);
+  RedSpec spec{2, {RED_MAX, RED_MAX}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_add(int64_t n, double* x, const double* c, hipStream_t s) {
+  k_add<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, x, c);
+}
+void launch_copy(int64_t n, double* d, const double* src, hipStream_t s) {
+  if (n > 0) k_copy<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, src);
+}
+
+}  // namespace pdipm
