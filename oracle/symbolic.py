@@ -17,12 +17,14 @@ ORD  Graph G = structure of K without its diagonal.
        otherwise: root r = pseudo-peripheral vertex (start at the vertex of
          minimum degree in G[C], move to the minimum-degree vertex of the last
          BFS level while the BFS height grows; ties to the smallest vertex);
-         BFS levels L_0..L_h from r; if h < 2 the natural (sorted) order;
+         BFS levels L_0..L_h from r; if h < 2 C is ordered by increasing
+         degree in G[C] (ties to the smallest vertex);
          else separator level l in [1, h-1] minimising
          |L_l| / min(|L_<l|, |L_>l|), then |2l - h|, then l;
          if the largest connected component left after removing L_l keeps
-         more than 7/8 of C the separator is rejected and C is ordered
-         naturally (such graphs fill in densely under any order);
+         more than 7/8 of C the separator is rejected and C is ordered by
+         increasing degree in G[C] (such graphs fill in densely under any
+         order; high-degree hub vertices go last);
          result order(L_<l) ++ order(L_>l) ++ sorted(L_l).
      The ND order is then composed with a postorder of the elimination tree
      (children in increasing index, roots in increasing index).
@@ -174,6 +176,11 @@ def _choose_separator(levels):
     return best[3]
 
 
+def _degree_order(adj, comp, inset):
+    deg = {v: sum(1 for u in adj[v] if inset[u]) for v in comp}
+    return sorted(comp, key=lambda v: (deg[v], v))
+
+
 def nested_dissection(adj, n, leaf=ND_LEAF):
     """ND order as a list: entry k = vertex placed at position k."""
     out = []
@@ -196,7 +203,7 @@ def nested_dissection(adj, n, leaf=ND_LEAF):
             _, levels = pseudo_peripheral(adj, comp, inset)
             h = len(levels) - 1
             if h < 2:
-                tasks.append(("emit", sorted(comp)))
+                tasks.append(("emit", _degree_order(adj, comp, inset)))
                 continue
             l = _choose_separator(levels)
             lower = [v for L in levels[:l] for v in L]
@@ -207,7 +214,7 @@ def nested_dissection(adj, n, leaf=ND_LEAF):
             for v in levels[l]:
                 inset[v] = True
             if 8 * biggest > 7 * len(comp):
-                tasks.append(("emit", sorted(comp)))
+                tasks.append(("emit", _degree_order(adj, comp, inset)))
                 continue
             tasks.append(("order", sorted(lower)))
             tasks.append(("order", sorted(upper)))

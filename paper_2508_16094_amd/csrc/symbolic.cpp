@@ -108,6 +108,15 @@ void leaf_minimum_degree(NdState& st, const std::vector<int32_t>& comp, std::vec
   }
 }
 
+// Order a component by increasing degree inside it (st.deg), ties by index.
+std::vector<int32_t> degree_order(const NdState& st, const std::vector<int32_t>& comp) {
+  std::vector<int32_t> out(comp);
+  std::stable_sort(out.begin(), out.end(), [&](int32_t a, int32_t b) {
+    return st.deg[a] != st.deg[b] ? st.deg[a] < st.deg[b] : a < b;
+  });
+  return out;
+}
+
 }  // namespace
 
 std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
@@ -186,7 +195,7 @@ std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
         }
         const int h = nl - 1;
         if (h < 2) {
-          tasks.push_back(Task{true, comp});
+          tasks.push_back(Task{true, degree_order(st, comp)});
         } else {
           const int64_t total = (int64_t)comp.size();
           int best = -1;
@@ -232,7 +241,7 @@ std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
           }
           for (int64_t q = lp[best]; q < lp[best + 1]; ++q) st.mark[order[q]] = cst;
           if (8 * biggest > 7 * total) {
-            tasks.push_back(Task{true, comp});
+            tasks.push_back(Task{true, degree_order(st, comp)});
             continue;
           }
           Task lo{false, std::vector<int32_t>(order.begin(), order.begin() + lp[best])};
