@@ -83,7 +83,7 @@ typedef struct ipm_options {
   double delta_d;        /* dual regularisation, default 1e-8 */
   int32_t precision;     /* PDIPM_FP64 or PDIPM_FP32 (workspace sized for it) */
   int32_t ir_max;        /* refinement steps per solve, default 10 */
-  double ir_tol;         /* relative residual target of refinement, 1e-12 */
+  double ir_tol;         /* backward-error target of refinement, 1e-14 */
   int32_t nd_leaf;       /* minimum-degree leaf size of the ordering, 64 */
   int32_t amalg_menu;    /* supernode amalgamation rule 0, 1, 2 (-1 = none) */
   int32_t print_level;   /* 0 silent, 1 per-iteration line on stderr */
@@ -112,7 +112,8 @@ typedef struct kkt_factor_info {
 
 typedef struct kkt_solve_info {
   int32_t ir_steps;      /* refinement corrections applied */
-  double residual;       /* ||rhs - K x||_inf / ||rhs||_inf after the solve */
+  double residual;       /* backward error ||rhs - K x||_inf /
+                            (max_i K_ii ||x||_inf + ||rhs||_inf) */
   int32_t fallback;      /* 0 none, 1 FP64 refactor */
   double ms;
 } kkt_solve_info;
@@ -131,7 +132,7 @@ typedef struct ipm_result {
   int32_t ir_steps;       /* refinement corrections over the solve */
   int32_t fp64_refactors; /* FP32 form: refactorisations in FP64 */
   int32_t inertia_corrections;
-  double max_ir_residual; /* worst relative KKT residual after refinement */
+  double max_ir_residual; /* worst backward error of the KKT solves */
 } ipm_result;
 
 typedef struct ipm_handle ipm_handle;

@@ -57,11 +57,12 @@ struct ipm_handle {
   bool ws_ready = false;
   struct Off {
     size_t c, b, q4, xl, xu, jp, jc, ja, jw, jtp, jtr, jte, hp, hc, hq, hdiag, hsp, hsc, hss;
-    size_t kmrow, kmc, kmh, kmtp, kmtk, kmta, kmtb, kmpos, ksp, ksc, kss, kval;
-    size_t sfirst, sw, sh, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
+    size_t kmrow, kmc, kmh, kmtp, kmtk, kmta, kmtb, kmpos, ksp, ksc, kss, kval, kmkp, dscale;
+    size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
-    size_t panel, ubuf, inv, bad, partials, xperm, uvec;
-    size_t vec[48];
+    size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
+    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part;
+    size_t vec[49];
   } o{};
   DevProblem dp{};
   DevPlan dpl64{}, dpl32{};
@@ -74,9 +75,16 @@ struct ipm_handle {
   double* xperm = nullptr;
   double* uvec = nullptr;
   double* kval = nullptr;
+  double* dscale = nullptr;     // symmetric scaling of the FP32 factor
+  double* ysol = nullptr;       // forward/backward solution (permuted)
+  double* part = nullptr;       // backward partial sums
+  bool scaled = false;          // current factor is of D K D
+  double kmax = 1.0;            // max diagonal of K (norm estimate)
+  double shift = 0.0;           // diagonal shift of the scaled FP32 factor
+  int64_t bad_diag_col = -1;    // permuted column of a non-positive diagonal
   IpmVecs v{}, tv{};
   double *dxa, *dsa, *dla, *dzla, *dzua, *dx, *ds, *dl, *dzl, *dzu, *ts, *tl, *tu, *rhs, *ir_r, *ir_c,
-      *ir_kx, *xhat, *lamhat;
+      *ir_kx, *xhat, *lamhat, *cg_p;
   // factor state
   int assembled_prec = -1, factor_prec = -1;
   bool values_set = false, factored = false;
@@ -148,15 +156,26 @@ void layout(ipm_handle* h) {
   }
   o.kmrow = r.take(bytes_of(h->km.krow)); o.kmc = r.take(bytes_of(h->km.kc)); o.kmpos = r.take(bytes_of(h->km.pos));
   o.kval = r.take(h->km.kc.size() * 8);
+  o.kmkp = r.take(bytes_of(h->km.kp));
+  o.dscale = r.take(n * 8);
   const Plan& P = h->plan64;
   o.sfirst = r.take(bytes_of(P.sfirst)); o.sw = r.take(bytes_of(P.sw)); o.sh = r.take(bytes_of(P.sh));
+  o.sld = r.take(bytes_of(P.sld));
   o.cptr = r.take(bytes_of(P.child_ptr)); o.child = r.take(bytes_of(P.child)); o.rel = r.take(bytes_of(P.rel));
   o.lsn = r.take(bytes_of(P.level_sn)); o.snrows = r.take(bytes_of(h->sym.sn_rows));
   o.perm = r.take(bytes_of(h->sym.perm)); o.spanel = r.take(bytes_of(P.spanel)); o.su = r.take(bytes_of(P.su));
   o.srow = r.take(bytes_of(P.srow)); o.suv = r.take(bytes_of(P.suv));
   o.ext = r.take(bytes_of(P.ext)); o.small = r.take(bytes_of(P.small));
-  if (h->need64) { o.gemm64 = r.take(bytes_of(h->plan64.gemm)); o.potrf64 = r.take(bytes_of(h->plan64.potrf)); }
-  if (h->need32) { o.gemm32 = r.take(bytes_of(h->plan32.gemm)); o.potrf32 = r.take(bytes_of(h->plan32.potrf)); }
+  if (h->need64) {
+    o.gemm64 = r.take(bytes_of(h->plan64.gemm)); o.potrf64 = r.take(bytes_of(h->plan64.potrf));
+    o.sdesc64 = r.take(bytes_of(h->plan64.sdesc)); o.ssmall64 = r.take(bytes_of(h->plan64.ssmall));
+    o.slarge64 = r.take(bytes_of(h->plan64.slarge));
+  }
+  if (h->need32) {
+    o.gemm32 = r.take(bytes_of(h->plan32.gemm)); o.potrf32 = r.take(bytes_of(h->plan32.potrf));
+    o.sdesc32 = r.take(bytes_of(h->plan32.sdesc)); o.ssmall32 = r.take(bytes_of(h->plan32.ssmall));
+    o.slarge32 = r.take(bytes_of(h->plan32.slarge));
+  }
   const size_t es = h->need64 ? 8 : 4;
   o.panel = r.take((size_t)P.panel_elems * es);
   o.ubuf = r.take((size_t)std::max<int64_t>(1, P.u_elems) * es);
@@ -167,10 +186,12 @@ void layout(ipm_handle* h) {
   o.partials = r.take((8 * RED_BLOCKS + 16) * sizeof(double));
   o.xperm = r.take(n * 8);
   o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
+  o.ysol = r.take(n * 8);
+  o.part = r.take((size_t)std::max(h->need64 ? h->plan64.part_elems : 1, h->need32 ? h->plan32.part_elems : 1) * 8);
   // vectors: 0..47 (n or m sized)
   const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
-  const int64_t sizes[48] = {
+  const int64_t sizes[49] = {
       nv, mv, mv, nv, nv,          // 0 x, 1 s, 2 lam, 3 zl, 4 zu
       nv, nv, mv, jn, hn,          // 5 gf, 6 qx, 7 g, 8 jv, 9 hv
       nv, mv, mv, nv,              // 10 rd, 11 rp, 12 sig_s, 13 sig_x
@@ -180,8 +201,9 @@ void layout(ipm_handle* h) {
       nv, mv, mv, nv, nv,          // 29..33 affine dx, ds, dlam, dzl, dzu
       nv, mv, mv, nv, nv,          // 34..38 dx, ds, dlam, dzl, dzu
       mv, nv, nv, nv,              // 39 ts, 40 tl, 41 tu, 42 rhs
-      nv, nv, nv, nv, mv};         // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
-  for (int i = 0; i < 48; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+      nv, nv, nv, nv, mv,          // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
+      nv};                         // 48 cg direction
+  for (int i = 0; i < 49; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
   h->ws_need = r.off;
 }
 
@@ -207,13 +229,19 @@ int bind_workspace(ipm_handle* h) {
   } else {
     UP(ksp, h->ksp); UP(ksc, h->ksc); UP(kss, h->kss);
   }
-  UP(kmrow, h->km.krow); UP(kmc, h->km.kc); UP(kmpos, h->km.pos);
+  UP(kmrow, h->km.krow); UP(kmc, h->km.kc); UP(kmpos, h->km.pos); UP(kmkp, h->km.kp);
   const Plan& P = h->plan64;
-  UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(cptr, P.child_ptr); UP(child, P.child);
+  UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(sld, P.sld); UP(cptr, P.child_ptr); UP(child, P.child);
   UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
   UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv); UP(ext, P.ext); UP(small, P.small);
-  if (h->need64) { UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); }
-  if (h->need32) { UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); }
+  if (h->need64) {
+    UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc);
+    UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge);
+  }
+  if (h->need32) {
+    UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc);
+    UP(ssmall32, h->plan32.ssmall); UP(slarge32, h->plan32.slarge);
+  }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   // device views
   DevProblem& d = h->dp;
@@ -239,18 +267,25 @@ int bind_workspace(ipm_handle* h) {
     const Plan& PP = prec == 0 ? h->plan64 : h->plan32;
     q.ns = PP.ns; q.n = PP.n; q.nb = PP.nb; q.small_h = PP.small_h;
     q.sfirst = at<int32_t>(h, o.sfirst); q.sw = at<int32_t>(h, o.sw); q.sh = at<int32_t>(h, o.sh);
+    q.sld = at<int32_t>(h, o.sld);
     q.child_ptr = at<int32_t>(h, o.cptr); q.child = at<int32_t>(h, o.child); q.rel = at<int32_t>(h, o.rel);
     q.level_sn = at<int32_t>(h, o.lsn); q.sn_rows = at<int32_t>(h, o.snrows); q.perm = at<int32_t>(h, o.perm);
     q.spanel = at<int64_t>(h, o.spanel); q.su = at<int64_t>(h, o.su); q.srow = at<int64_t>(h, o.srow);
     q.suv = at<int64_t>(h, o.suv); q.ext = at<ExtAddDesc>(h, o.ext); q.small = at<int32_t>(h, o.small);
     q.gemm = at<GemmDesc>(h, prec == 0 ? o.gemm64 : o.gemm32);
     q.potrf = at<PotrfDesc>(h, prec == 0 ? o.potrf64 : o.potrf32);
+    q.sdesc = at<SolveDesc>(h, prec == 0 ? o.sdesc64 : o.sdesc32);
+    q.ssmall = at<int32_t>(h, prec == 0 ? o.ssmall64 : o.ssmall32);
+    q.slarge = at<int32_t>(h, prec == 0 ? o.slarge64 : o.slarge32);
   }
   h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;
   h->bad = at<int>(h, o.bad); h->partials = at<double>(h, o.partials);
   h->xperm = at<double>(h, o.xperm); h->uvec = at<double>(h, o.uvec); h->kval = at<double>(h, o.kval);
-  double* V[48];
-  for (int i = 0; i < 48; ++i) V[i] = at<double>(h, o.vec[i]);
+  h->dscale = at<double>(h, o.dscale);
+  h->ysol = at<double>(h, o.ysol);
+  h->part = at<double>(h, o.part);
+  double* V[49];
+  for (int i = 0; i < 49; ++i) V[i] = at<double>(h, o.vec[i]);
   IpmVecs& v = h->v;
   v.x = V[0]; v.s = V[1]; v.lam = V[2]; v.zl = V[3]; v.zu = V[4]; v.gf = V[5]; v.qx = V[6]; v.g = V[7];
   v.jv = V[8]; v.hv = V[9]; v.rd = V[10]; v.rp = V[11]; v.sig_s = V[12]; v.sig_x = V[13];
@@ -263,6 +298,7 @@ int bind_workspace(ipm_handle* h) {
   h->dx = V[34]; h->ds = V[35]; h->dl = V[36]; h->dzl = V[37]; h->dzu = V[38];
   h->ts = V[39]; h->tl = V[40]; h->tu = V[41]; h->rhs = V[42];
   h->ir_r = V[43]; h->ir_c = V[44]; h->ir_kx = V[45]; h->xhat = V[46]; h->lamhat = V[47];
+  h->cg_p = V[48];
   h->ws_ready = true;
   h->assembled_prec = h->factor_prec = -1;
   h->factored = h->values_set = false;
@@ -314,20 +350,19 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
   const int prec = h->factor_prec;
   const Plan& P = prec == PDIPM_FP64 ? h->plan64 : h->plan32;
   const DevPlan& D = prec == PDIPM_FP64 ? h->dpl64 : h->dpl32;
-  launch_permute_in(D, rhs, h->xperm, h->stream);
-  for (int l = 0; l < P.nlevels; ++l) {
-    if (prec == PDIPM_FP64)
-      launch_fwd_level<double>(D, P.level_ptr[l], P.level_ptr[l + 1], (const double*)h->panel, h->xperm, h->uvec, h->stream);
-    else
-      launch_fwd_level<float>(D, P.level_ptr[l], P.level_ptr[l + 1], (const float*)h->panel, h->xperm, h->uvec, h->stream);
+  const double* d = h->scaled ? h->dscale : nullptr;
+  launch_permute_in(D, rhs, d, h->xperm, h->stream);
+  for (const std::vector<Op>* ops : {&P.fwd_ops, &P.bwd_ops}) {
+    for (const Op& op : *ops) {
+      if (prec == PDIPM_FP64)
+        launch_solve_op<double>(op, D, (const double*)h->panel, (const double*)h->inv, h->xperm, h->ysol,
+                                h->uvec, h->part, h->stream);
+      else
+        launch_solve_op<float>(op, D, (const float*)h->panel, (const float*)h->inv, h->xperm, h->ysol,
+                               h->uvec, h->part, h->stream);
+    }
   }
-  for (int l = P.nlevels - 1; l >= 0; --l) {
-    if (prec == PDIPM_FP64)
-      launch_bwd_level<double>(D, P.level_ptr[l], P.level_ptr[l + 1], (const double*)h->panel, h->xperm, h->stream);
-    else
-      launch_bwd_level<float>(D, P.level_ptr[l], P.level_ptr[l + 1], (const float*)h->panel, h->xperm, h->stream);
-  }
-  launch_permute_out(D, h->xperm, out, h->stream);
+  launch_permute_out(D, h->ysol, d, out, h->stream);
 }
 
 void kmul(ipm_handle* h, const double* x, double* out) {
@@ -339,50 +374,130 @@ void kmul(ipm_handle* h, const double* x, double* out) {
                       h->v.tmp_n2, h->stream);
 }
 
-// Solve with the current factor; FP64 refinement when the factor is FP32.
+// Solve with the current factor; with an FP32 factor, FP64 refinement:
+// plain iterative refinement while the backward error
+// ||r|| / (kmax ||x|| + ||b||) halves each step, then preconditioned
+// conjugate gradients on K (SPD) with the FP32 factor as preconditioner.
 int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info* info) {
   const int64_t n = h->sym.n;
   trisolve(h, rhs, out);
   int steps = 0;
-  double rel = 0;
+  double omega = 0, nb = 0;
   const bool refine = h->factor_prec == PDIPM_FP32;
-  if (refine || info) {
-    double prev = INFINITY;
-    for (int it = 0;; ++it) {
-      kmul(h, out, h->ir_kx);
-      launch_residual_norms(n, rhs, h->ir_kx, h->ir_r, h->partials, h->stream);
+  double prev = INFINITY;
+  for (int it = 0;; ++it) {
+    kmul(h, out, h->ir_kx);
+    launch_residual_norms(n, rhs, h->ir_kx, out, h->ir_r, h->partials, h->stream);
+    double nr[3];
+    int rc = read_back(h, red_out(h), nr, 3);
+    if (rc) return rc;
+    nb = nr[1];
+    omega = nr[0] / (h->kmax * nr[2] + nb + 1e-300);
+    if (!refine || omega <= h->opt.ir_tol || it >= h->opt.ir_max || !(omega < 0.5 * prev)) break;
+    prev = omega;
+    trisolve(h, h->ir_r, h->ir_c);
+    launch_add(n, out, h->ir_c, h->stream);
+    ++steps;
+  }
+  int cg = 0;
+  if (refine && omega > h->opt.ir_tol && std::isfinite(omega)) {
+    // PCG from the refined point; ir_r holds its residual
+    double* r = h->ir_r; double* z = h->ir_c; double* q = h->ir_kx; double* p = h->cg_p;
+    trisolve(h, r, z);
+    launch_copy(n, p, z, h->stream);
+    launch_dot(n, r, z, h->partials, h->stream);
+    double rho;
+    int rc = read_back(h, red_out(h), &rho, 1);
+    if (rc) return rc;
+    const int max_cg = 4 * std::max(1, h->opt.ir_max);
+    for (cg = 0; cg < max_cg && rho > 0; ++cg) {
+      kmul(h, p, q);
+      launch_dot(n, p, q, h->partials, h->stream);
+      double pq;
+      if ((rc = read_back(h, red_out(h), &pq, 1))) return rc;
+      if (!(pq > 0)) break;
+      const double alpha = rho / pq;
+      launch_cg_step(n, alpha, p, q, out, r, h->partials, h->stream);
       double nr[2];
-      int rc = read_back(h, red_out(h), nr, 2);
-      if (rc) return rc;
-      rel = nr[1] > 0 ? nr[0] / nr[1] : nr[0];
-      if (!refine || rel <= h->opt.ir_tol || it >= h->opt.ir_max || !(rel < 0.5 * prev)) break;
-      prev = rel;
-      trisolve(h, h->ir_r, h->ir_c);
-      launch_add(n, out, h->ir_c, h->stream);
-      ++steps;
+      if ((rc = read_back(h, red_out(h), nr, 2))) return rc;
+      omega = nr[0] / (h->kmax * nr[1] + nb + 1e-300);
+      if (omega <= h->opt.ir_tol || !std::isfinite(omega)) { ++cg; break; }
+      trisolve(h, r, z);
+      launch_dot(n, r, z, h->partials, h->stream);
+      double rho2;
+      if ((rc = read_back(h, red_out(h), &rho2, 1))) return rc;
+      launch_xpby(n, z, rho2 / rho, p, h->stream);
+      rho = rho2;
     }
   }
-  if (info) { info->ir_steps = steps; info->residual = rel; info->fallback = 0; }
-  if (!std::isfinite(rel)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
+  if (info) { info->ir_steps = steps + cg; info->residual = omega; info->fallback = 0; }
+  if (!std::isfinite(omega)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
   return PDIPM_OK;
 }
 
-template <typename T>
-void assemble_into(ipm_handle* h, double delta_p) {
-  const size_t es = sizeof(T);
-  launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
-  launch_assemble<T>(h->dk, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, (T*)h->panel, h->kval, h->stream);
+// K values (FP64, K pattern order) for the point held in the vectors.
+void assemble_values(ipm_handle* h, double delta_p) {
+  launch_assemble<double>(h->dk, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, nullptr, h->kval, h->stream);
+  h->cur_delta_p = delta_p;
 }
 
-int assemble(ipm_handle* h, int prec, double delta_p) {
+// Load the panels from the K values: FP64 as is; FP32 as D K D + shift I with
+// D = diag(K)^(-1/2).  Returns NOT_PD when a diagonal entry is not positive.
+int load_panels(ipm_handle* h, int prec, double shift) {
   if (prec == PDIPM_FP64 && !h->need64) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace has no FP64 factor space");
   if (prec == PDIPM_FP32 && !h->need32) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace has no FP32 plan");
-  if (prec == PDIPM_FP64) assemble_into<double>(h, delta_p);
-  else assemble_into<float>(h, delta_p);
-  h->cur_delta_p = delta_p;
+  const size_t es = prec == PDIPM_FP64 ? 8 : 4;
+  launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
+  launch_diag_scale(h->sym.n, at<int64_t>(h, h->o.kmkp), h->kval, h->dscale, h->partials, h->stream);
+  double dd[3];
+  int rc = read_back(h, red_out(h), dd, 3);
+  if (rc) return rc;
+  h->kmax = dd[0] > 0 ? dd[0] : 1.0;
+  if (dd[1] > 0) {
+    h->factored = false;
+    h->bad_diag_col = h->sym.pinv[(int64_t)dd[2]];
+    return fail(h, PDIPM_ERR_NOT_PD, "non-positive diagonal entry of K at permuted column " +
+                                         std::to_string(h->bad_diag_col));
+  }
+  if (prec == PDIPM_FP64) {
+    launch_set_values<double>(h->dk, h->kval, (double*)h->panel, h->stream);
+    h->scaled = false;
+  } else {
+    launch_set_scaled<float>(h->dk, h->kval, h->dscale, shift, (float*)h->panel, h->stream);
+    h->scaled = true;
+  }
+  h->shift = shift;
   h->assembled_prec = prec;
   h->factored = false;
   return PDIPM_OK;
+}
+
+// Factor K in the requested precision.  FP32: on a non-positive pivot the
+// scaled factor is retried with diagonal shifts 1e-7, 1e-6, ... 1e-3 (the
+// shifted factor only preconditions refinement against the true K).
+int factor_k(ipm_handle* h, int prec, kkt_factor_info* fi, double* ms_acc, int* shifts) {
+  double shift = 0.0;
+  for (int attempt = 0;; ++attempt) {
+    int rc = load_panels(h, prec, shift);
+    if (rc == PDIPM_ERR_NOT_PD && fi) {
+      fi->status = rc;
+      fi->first_bad_col = h->bad_diag_col;
+      fi->ms = 0;
+      fi->flops = h->sym.flops;
+    }
+    if (rc) return rc;
+    rc = factor_now(h, prec, fi);
+    if (ms_acc) *ms_acc += fi->ms;
+    if (rc != PDIPM_ERR_NOT_PD || prec == PDIPM_FP64) return rc;
+    if (attempt >= 5) return rc;
+    shift = shift == 0.0 ? 1e-7 : shift * 10.0;
+    if (shifts) ++*shifts;
+  }
+}
+
+int assemble(ipm_handle* h, int prec, double delta_p) {
+  assemble_values(h, delta_p);
+  return load_panels(h, prec, 0.0);
 }
 
 int check_ready(ipm_handle* h) {
@@ -462,25 +577,29 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     if (it >= O.max_iter) { status = PDIPM_MAX_ITER; break; }
     if (ms_since(t_start) > O.max_wall_time * 1e3) { status = PDIPM_TIME_LIMIT; break; }
     launch_sigmas(P, v, O.delta_d, h->stream);
-    // assemble + factor, with inertia correction on a non-positive pivot
+    // assemble + factor.  FP32: scaled factor with shift retries, then an
+    // FP64 refactor when allowed; a non-positive pivot in FP64 triggers the
+    // inertia correction (delta_w added to the diagonal of K).
     int fprec = prec;
     double delta_w = 0.0;
     auto ta = clk::now();
-    rc = assemble(h, fprec, O.delta_p);
-    if (rc) return rc;
+    assemble_values(h, O.delta_p);
     HIPCHK(h, hipStreamSynchronize(h->stream));
     R.ms_assemble += ms_since(ta);
     kkt_factor_info fi{};
-    rc = factor_now(h, fprec, &fi);
-    R.ms_factor += fi.ms;
+    int shifts = 0;
+    rc = factor_k(h, fprec, &fi, &R.ms_factor, &shifts);
+    if (rc == PDIPM_ERR_NOT_PD && fprec == PDIPM_FP32 && h->need64) {
+      fprec = PDIPM_FP64;
+      R.fp64_refactors++;
+      rc = factor_k(h, fprec, &fi, &R.ms_factor, nullptr);
+    }
     if (rc == PDIPM_ERR_NOT_PD) {
       delta_w = delta_w_last == 0.0 ? 1e-4 : std::max(1e-20, delta_w_last / 3.0);
       const bool first = delta_w_last == 0.0;
       while (true) {
-        rc = assemble(h, fprec, O.delta_p + delta_w);
-        if (rc) return rc;
-        rc = factor_now(h, fprec, &fi);
-        R.ms_factor += fi.ms;
+        assemble_values(h, O.delta_p + delta_w);
+        rc = factor_k(h, fprec, &fi, &R.ms_factor, nullptr);
         if (rc == PDIPM_OK) { delta_w_last = delta_w; break; }
         if (rc != PDIPM_ERR_NOT_PD) return rc;
         delta_w *= first ? 100.0 : 8.0;
@@ -498,6 +617,15 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
       launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
       int r2 = solve_refined(h, h->rhs, dx, &si);
       if (r2) return r2;
+      if (h->factor_prec == PDIPM_FP32 && si.residual > 1e-10 && h->need64) {
+        // refinement stalled: refactor in FP64 for the rest of the iteration
+        kkt_factor_info f64{};
+        r2 = factor_k(h, PDIPM_FP64, &f64, &R.ms_factor, nullptr);
+        if (r2) return r2;
+        R.fp64_refactors++;
+        r2 = solve_refined(h, h->rhs, dx, &si);
+        if (r2) return r2;
+      }
       R.ir_steps += si.ir_steps;
       R.max_ir_residual = std::max(R.max_ir_residual, si.residual);
       launch_recover(P, v, dx, tsv, tlv, tuv, O.delta_d, ds, dl, dzl, dzu, h->stream);
@@ -522,6 +650,9 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     launch_step_limits(P, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->partials, h->stream);
     if ((rc = read_back(h, red_out(h), lim, 2))) return rc;
     R.ms_solve += ms_since(ts0);
+    if (O.print_level > 1)
+      fprintf(stderr, "    solve: ir %d omega %.2e shifts %d fp64 %d delta_w %.1e kmax %.2e sigma %.2e\n",
+              si.ir_steps, si.residual, shifts, R.fp64_refactors, delta_w, h->kmax, sigma);
     const double tau = std::max(0.99, 1.0 - mu);
     double ap = std::min(1.0, tau * lim[0]), ad = std::min(1.0, tau * lim[1]);
     if (kind != KIND_LP) ap = ad = std::min(ap, ad);
@@ -571,7 +702,7 @@ void ipm_default_options(ipm_options* o) {
   o->delta_d = 1e-8;
   o->precision = PDIPM_FP64;
   o->ir_max = 10;
-  o->ir_tol = 1e-12;
+  o->ir_tol = 1e-14;
   o->nd_leaf = 64;
   o->amalg_menu = 0;
   o->print_level = 0;
@@ -667,7 +798,8 @@ int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* s) {
   s->n = h->sym.n;
   s->nnz_K = (int64_t)h->km.kc.size();
   s->nnz_L = h->sym.nnz_L;
-  s->nnz_L_stored = h->plan64.panel_elems;
+  s->nnz_L_stored = 0;
+  for (int64_t k = 0; k < h->plan64.ns; ++k) s->nnz_L_stored += (int64_t)h->plan64.sh[k] * h->plan64.sw[k];
   s->n_super = h->sym.nsuper();
   s->max_front = h->plan64.max_front;
   s->n_levels = h->plan64.nlevels;
@@ -730,6 +862,7 @@ int kkt_set_values(ipm_handle* h, const double* d_kval) {
   HIPCHK(h, hipMemcpyAsync(h->kval, d_kval, h->km.kc.size() * 8, hipMemcpyDeviceToDevice, h->stream));
   h->values_set = true;
   h->factored = false;
+  h->cur_delta_p = 0.0;
   return PDIPM_OK;
 }
 
@@ -766,31 +899,47 @@ int kkt_factor(ipm_handle* h, int prec, kkt_factor_info* info) {
   if (prec != PDIPM_FP64 && prec != PDIPM_FP32) return fail(h, PDIPM_ERR_INVALID_ARG, "bad precision");
   if ((prec == PDIPM_FP64 && !h->need64) || (prec == PDIPM_FP32 && !h->need32))
     return fail(h, PDIPM_ERR_INVALID_ARG, "the workspace was not sized for this precision");
-  if (h->standalone) {
-    if (!h->values_set) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no K values set");
-    const size_t es = prec == PDIPM_FP64 ? 8 : 4;
-    launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
-    if (prec == PDIPM_FP64) launch_set_values<double>(h->dk, h->kval, (double*)h->panel, h->stream);
-    else launch_set_values<float>(h->dk, h->kval, (float*)h->panel, h->stream);
-  } else if (h->assembled_prec != prec) {
-    return fail(h, PDIPM_ERR_INVALID_ARG, "assemble K in this precision first (kkt_assemble)");
-  }
-  return factor_now(h, prec, info);
+  if (h->standalone ? !h->values_set : h->assembled_prec < 0)
+    return fail(h, PDIPM_ERR_NOT_ANALYZED, "no K values (kkt_set_values / kkt_assemble)");
+  kkt_factor_info fi{};
+  rc = factor_k(h, prec, &fi, nullptr, nullptr);
+  if (rc == PDIPM_ERR_NOT_PD && fi.first_bad_col < 0) fi.status = PDIPM_ERR_NOT_PD;
+  if (info) *info = fi;
+  return rc;
 }
 
 int kkt_get_factor(ipm_handle* h, double* out) {
   int rc = check_ready(h);
   if (rc) return rc;
   if (h->factor_prec < 0) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no factor");
-  const int64_t ne = h->plan64.panel_elems;
+  const Plan& P = h->plan64;
+  const int64_t ne = P.panel_elems;
+  std::vector<double> pan(ne);
   if (h->factor_prec == PDIPM_FP64) {
-    HIPCHK(h, hipMemcpyAsync(out, h->panel, ne * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(pan.data(), h->panel, ne * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
   } else {
     std::vector<float> tmp(ne);
     HIPCHK(h, hipMemcpyAsync(tmp.data(), h->panel, ne * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int64_t i = 0; i < ne; ++i) out[i] = tmp[i];
+    for (int64_t i = 0; i < ne; ++i) pan[i] = tmp[i];
+  }
+  std::vector<double> d;
+  if (h->scaled) {
+    // the device factor is of D P'KP D: row k of L is divided by d[perm[k]]
+    d.resize(h->sym.n);
+    HIPCHK(h, hipMemcpyAsync(d.data(), h->dscale, d.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  int64_t o = 0;
+  for (int64_t k = 0; k < P.ns; ++k) {
+    const int32_t* rows = h->sym.sn_rows.data() + h->sym.sn_rowptr[k];
+    for (int32_t c = 0; c < P.sw[k]; ++c)
+      for (int32_t r = 0; r < P.sh[k]; ++r) {
+        double v = pan[P.spanel[k] + (int64_t)c * P.sld[k] + r];
+        if (h->scaled) v /= d[h->sym.perm[rows[r]]];
+        out[o++] = v;
+      }
   }
   return PDIPM_OK;
 }

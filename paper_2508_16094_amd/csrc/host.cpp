@@ -277,13 +277,14 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
   const int64_t ns = s.nsuper();
   P.ns = ns;
   P.n = s.n;
-  P.sfirst.resize(ns); P.sw.resize(ns); P.sh.resize(ns); P.sparent.assign(ns, -1);
+  P.sfirst.resize(ns); P.sw.resize(ns); P.sh.resize(ns); P.sld.resize(ns); P.sparent.assign(ns, -1);
   P.slevel.assign(ns, 0); P.spanel.resize(ns); P.su.resize(ns); P.srow.resize(ns + 1); P.suv.resize(ns);
   std::vector<int32_t> col2sn(s.n);
   for (int64_t k = 0; k < ns; ++k) {
     P.sfirst[k] = s.sn_start[k];
     P.sw[k] = s.sn_start[k + 1] - s.sn_start[k];
     P.sh[k] = (int32_t)(s.sn_rowptr[k + 1] - s.sn_rowptr[k]);
+    P.sld[k] = (P.sh[k] + 3) & ~3;
     P.srow[k] = s.sn_rowptr[k];
     for (int32_t j = s.sn_start[k]; j < s.sn_start[k + 1]; ++j) col2sn[j] = (int32_t)k;
   }
@@ -291,7 +292,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
   int64_t off = 0, uoff = 0, uvoff = 0;
   for (int64_t k = 0; k < ns; ++k) {
     P.spanel[k] = off;
-    off += (int64_t)P.sh[k] * P.sw[k];
+    off += (int64_t)P.sld[k] * P.sw[k];
     int64_t hu = P.sh[k] - P.sw[k];
     P.su[k] = uoff;
     uoff += hu * hu;
@@ -343,9 +344,17 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       P.rel[e] = (int32_t)q;
     }
   }
-  // launch schedule, level by level
+  // permanent storage of the inverses of the diagonal blocks (large fronts)
   const int nb = P.nb;
-  int64_t max_inv_fronts = 0;
+  P.sinv.assign(ns, -1);
+  int64_t ioff = 0;
+  for (int64_t k = 0; k < ns; ++k) {
+    if (P.sh[k] <= P.small_h) continue;
+    P.sinv[k] = ioff;
+    ioff += (int64_t)((P.sw[k] + nb - 1) / nb) * nb * nb;
+  }
+  P.inv_elems = std::max<int64_t>(1, ioff);
+  // launch schedule, level by level
   for (int l = 0; l < P.nlevels; ++l) {
     std::vector<int32_t> large;
     int64_t small_begin = (int64_t)P.small.size();
@@ -372,23 +381,21 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
     const int tm = esize == 8 ? 64 : 128;  // gemm tile
     for (int32_t c0 = 0; c0 < maxw; c0 += nb) {
       int64_t pb = (int64_t)P.potrf.size();
-      int64_t slot = 0;
       std::vector<int64_t> slot_of(large.size(), -1);
       for (size_t q = 0; q < large.size(); ++q) {
         int32_t k = large[q];
         if (P.sw[k] <= c0) continue;
         int32_t bw = std::min(nb, P.sw[k] - c0);
         PotrfDesc d;
-        d.d_off = P.spanel[k] + (int64_t)c0 * P.sh[k] + c0;
-        d.inv_off = slot * (int64_t)nb * nb;
-        d.ld = P.sh[k];
+        d.d_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0;
+        d.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
+        d.ld = P.sld[k];
         d.bw = bw;
         d.col0 = P.sfirst[k] + c0;
         d.pad = 0;
-        slot_of[q] = slot++;
+        slot_of[q] = d.inv_off;
         P.potrf.push_back(d);
       }
-      max_inv_fronts = std::max(max_inv_fronts, slot);
       P.ops.push_back({OP_POTRF, pb, (int64_t)P.potrf.size(), (int64_t)P.potrf.size() - pb});
       // TRSM: rows below the diagonal block, in place, C = A * Dinv^T
       int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
@@ -399,10 +406,10 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
         int32_t M = P.sh[k] - c0 - bw;
         if (M <= 0) continue;
         GemmDesc g{};
-        g.c_off = P.spanel[k] + (int64_t)c0 * P.sh[k] + c0 + bw;
+        g.c_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0 + bw;
         g.a_off = g.c_off;
-        g.b_off = slot_of[q] * (int64_t)nb * nb;
-        g.ldc = P.sh[k]; g.lda = P.sh[k]; g.ldb = nb;
+        g.b_off = slot_of[q];
+        g.ldc = P.sld[k]; g.lda = P.sld[k]; g.ldb = nb;
         g.M = M; g.N = bw; g.K = bw;
         g.c_buf = 0; g.b_buf = 1; g.mode = 1; g.lower = 0;
         g.tiles_m = (M + tm - 1) / tm; g.tiles_n = 1;
@@ -417,15 +424,15 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       for (size_t q = 0; q < large.size(); ++q) {
         int32_t k = large[q];
         if (slot_of[q] < 0) continue;
-        int32_t h = P.sh[k], w = P.sw[k];
+        int32_t h = P.sh[k], w = P.sw[k], ld = P.sld[k];
         int32_t bw = std::min(nb, w - c0);
         int32_t r0 = c0 + bw;
         if (w - r0 > 0) {
           GemmDesc g{};
-          g.c_off = P.spanel[k] + (int64_t)r0 * h + r0;
-          g.a_off = P.spanel[k] + (int64_t)c0 * h + r0;
+          g.c_off = P.spanel[k] + (int64_t)r0 * ld + r0;
+          g.a_off = P.spanel[k] + (int64_t)c0 * ld + r0;
           g.b_off = g.a_off;
-          g.ldc = h; g.lda = h; g.ldb = h;
+          g.ldc = ld; g.lda = ld; g.ldb = ld;
           g.M = h - r0; g.N = w - r0; g.K = bw;
           g.c_buf = 0; g.b_buf = 0; g.mode = 0; g.lower = 1;
           g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
@@ -436,9 +443,9 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
         if (h - w > 0) {
           GemmDesc g{};
           g.c_off = P.su[k];
-          g.a_off = P.spanel[k] + (int64_t)c0 * h + w;
+          g.a_off = P.spanel[k] + (int64_t)c0 * ld + w;
           g.b_off = g.a_off;
-          g.ldc = h - w; g.lda = h; g.ldb = h;
+          g.ldc = h - w; g.lda = ld; g.ldb = ld;
           g.M = h - w; g.N = h - w; g.K = bw;
           g.c_buf = 1; g.b_buf = 0; g.mode = 0; g.lower = 1;
           g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
@@ -450,7 +457,93 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
     }
   }
-  P.inv_elems = std::max<int64_t>(1, max_inv_fronts) * nb * nb;
+  // ---- triangular solve schedule (same levels; large fronts blocked by nb)
+  const int RB = 256;  // rows per work item
+  int64_t max_parts = 1;
+  for (int l = 0; l < P.nlevels; ++l) {
+    std::vector<int32_t> large;
+    int64_t sb = (int64_t)P.ssmall.size();
+    for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+      int32_t k = P.level_sn[q];
+      if (P.sh[k] <= P.small_h) P.ssmall.push_back(k);
+      else large.push_back(k);
+    }
+    if ((int64_t)P.ssmall.size() > sb)
+      P.fwd_ops.push_back({OP_FWD_SMALL, sb, (int64_t)P.ssmall.size(), (int64_t)P.ssmall.size() - sb});
+    if (large.empty()) continue;
+    int64_t gb = (int64_t)P.slarge.size();
+    for (int32_t k : large) P.slarge.push_back(k);
+    P.fwd_ops.push_back({OP_FWD_GATHER, gb, (int64_t)P.slarge.size(), (int64_t)large.size()});
+    int32_t maxw = 0;
+    for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
+    for (int32_t c0 = 0; c0 < maxw; c0 += nb) {
+      int64_t db = (int64_t)P.sdesc.size();
+      for (int32_t k : large) {
+        if (P.sw[k] <= c0) continue;
+        int32_t bw = std::min(nb, P.sw[k] - c0);
+        int64_t inv = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
+        int32_t rbeg = c0 + bw;
+        bool first = true;
+        for (int32_t r0 = rbeg; r0 < P.sh[k] || first; r0 += RB) {
+          SolveDesc d{};
+          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = std::min(r0, P.sh[k]);
+          d.r1 = std::min(r0 + RB, P.sh[k]); d.owner = first ? 1 : 0; d.inv_off = inv;
+          P.sdesc.push_back(d);
+          first = false;
+          if (r0 >= P.sh[k]) break;
+        }
+      }
+      P.fwd_ops.push_back({OP_FWD_STEP, db, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - db});
+    }
+  }
+  // backward: levels from the root down; large fronts from their last block
+  for (int l = P.nlevels - 1; l >= 0; --l) {
+    std::vector<int32_t> large;
+    int64_t sb = (int64_t)P.ssmall.size();
+    for (int32_t q = P.level_ptr[l]; q < P.level_ptr[l + 1]; ++q) {
+      int32_t k = P.level_sn[q];
+      if (P.sh[k] <= P.small_h) P.ssmall.push_back(k);
+      else large.push_back(k);
+    }
+    if ((int64_t)P.ssmall.size() > sb)
+      P.bwd_ops.push_back({OP_BWD_SMALL, sb, (int64_t)P.ssmall.size(), (int64_t)P.ssmall.size() - sb});
+    if (large.empty()) continue;
+    int32_t maxw = 0;
+    for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
+    const int32_t nsteps = (maxw + nb - 1) / nb;
+    for (int32_t step = nsteps - 1; step >= 0; --step) {
+      const int32_t c0 = step * nb;
+      int64_t pb = (int64_t)P.sdesc.size();
+      int64_t part = 0;
+      std::vector<SolveDesc> diag;
+      for (int32_t k : large) {
+        if (P.sw[k] <= c0) continue;
+        int32_t bw = std::min(nb, P.sw[k] - c0);
+        SolveDesc dd{};
+        dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.r0 = dd.r1 = 0; dd.owner = 1;
+        dd.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
+        dd.part_off = part;
+        int32_t np = 0;
+        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RB) {
+          SolveDesc d{};
+          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RB, P.sh[k]);
+          d.part_off = part;
+          part += nb;
+          ++np;
+          P.sdesc.push_back(d);
+        }
+        dd.nparts = np;
+        diag.push_back(dd);
+      }
+      max_parts = std::max(max_parts, part);
+      if ((int64_t)P.sdesc.size() > pb)
+        P.bwd_ops.push_back({OP_BWD_PART, pb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - pb});
+      int64_t qb = (int64_t)P.sdesc.size();
+      for (auto& d : diag) P.sdesc.push_back(d);
+      P.bwd_ops.push_back({OP_BWD_DIAG, qb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - qb});
+    }
+  }
+  P.part_elems = max_parts;
 }
 
 void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {
@@ -467,7 +560,7 @@ void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {
     int64_t h = s.sn_rowptr[k + 1] - s.sn_rowptr[k];
     const int32_t* it = std::lower_bound(rows, rows + h, r);
     if (it == rows + h || *it != r) throw std::runtime_error("K entry outside the factor structure");
-    km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sh[k] + (it - rows);
+    km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sld[k] + (it - rows);
   }
 }
 

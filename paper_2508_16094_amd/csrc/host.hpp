@@ -73,7 +73,20 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
   int32_t sn, t0, t1, pad;
 };
 
-enum OpType { OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE };
+// Blocked triangular-solve work item: rows [r0, r1) of supernode sn against
+// its column block [c0, c0 + bw).
+struct SolveDesc {
+  int32_t sn, c0, bw, r0, r1, owner;
+  int64_t inv_off;         // inverse of the diagonal block (ld = nb)
+  int64_t part_off;        // backward partial sums of this item (bw values)
+  int32_t nparts, pad;     // backward diagonal item: number of partial items
+};
+
+enum OpType {
+  OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE,   // factorisation
+  OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_STEP,                      // forward solve
+  OP_BWD_SMALL, OP_BWD_PART, OP_BWD_DIAG                         // backward solve
+};
 
 struct Op {
   int type;
@@ -86,7 +99,7 @@ struct Plan {
   int nb = 64;             // panel block width of the blocked path
   int small_h = 64;        // fronts with h <= small_h use the one-workgroup path
   int esize = 8;           // bytes per panel element (8 FP64, 4 FP32)
-  std::vector<int32_t> sfirst, sw, sh, sparent, slevel;
+  std::vector<int32_t> sfirst, sw, sh, sld, sparent, slevel;  // sld: panel leading dim (h rounded up to 4)
   std::vector<int64_t> spanel, su, srow, suv;  // panel / U / row / update-vector offsets
   std::vector<int32_t> child_ptr, child;
   std::vector<int32_t> rel;           // parallel to sn_rows: row position in the parent
@@ -101,6 +114,13 @@ struct Plan {
   std::vector<ExtAddDesc> ext;
   std::vector<int32_t> small;
   double update_bytes = 0;
+  // permanent inverses of the diagonal blocks of large supernodes
+  std::vector<int64_t> sinv;          // -1 for small supernodes
+  // triangular solves
+  std::vector<Op> fwd_ops, bwd_ops;
+  std::vector<SolveDesc> sdesc;
+  std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
+  int64_t part_elems = 1;
 };
 
 std::string build_problem(const ::ipm_problem_desc* d, HostProblem* p);

@@ -164,7 +164,7 @@ __global__ void k_assemble(DevKMap K, const double* hv, const double* jv, const 
   int32_t r = K.krow[e];
   if (r == K.kc[e]) v += sig_x[r] + delta_p;
   for (int64_t t = K.tp[e]; t < K.tp[e + 1]; ++t) v += sig_s[K.tk[t]] * jv[K.ta[t]] * jv[K.tb[t]];
-  panel[K.pos[e]] = (T)v;
+  if (panel) panel[K.pos[e]] = (T)v;
   if (kval) kval[e] = v;
 }
 
@@ -172,6 +172,35 @@ template <typename T>
 __global__ void k_set_values(DevKMap K, const double* kval, T* panel) {
   int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e < K.nk) panel[K.pos[e]] = (T)kval[e];
+}
+
+// Symmetric scaling D = diag(K)^(-1/2): partials give max K_ii and the count
+// of non-positive diagonal entries.
+__global__ void k_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials) {
+  RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
+  double a[3] = {0.0, 0.0, INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double kii = kval[kp[i + 1] - 1];
+    if (kii > 0.0 && isfinite(kii)) {
+      d[i] = 1.0 / sqrt(kii);
+      a[0] = fmax(a[0], kii);
+    } else {
+      d[i] = 1.0;
+      a[1] += 1.0;
+      a[2] = fmin(a[2], (double)i);
+    }
+  }
+  block_reduce_store<3>(a, spec, partials);
+}
+
+template <typename T>
+__global__ void k_set_scaled(DevKMap K, const double* kval, const double* d, double shift, T* panel) {
+  int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (e >= K.nk) return;
+  const int32_t r = K.krow[e], c = K.kc[e];
+  double v = kval[e] * d[r] * d[c];
+  if (r == c) v += shift;
+  panel[K.pos[e]] = (T)v;
 }
 
 __global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc, const int64_t* kss,
@@ -192,11 +221,11 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
   constexpr int LD = 65;
   __shared__ T F[64 * LD];
   const int32_t S = P.small[d0 + blockIdx.x];
-  const int h = P.sh[S], w = P.sw[S];
+  const int h = P.sh[S], w = P.sw[S], ld = P.sld[S];
   const int64_t poff = P.spanel[S];
   for (int idx = threadIdx.x; idx < h * h; idx += BS) {
     int i = idx % h, j = idx / h;
-    F[i + j * LD] = (j < w && i >= j) ? panel[poff + i + (int64_t)j * h] : (T)0;
+    F[i + j * LD] = (j < w && i >= j) ? panel[poff + i + (int64_t)j * ld] : (T)0;
   }
   __syncthreads();
   for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
@@ -232,7 +261,7 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
   }
   for (int idx = threadIdx.x; idx < h * w; idx += BS) {
     int i = idx % h, j = idx / h;
-    if (i >= j) panel[poff + i + (int64_t)j * h] = F[i + j * LD];
+    if (i >= j) panel[poff + i + (int64_t)j * ld] = F[i + j * LD];
   }
   const int hu = h - w;
   T* U = ubuf + P.su[S];
@@ -249,7 +278,7 @@ template <typename T>
 __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* panel, T* ubuf) {
   const ExtAddDesc d = P.ext[d0 + blockIdx.x];
   const int32_t S = d.sn;
-  const int hP = P.sh[S], wP = P.sw[S];
+  const int hP = P.sh[S], wP = P.sw[S], ldP = P.sld[S];
   T* pan = panel + P.spanel[S];
   T* UP = ubuf + P.su[S];
   const int64_t ldu = hP - wP;
@@ -269,7 +298,7 @@ __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* pan
       for (int i = j + threadIdx.x; i < hu; i += BS) {
         const int ti = rc[i];
         const T v = U[i + (int64_t)j * hu];
-        if (tj < wP) pan[ti + (int64_t)tj * hP] += v;
+        if (tj < wP) pan[ti + (int64_t)tj * ldP] += v;
         else UP[(ti - wP) + (int64_t)(tj - wP) * ldu] += v;
       }
     }
@@ -277,61 +306,126 @@ __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* pan
   }
 }
 
-// Diagonal block Cholesky in LDS plus the inverse of the factor (used by
-// the triangular solve of the panel below it as a product).
+// Diagonal block Cholesky and inverse.  The NB x NB block lives in
+// registers: thread (tr, tc) of a 16 x 16 grid owns a TS x TS tile.  Column k
+// of the factor is published to LDS once (two barriers per column); the
+// inverse X = L^{-1} is then formed row by row in registers from the factor
+// columns kept in LDS (one barrier per row, double-buffered row exchange).
 template <typename T, int NB>
 __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
-  __shared__ T D[NB * (NB + 1)];
-  __shared__ T I[NB * (NB + 1)];
-  constexpr int LD = NB + 1;
+  constexpr int TS = NB / 16, LD = NB + 1;
+  __shared__ T Lc[NB * LD];
+  __shared__ T xrow[2][NB];
+  __shared__ T pivs;
   const PotrfDesc d = P.potrf[d0 + blockIdx.x];
   const int bw = d.bw;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   T* g = panel + d.d_off;
-  for (int idx = threadIdx.x; idx < bw * bw; idx += BS) {
-    int i = idx % bw, j = idx / bw;
-    D[i + j * LD] = i >= j ? g[i + (int64_t)j * d.ld] : (T)0;
-  }
-  __syncthreads();
+  T a[TS][TS];
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const int i = tr * TS + r, j = tc * TS + c;
+      a[r][c] = (i < bw && j <= i) ? g[i + (int64_t)j * d.ld] : (T)0;
+    }
   for (int k = 0; k < bw; ++k) {
-    if (threadIdx.x == 0) {
-      T v = D[k + k * LD];
-      if (!(v > (T)0) || !isfinite((double)v)) {
-        atomicMin(bad, d.col0 + k);
-        v = (T)1;
+    if (tr == k / TS && tc == k / TS) {
+#pragma unroll
+      for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c)
+          if (r == k % TS && c == k % TS) {
+            T v = a[r][c];
+            const bool ok = v > (T)0 && isfinite((double)v);
+            if (!ok) { atomicMin(bad, d.col0 + k); v = (T)1; }
+            v = sqrt(v);
+            a[r][c] = v;
+            pivs = v;
+            Lc[k + k * LD] = v;
+          }
+    }
+    __syncthreads();
+    if (tc == k / TS) {
+      const T p = pivs;
+#pragma unroll
+      for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+          const int i = tr * TS + r;
+          if (c == k % TS && i > k && i < bw) {
+            a[r][c] /= p;
+            Lc[i + k * LD] = a[r][c];
+          }
+        }
+    }
+    __syncthreads();
+    T li[TS], lj[TS];
+#pragma unroll
+    for (int r = 0; r < TS; ++r) {
+      const int i = tr * TS + r;
+      li[r] = (i > k && i < bw) ? Lc[i + k * LD] : (T)0;
+    }
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const int j = tc * TS + c;
+      lj[c] = (j > k && j < bw) ? Lc[j + k * LD] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < TS; ++r)
+#pragma unroll
+      for (int c = 0; c < TS; ++c)
+        if (tc * TS + c <= tr * TS + r) a[r][c] -= li[r] * lj[c];
+  }
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const int i = tr * TS + r, j = tc * TS + c;
+      if (i < bw && j <= i) g[i + (int64_t)j * d.ld] = a[r][c];
+    }
+  // X = L^{-1}: row k of X is final after dividing by L(k,k); rows below
+  // subtract L(i,k) times it.  X starts as the identity.
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) a[r][c] = (tr * TS + r == tc * TS + c) ? (T)1 : (T)0;
+  for (int k = 0; k < bw; ++k) {
+    T* xr = xrow[k & 1];
+    if (tr == k / TS) {
+      const T dk = Lc[k + k * LD];
+#pragma unroll
+      for (int r = 0; r < TS; ++r)
+        if (r == k % TS) {
+#pragma unroll
+          for (int c = 0; c < TS; ++c) {
+            a[r][c] /= dk;
+            xr[tc * TS + c] = a[r][c];
+          }
+        }
+    }
+    __syncthreads();
+    T xk[TS];
+#pragma unroll
+    for (int c = 0; c < TS; ++c) xk[c] = xr[tc * TS + c];
+#pragma unroll
+    for (int r = 0; r < TS; ++r) {
+      const int i = tr * TS + r;
+      if (i > k && i < bw) {
+        const T lik = Lc[i + k * LD];
+#pragma unroll
+        for (int c = 0; c < TS; ++c) a[r][c] -= lik * xk[c];
       }
-      D[k + k * LD] = sqrt(v);
-    }
-    __syncthreads();
-    const T piv = D[k + k * LD];
-    for (int i = k + 1 + threadIdx.x; i < bw; i += BS) D[i + k * LD] /= piv;
-    __syncthreads();
-    const int r = bw - k - 1;
-    for (int idx = threadIdx.x; idx < r * r; idx += BS) {
-      int i = k + 1 + idx % r, j = k + 1 + idx / r;
-      if (i >= j) D[i + j * LD] -= D[i + k * LD] * D[j + k * LD];
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < bw * bw; idx += BS) {
-    int i = idx % bw, j = idx / bw;
-    if (i >= j) g[i + (int64_t)j * d.ld] = D[i + j * LD];
-  }
-  // inverse of the lower factor, one column per thread
-  for (int j = threadIdx.x; j < bw; j += BS) {
-    for (int i = 0; i < j; ++i) I[i + j * LD] = (T)0;
-    I[j + j * LD] = (T)1 / D[j + j * LD];
-    for (int i = j + 1; i < bw; ++i) {
-      T s = 0;
-      for (int k = j; k < i; ++k) s += D[i + k * LD] * I[k + j * LD];
-      I[i + j * LD] = -s / D[i + i * LD];
     }
   }
-  __syncthreads();
   T* o = inv + d.inv_off;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += BS) {
-    int i = idx % NB, j = idx / NB;
-    o[i + (int64_t)j * NB] = (i < bw && j < bw) ? I[i + j * LD] : (T)0;
-  }
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const int i = tr * TS + r, j = tc * TS + c;
+      o[i + (int64_t)j * NB] = (i < bw && j <= i) ? a[r][c] : (T)0;
+    }
 }
 
 __device__ inline int64_t find_desc(const GemmDesc* g, int64_t d0, int64_t d1, int64_t bid) {
@@ -345,12 +439,33 @@ __device__ inline int64_t find_desc(const GemmDesc* g, int64_t d0, int64_t d1, i
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// 16-byte vectors that only assume element alignment (panel rows may start
+// at any element; the hardware splits misaligned accesses)
+typedef float float4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double double2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// Load up to 4 consecutive elements; `valid` of them are in range (<= 0: none).
+__device__ inline float4u load4(const float* p, int valid) {
+  if (valid >= 4) return *(const float4u*)p;
+  float4u v = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (valid > 0) v.x = p[0];
+  if (valid > 1) v.y = p[1];
+  if (valid > 2) v.z = p[2];
+  return v;
+}
+__device__ inline double2u load2(const double* p, int valid) {
+  if (valid >= 2) return *(const double2u*)p;
+  double2u v = {0.0, 0.0};
+  if (valid > 0) v.x = p[0];
+  return v;
+}
 
 // C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup, each of the
-// four waves owns a 32x32 quadrant (2x2 MFMA blocks).
+// four waves owns a 32x32 quadrant (2x2 MFMA blocks); K chunks of 32 staged
+// through LDS with the next chunk prefetched into registers.
 __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, double* panel,
                                                  double* ubuf, const double* inv) {
-  constexpr int TM = 64, KC = 16, LDS_LD = TM + 2;
+  constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS;  // 8 per operand
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
   const int64_t bid = blockIdx.x;
@@ -363,22 +478,34 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
   const double* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 8 r
+  const int ii = (tid & 31) * 2, kb = tid >> 5;
+  const double* Ap = A + (i0 + ii);
+  const double* Bp = B + (j0 + ii);
+  const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
   doublex4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
+  double2u ra[PER / 2], rb[PER / 2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < PER / 2; ++r) {
+      const int gk = k0 + kb + 8 * r;
+      ra[r] = load2(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
+      rb[r] = load2(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
+    }
+  };
+  load(0);
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
-    for (int r = 0; r < (TM * KC) / BS; ++r) {
-      const int idx = tid + r * BS;
-      const int ii = idx % TM, kk = idx / TM;
-      const int gk = k0 + kk;
-      const int gi = i0 + ii, gj = j0 + ii;
-      As[kk * LDS_LD + ii] = (gi < d.M && gk < d.K) ? A[gi + (int64_t)gk * d.lda] : 0.0;
-      Bs[kk * LDS_LD + ii] = (gj < d.N && gk < d.K) ? B[gj + (int64_t)gk * d.ldb] : 0.0;
+    for (int r = 0; r < PER / 2; ++r) {
+      *(double2u*)&As[(kb + 8 * r) * LDS_LD + ii] = ra[r];
+      *(double2u*)&Bs[(kb + 8 * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
+    if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       double a[2], b[2];
@@ -391,7 +518,7 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -401,8 +528,9 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm + x * 16 + 4 * r + (lane >> 4);
-        const int j = j0 + wn + y * 16 + (lane & 15);
+        // operands swapped: lanes run along rows of C (contiguous stores)
+        const int i = i0 + wm + x * 16 + (lane & 15);
+        const int j = j0 + wn + y * 16 + 4 * r + (lane >> 4);
         if (i < d.M && j < d.N && (!d.lower || i >= j)) {
           double* cp = C + i + (int64_t)j * d.ldc;
           if (d.mode == 0) *cp -= acc[x][y][r];
@@ -412,10 +540,11 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
 }
 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
-// per workgroup, each wave a 64x64 quadrant (2x2 MFMA blocks).
+// per workgroup, each wave a 64x64 quadrant (2x2 MFMA blocks); K is staged
+// through LDS in chunks of 32 with the next chunk prefetched into registers.
 __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, float* panel,
                                                  float* ubuf, const float* inv) {
-  constexpr int TM = 128, KC = 16, LDS_LD = TM + 4;
+  constexpr int TM = 128, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS;  // 16 per operand
   __shared__ float As[KC * LDS_LD];
   __shared__ float Bs[KC * LDS_LD];
   const int64_t bid = blockIdx.x;
@@ -428,6 +557,12 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
   const float* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  // this thread loads 4 consecutive rows (16-byte loads) at k offsets
+  // kb + 8 r; edge rows fall back to guarded scalar loads
+  const int ii = (tid & 31) * 4, kb = tid >> 5;
+  const float* Ap = A + (i0 + ii);
+  const float* Bp = B + (j0 + ii);
+  const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
   floatx16 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -435,17 +570,24 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  float4u ra[PER / 4], rb[PER / 4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < PER / 4; ++r) {
+      const int gk = k0 + kb + 8 * r;
+      ra[r] = load4(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
+      rb[r] = load4(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
+    }
+  };
+  load(0);
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
-    for (int r = 0; r < (TM * KC) / BS; ++r) {
-      const int idx = tid + r * BS;
-      const int ii = idx % TM, kk = idx / TM;
-      const int gk = k0 + kk;
-      const int gi = i0 + ii, gj = j0 + ii;
-      As[kk * LDS_LD + ii] = (gi < d.M && gk < d.K) ? A[gi + (int64_t)gk * d.lda] : 0.0f;
-      Bs[kk * LDS_LD + ii] = (gj < d.N && gk < d.K) ? B[gj + (int64_t)gk * d.ldb] : 0.0f;
+    for (int r = 0; r < PER / 4; ++r) {
+      *(float4u*)&As[(kb + 8 * r) * LDS_LD + ii] = ra[r];
+      *(float4u*)&Bs[(kb + 8 * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
+    if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
       float a[2], b[2];
@@ -458,7 +600,7 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[x], b[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(b[y], a[x], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -468,8 +610,9 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = i0 + wm + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int j = j0 + wn + y * 32 + (lane & 31);
+        // operands swapped: lanes run along rows of C (contiguous stores)
+        const int i = i0 + wm + x * 32 + (lane & 31);
+        const int j = j0 + wn + y * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (i < d.M && j < d.N && (!d.lower || i >= j)) {
           float* cp = C + i + (int64_t)j * d.ldc;
           if (d.mode == 0) *cp -= acc[x][y][r];
@@ -479,24 +622,47 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
 }
 
 // --------------------------------------------------- triangular solves
-__global__ void k_permute_in(int64_t n, const int32_t* perm, const double* rhs, double* xp) {
+__global__ void k_permute_in(int64_t n, const int32_t* perm, const double* rhs, const double* d, double* xp) {
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
-  if (k < n) xp[k] = rhs[perm[k]];
+  if (k < n) xp[k] = d ? rhs[perm[k]] * d[perm[k]] : rhs[perm[k]];
 }
-__global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, double* x) {
+__global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, const double* d, double* x) {
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
-  if (k < n) x[perm[k]] = xp[k];
+  if (k < n) x[perm[k]] = d ? xp[k] * d[perm[k]] : xp[k];
 }
 
-// Forward solve of one level: each supernode gathers its children's update
-// vectors, eliminates its columns and leaves its own update vector.
+// Forward solve, small supernodes (h <= 64): one workgroup, vector in LDS.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_fwd_level(DevPlan P, int32_t q0, const T* panel, double* xp,
-                                                 double* uvec) {
-  const int32_t S = P.level_sn[q0 + blockIdx.x];
+__global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T* panel, const double* xp,
+                                                 double* ys, double* uvec) {
+  __shared__ double t[64];
+  const int32_t S = P.ssmall[d0 + blockIdx.x];
+  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
+  const T* L = panel + P.spanel[S];
+  if ((int)threadIdx.x < h) t[threadIdx.x] = (int)threadIdx.x < w ? xp[f + threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
+    const int32_t c = P.child[q];
+    const int hu = P.sh[c] - P.sw[c];
+    const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
+    const double* uc = uvec + P.suv[c];
+    for (int i = threadIdx.x; i < hu; i += BS) t[rc[i]] += uc[i];
+    __syncthreads();
+  }
+  for (int j = 0; j < w; ++j) {
+    const double yj = t[j] / (double)L[j + (int64_t)j * ld];
+    if ((int)threadIdx.x > j && (int)threadIdx.x < h) t[threadIdx.x] -= (double)L[threadIdx.x + (int64_t)j * ld] * yj;
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < w) ys[f + threadIdx.x] = t[threadIdx.x] / (double)L[threadIdx.x + (int64_t)threadIdx.x * ld];
+  else if ((int)threadIdx.x < h) uvec[P.suv[S] + threadIdx.x - w] = t[threadIdx.x];
+}
+
+// Forward solve, large supernodes: collect the children's update vectors.
+__global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, double* xp, double* uvec) {
+  const int32_t S = P.slarge[d0 + blockIdx.x];
   const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
   const int64_t uo = P.suv[S];
-  const T* L = panel + P.spanel[S];
   for (int i = threadIdx.x; i < h - w; i += BS) uvec[uo + i] = 0.0;
   __syncthreads();
   for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
@@ -511,40 +677,114 @@ __global__ void __launch_bounds__(BS) k_fwd_level(DevPlan P, int32_t q0, const T
     }
     __syncthreads();
   }
-  // row i is owned by thread i % BS; y_j = t_j / L_jj is formed on the fly
-  for (int j = 0; j < w; ++j) {
-    const double yj = xp[f + j] / (double)L[j + (int64_t)j * h];
-    for (int i = j + 1 + threadIdx.x; i < h; i += BS) {
-      const double l = (double)L[i + (int64_t)j * h];
-      if (i < w) xp[f + i] -= l * yj;
-      else uvec[uo + i - w] -= l * yj;
-    }
-    __syncthreads();
-  }
-  for (int j = threadIdx.x; j < w; j += BS) xp[f + j] /= (double)L[j + (int64_t)j * h];
 }
 
+// Forward solve step of a column block: y_J = inv(L_JJ) t_J (every item
+// recomputes it), the owner stores y_J, each item updates its row range.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_bwd_level(DevPlan P, int32_t q0, const T* panel, double* xp) {
-  const int32_t S = P.level_sn[q0 + blockIdx.x];
-  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
+__global__ void __launch_bounds__(BS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
+                                                double* xp, double* ys, double* uvec) {
+  __shared__ double b[128], y[128];
+  const SolveDesc d = P.sdesc[d0 + blockIdx.x];
+  const int32_t S = d.sn;
+  const int w = P.sw[S], f = P.sfirst[S], h = P.sld[S];  // h: leading dimension
+  const int64_t uo = P.suv[S];
+  const T* L = panel + P.spanel[S];
+  const T* I = inv + d.inv_off;
+  const int nb = P.nb, bw = d.bw, c0 = d.c0;
+  if ((int)threadIdx.x < bw) b[threadIdx.x] = xp[f + c0 + threadIdx.x];
+  __syncthreads();
+  if ((int)threadIdx.x < bw) {
+    const int k = threadIdx.x;
+    double acc = 0.0;
+    for (int j = 0; j <= k; ++j) acc += (double)I[k + (int64_t)j * nb] * b[j];
+    y[k] = acc;
+    if (d.owner) ys[f + c0 + k] = acc;
+  }
+  __syncthreads();
+  for (int i = d.r0 + threadIdx.x; i < d.r1; i += BS) {
+    double acc = 0.0;
+    const T* Lr = L + i + (int64_t)c0 * h;
+    for (int k = 0; k < bw; ++k) acc += (double)Lr[(int64_t)k * h] * y[k];
+    if (i < w) xp[f + i] -= acc;
+    else uvec[uo + i - w] -= acc;
+  }
+}
+
+// Backward solve, small supernodes.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T* panel, double* ys) {
+  __shared__ double y[64], xr[64];
+  const int32_t S = P.ssmall[d0 + blockIdx.x];
+  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
   const int hu = h - w;
   const T* L = panel + P.spanel[S];
   const int32_t* rows = P.sn_rows + P.srow[S];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < w; j += BS / 64) {
+  const int tid = threadIdx.x;
+  if (tid < w) y[tid] = ys[f + tid];
+  if (tid < hu) xr[tid] = ys[rows[w + tid]];
+  __syncthreads();
+  if (tid < w) {
     double s = 0.0;
-    for (int i = lane; i < hu; i += 64) s += (double)L[(w + i) + (int64_t)j * h] * xp[rows[w + i]];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) xp[f + j] -= s;
+    for (int i = 0; i < hu; ++i) s += (double)L[(w + i) + (int64_t)tid * ld] * xr[i];
+    y[tid] -= s;
   }
   __syncthreads();
   for (int j = w - 1; j >= 0; --j) {
-    const double zj = xp[f + j] / (double)L[j + (int64_t)j * h];
-    for (int i = threadIdx.x; i < j; i += BS) xp[f + i] -= (double)L[j + (int64_t)i * h] * zj;
+    const double xj = y[j] / (double)L[j + (int64_t)j * ld];
+    if (tid < j) y[tid] -= (double)L[j + (int64_t)tid * ld] * xj;
     __syncthreads();
   }
-  for (int j = threadIdx.x; j < w; j += BS) xp[f + j] /= (double)L[j + (int64_t)j * h];
+  if (tid < w) ys[f + tid] = y[tid] / (double)L[tid + (int64_t)tid * ld];
+}
+
+// Backward solve, large supernodes: partial products L(rows, J)' x(rows)
+// over a row range (one wave per column, fixed summation order).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
+                                                double* part) {
+  __shared__ double xv[256];
+  const SolveDesc d = P.sdesc[d0 + blockIdx.x];
+  const int32_t S = d.sn;
+  const int h = P.sld[S], w = P.sw[S], f = P.sfirst[S];  // h: leading dimension
+  const T* L = panel + P.spanel[S];
+  const int32_t* rows = P.sn_rows + P.srow[S];
+  const int nr = d.r1 - d.r0;
+  for (int i = threadIdx.x; i < nr; i += BS) {
+    const int r = d.r0 + i;
+    xv[i] = r < w ? ys[f + r] : ys[rows[r]];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < d.bw; c += BS / 64) {
+    const T* Lc = L + d.r0 + (int64_t)(d.c0 + c) * h;
+    double s = 0.0;
+    for (int i = lane; i < nr; i += 64) s += (double)Lc[i] * xv[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) part[d.part_off + c] = s;
+  }
+}
+
+// Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of partials).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
+                                                const double* part) {
+  __shared__ double z[128];
+  const SolveDesc d = P.sdesc[d0 + blockIdx.x];
+  const int f = P.sfirst[d.sn], nb = P.nb, bw = d.bw;
+  const T* I = inv + d.inv_off;
+  const int tid = threadIdx.x;
+  if (tid < bw) {
+    double s = 0.0;
+    for (int q = 0; q < d.nparts; ++q) s += part[d.part_off + (int64_t)q * nb + tid];
+    z[tid] = ys[f + d.c0 + tid] - s;
+  }
+  __syncthreads();
+  if (tid < bw) {
+    double acc = 0.0;
+    for (int c = tid; c < bw; ++c) acc += (double)I[c + (int64_t)tid * nb] * z[c];
+    ys[f + d.c0 + tid] = acc;
+  }
 }
 
 // -------------------------------------------------------- IPM vectors
@@ -778,17 +1018,48 @@ __global__ void k_kfree_n(int64_t n, const double* hv_v, const double* jt, const
   if (i < n) out[i] = hv_v[i] + jt[i] + (sig_x[i] + dp) * v[i];
 }
 
-__global__ void k_residual_norms(int64_t n, const double* rhs, const double* kx, double* r, double* partials) {
-  RedSpec spec{2, {RED_MAX, RED_MAX}};
-  double a[2] = {0.0, 0.0};
+__global__ void k_residual_norms(int64_t n, const double* rhs, const double* kx, const double* x, double* r,
+                                 double* partials) {
+  RedSpec spec{3, {RED_MAX, RED_MAX, RED_MAX}};
+  double a[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
     const double ri = rhs[i] - kx[i];
     r[i] = ri;
     a[0] = fmax(a[0], fabs(ri));
     a[1] = fmax(a[1], fabs(rhs[i]));
+    a[2] = fmax(a[2], fabs(x[i]));
+    if (!isfinite(ri)) a[0] = INFINITY;
+  }
+  block_reduce_store<3>(a, spec, partials);
+}
+
+__global__ void k_dot(int64_t n, const double* a, const double* b, double* partials) {
+  RedSpec spec{1, {RED_SUM}};
+  double acc[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) acc[0] += a[i] * b[i];
+  block_reduce_store<1>(acc, spec, partials);
+}
+
+// x += alpha p, r -= alpha q; reports max|r| and max|x|.
+__global__ void k_cg_step(int64_t n, double alpha, const double* p, const double* q, double* x, double* r,
+                          double* partials) {
+  RedSpec spec{2, {RED_MAX, RED_MAX}};
+  double a[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const double xi = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    x[i] = xi;
+    r[i] = ri;
+    a[0] = fmax(a[0], fabs(ri));
+    a[1] = fmax(a[1], fabs(xi));
     if (!isfinite(ri)) a[0] = INFINITY;
   }
   block_reduce_store<2>(a, spec, partials);
+}
+
+__global__ void k_xpby(int64_t n, const double* z, double beta, double* p) {
+  int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
 }
 
 __global__ void k_add(int64_t n, double* x, const double* c) {
@@ -893,25 +1164,44 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
 template void launch_factor_op<double>(const Op&, const DevPlan&, double*, double*, double*, int*, hipStream_t);
 template void launch_factor_op<float>(const Op&, const DevPlan&, float*, float*, float*, int*, hipStream_t);
 
-void launch_permute_in(const DevPlan& P, const double* rhs, double* xp, hipStream_t s) {
-  k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, xp);
+void launch_permute_in(const DevPlan& P, const double* rhs, const double* d, double* xp, hipStream_t s) {
+  k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, d, xp);
 }
-void launch_permute_out(const DevPlan& P, const double* xp, double* x, hipStream_t s) {
-  k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, x);
+void launch_permute_out(const DevPlan& P, const double* xp, const double* d, double* x, hipStream_t s) {
+  k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, d, x);
+}
+void launch_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
+                       hipStream_t s) {
+  int g = red_grid(n);
+  k_diag_scale<<<g, BS, 0, s>>>(n, kp, kval, d, partials);
+  RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 template <typename T>
-void launch_fwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xp, double* uvec,
-                      hipStream_t s) {
-  if (q1 > q0) k_fwd_level<T><<<(unsigned)(q1 - q0), BS, 0, s>>>(P, q0, panel, xp, uvec);
+void launch_set_scaled(const DevKMap& K, const double* kval, const double* d, double shift, T* panel,
+                       hipStream_t s) {
+  k_set_scaled<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, d, shift, panel);
 }
-template void launch_fwd_level<double>(const DevPlan&, int32_t, int32_t, const double*, double*, double*, hipStream_t);
-template void launch_fwd_level<float>(const DevPlan&, int32_t, int32_t, const float*, double*, double*, hipStream_t);
+template void launch_set_scaled<float>(const DevKMap&, const double*, const double*, double, float*, hipStream_t);
+template void launch_set_scaled<double>(const DevKMap&, const double*, const double*, double, double*, hipStream_t);
 template <typename T>
-void launch_bwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xp, hipStream_t s) {
-  if (q1 > q0) k_bwd_level<T><<<(unsigned)(q1 - q0), BS, 0, s>>>(P, q0, panel, xp);
+void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* inv, double* xp, double* ys,
+                     double* uvec, double* part, hipStream_t s) {
+  if (op.grid <= 0) return;
+  const unsigned g = (unsigned)op.grid;
+  switch (op.type) {
+    case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec); break;
+    case OP_FWD_GATHER: k_fwd_gather<<<g, BS, 0, s>>>(P, op.begin, xp, uvec); break;
+    case OP_FWD_STEP: k_fwd_step<T><<<g, BS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
+    case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
+    case OP_BWD_PART: k_bwd_part<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, part); break;
+    case OP_BWD_DIAG: k_bwd_diag<T><<<g, BS, 0, s>>>(P, op.begin, inv, ys, part); break;
+  }
 }
-template void launch_bwd_level<double>(const DevPlan&, int32_t, int32_t, const double*, double*, hipStream_t);
-template void launch_bwd_level<float>(const DevPlan&, int32_t, int32_t, const float*, double*, hipStream_t);
+template void launch_solve_op<double>(const Op&, const DevPlan&, const double*, const double*, double*, double*,
+                                      double*, double*, hipStream_t);
+template void launch_solve_op<float>(const Op&, const DevPlan&, const float*, const float*, double*, double*,
+                                     double*, double*, hipStream_t);
 
 void launch_residuals(const DevProblem& P, IpmVecs& v, hipStream_t s) {
   // J' lambda into tmp_n
@@ -1016,12 +1306,28 @@ void launch_k_mul_free(const DevProblem& P, const double* jv, const double* hv, 
   }
   k_kfree_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, out, tmp_n, sig_x, dp, v, out);
 }
-void launch_residual_norms(int64_t n, const double* rhs, const double* kx, double* r, double* partials,
-                           hipStream_t s) {
+void launch_residual_norms(int64_t n, const double* rhs, const double* kx, const double* x, double* r,
+                           double* partials, hipStream_t s) {
   int g = red_grid(n);
-  k_residual_norms<<<g, BS, 0, s>>>(n, rhs, kx, r, partials);
+  k_residual_norms<<<g, BS, 0, s>>>(n, rhs, kx, x, r, partials);
+  RedSpec spec{3, {RED_MAX, RED_MAX, RED_MAX}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_dot(int64_t n, const double* a, const double* b, double* partials, hipStream_t s) {
+  int g = red_grid(n);
+  k_dot<<<g, BS, 0, s>>>(n, a, b, partials);
+  RedSpec spec{1, {RED_SUM}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_cg_step(int64_t n, double alpha, const double* p, const double* q, double* x, double* r,
+                    double* partials, hipStream_t s) {
+  int g = red_grid(n);
+  k_cg_step<<<g, BS, 0, s>>>(n, alpha, p, q, x, r, partials);
   RedSpec spec{2, {RED_MAX, RED_MAX}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
+}
+void launch_xpby(int64_t n, const double* z, double beta, double* p, hipStream_t s) {
+  k_xpby<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, z, beta, p);
 }
 void launch_add(int64_t n, double* x, const double* c, hipStream_t s) {
   k_add<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, x, c);

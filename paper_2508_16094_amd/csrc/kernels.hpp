@@ -22,9 +22,10 @@ struct DevProblem {
 struct DevPlan {
   int64_t ns, n;
   int nb, small_h;
-  const int32_t *sfirst, *sw, *sh, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
+  const int32_t *sfirst, *sw, *sh, *sld, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
   const int64_t *spanel, *su, *srow, *suv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
+  const SolveDesc* sdesc; const int32_t *ssmall, *slarge;
 };
 
 struct DevKMap {
@@ -63,14 +64,17 @@ template <typename T>
 void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv, int* bad, hipStream_t s);
 
 // triangular solves (vectors FP64, panels T)
-void launch_permute_in(const DevPlan& P, const double* rhs, double* xperm, hipStream_t s);
-void launch_permute_out(const DevPlan& P, const double* xperm, double* x, hipStream_t s);
+void launch_permute_in(const DevPlan& P, const double* rhs, const double* d, double* xperm, hipStream_t s);
+void launch_permute_out(const DevPlan& P, const double* xperm, const double* d, double* x, hipStream_t s);
+// symmetric scaling of K (FP32 factor): d = diag(K)^(-1/2), max diag, count of bad pivots
+void launch_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
+                       hipStream_t s);
 template <typename T>
-void launch_fwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xperm,
-                      double* uvec, hipStream_t s);
+void launch_set_scaled(const DevKMap& K, const double* kval, const double* d, double shift, T* panel,
+                       hipStream_t s);
 template <typename T>
-void launch_bwd_level(const DevPlan& P, int32_t q0, int32_t q1, const T* panel, double* xperm,
-                      hipStream_t s);
+void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* inv, double* xp, double* ys,
+                     double* uvec, double* part, hipStream_t s);
 // symmetric product with stored K values (lower CSR, original numbering)
 void launch_k_mul_stored(int64_t n, const int64_t* kp, const int32_t* kc, const int64_t* ksp,
                          const int32_t* ksc, const int64_t* kss, const double* kval,
@@ -113,9 +117,13 @@ void launch_sum_sl(const DevProblem& P, IpmVecs& v, double* partials, hipStream_
 void launch_k_mul_free(const DevProblem& P, const double* jv, const double* hv, const double* sig_s,
                        const double* sig_x, double delta_p, const double* v, double* out,
                        double* tmp_m, double* tmp_n, hipStream_t s);
-void launch_residual_norms(int64_t n, const double* rhs, const double* kx, double* r,
+void launch_residual_norms(int64_t n, const double* rhs, const double* kx, const double* x, double* r,
                            double* partials, hipStream_t s);
 void launch_add(int64_t n, double* x, const double* c, hipStream_t s);
+void launch_dot(int64_t n, const double* a, const double* b, double* partials, hipStream_t s);
+void launch_cg_step(int64_t n, double alpha, const double* p, const double* q, double* x, double* r,
+                    double* partials, hipStream_t s);
+void launch_xpby(int64_t n, const double* z, double beta, double* p, hipStream_t s);
 void launch_copy(int64_t n, double* dst, const double* src, hipStream_t s);
 void launch_f32_from_f64(int64_t n, float* dst, const double* src, hipStream_t s);
 void launch_f64_from_f32(int64_t n, double* dst, const float* src, hipStream_t s);
