@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark of the interior-point hot path on one MI355X.
+
+Workload (default): the large block-angular LP — n = 2,000,000 columns,
+m = 1,020,000 rows (200 diagonal blocks of 5,000 x 10,000 with 6 nnz per
+column plus 20,000 linking rows of 20 nnz), 0 <= x <= 10, solved to 1e-6 with
+the FP32 supernodal factorisation and FP64 refinement.  One step = one full
+interior-point solve (every per-iteration stage: evaluation, assembly,
+factorisation, triangular solves, refinement, step).  Inputs are generated
+on the host, analysed once (ordering, supernodes) and resident in HBM before
+the timed region.
+
+Prints one JSON line (see the repository's contract): value = solves/s,
+roofline of the dominant kernel (the MFMA Schur-update GEMM of the
+factorisation) measured live with HIP events around each of its launches,
+and a CPU baseline from the oracle timed on a bounded slice of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA TFLOP/s
+
+
+def make_problem(args):
+    from paper_2508_16094_amd import workloads as w
+    if args.workload == "lp_block":
+        p = w.lp_block(nblocks=args.nblocks)
+        name = f"lp_block n={p.n} m={p.m} ({args.nblocks} blocks 5000x10000, 6 nnz/col, 2% linking rows)"
+    elif args.workload == "nlp_grid":
+        p = w.nlp_grid()
+        name = f"nlp_grid n={p.n} m={p.m} (700x700 grid, quadratic stencil constraints)"
+    elif args.workload == "lp_small":
+        p = w.lp_small()
+        name = f"lp_small n={p.n} m={p.m}"
+    else:
+        raise SystemExit(f"unknown workload {args.workload}")
+    return p, name
+
+
+def cpu_baseline(args, flops_full, iters_full):
+    """The oracle (plain FP64 CPU IPM) on a bounded slice of the workload:
+    its time per IPM iteration per factorisation flop, scaled to the full
+    workload's sum_j (c_j^2 - 1) and iteration count."""
+    import numpy as np
+    from oracle import ipm as oipm
+    from oracle import symbolic as osym
+    from paper_2508_16094_amd import workloads as w
+    if args.workload == "lp_block":
+        p = w.lp_block(nblocks=1, block_rows=1000, block_cols=2000, n_link_rows=0)
+        sample = "oracle IPM, 5 iterations on a 1000x2000 block of the block-angular LP generator"
+    elif args.workload == "nlp_grid":
+        p = w.nlp_grid(60, 60)
+        sample = "oracle IPM, 5 iterations on the 60x60 grid instance of the same generator"
+    else:
+        p = w.lp_small()
+        sample = "oracle IPM, 5 iterations on the same instance"
+    t0 = time.time()
+    r = oipm.solve(p, tol=1e-6, max_iter=5, dense_max=0)
+    dt = time.time() - t0
+    # factorisation work of the sample from the oracle's own symbolic analysis
+    import scipy.sparse as sp
+    from oracle import model
+    J = model.jacobian(p, np.zeros(p.n)).tocsr()
+    H = sp.tril(model.hessian(p, np.zeros(p.n), np.ones(p.m))).tocsr()
+    adj = osym.kkt_pattern(p.n, J.indptr, J.indices, H.indptr, H.indices)
+    f_sample = float(osym.analyze(adj, p.n)["flops"])
+    it = max(1, r["iterations"])
+    sec_per_flop_iter = dt / (it * f_sample)
+    t_full = sec_per_flop_iter * flops_full * iters_full
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}: {dt:.1f} s for {it} iterations, sum c_j^2 = {f_sample:.3g}; "
+                      f"scaled by flops ({flops_full:.3g}) and iterations ({iters_full})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lp_block")
+    ap.add_argument("--nblocks", type=int, default=200)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: the hot path is single-GPU (see DESIGN.md, "
+              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2508_16094_amd import lib as L
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    t = time.time()
+    p, name = make_problem(args)
+    log(f"[bench] generated {name} in {time.time() - t:.1f}s")
+    prec = L.PDIPM_FP32 if args.precision == "fp32" else L.PDIPM_FP64
+    t = time.time()
+    # FP32 form: FP64 factors take over for the rest of a solve once FP32
+    # refinement cannot reach the accuracy the iteration needs
+    s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0)
+    st = s.stats()
+    log(f"[bench] analysed in {time.time() - t:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
+        f"supernodes={st['n_super']} levels={st['n_levels']} workspace={s.workspace_bytes() / 1e9:.1f} GB")
+    s.bind()
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        r = s.solve()
+        log(f"[bench] warmup {i}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s")
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    results = []
+    for i in range(args.steps):
+        r = s.solve()
+        results.append(r)
+        log(f"[bench] step {i}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s "
+            f"f {r['f']:.10e} P {r['P']:.1e} D {r['D']:.1e} C {r['C']:.1e}")
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    prof = s.profile()
+    last = results[-1]
+    iters = sum(r["iterations"] for r in results)
+    gemm_tf = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12 if prof["gemm_ms"] > 0 else 0.0
+    pkey = "fp32" if prof["gemm_precision"] == L.PDIPM_FP32 else "fp64"
+    factor_tf = prof["factor_flops"] / (prof["factor_ms"] * 1e-3) / 1e12 if prof["factor_ms"] > 0 else 0.0
+    out = {
+        "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.PDIPM_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "form": "fp32 factor + fp64 refinement" if prec == L.PDIPM_FP32 else "fp64",
+                   "tol": 1e-6, "parallelism": "single GPU"},
+        "status": last["status"], "iterations": last["iterations"], "f": last["f"],
+        "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],
+        "P": last["P"], "D": last["D"], "C": last["C"],
+        "factor_tflops": factor_tf,
+        "factor_ms_per_iter": prof["factor_ms"] / max(1, prof["factorizations"]),
+        "solve_gbps": prof["solve_bytes"] / (last["ms_solve"] * 1e-3 * len(results)) / 1e9
+        if last["ms_solve"] > 0 else None,
+        "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
+                     "frac": gemm_tf / PEAK[pkey], "traffic": None,
+                     "kernel": "k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
+                     "launches": prof["gemm_launches"],
+                     "avg_launch_us": 1e3 * prof["gemm_ms"] / max(1, prof["gemm_launches"])},
+    }
+    if not args.no_cpu_baseline:
+        t = time.time()
+        out["cpu_baseline"] = cpu_baseline(args, st["flops"], last["iterations"])
+        log(f"[bench] cpu baseline in {time.time() - t:.1f}s")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

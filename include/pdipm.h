@@ -87,7 +87,9 @@ typedef struct ipm_options {
   int32_t nd_leaf;       /* minimum-degree leaf size of the ordering, 64 */
   int32_t amalg_menu;    /* supernode amalgamation rule 0, 1, 2 (-1 = none) */
   int32_t print_level;   /* 0 silent, 1 per-iteration line on stderr */
-  int32_t fp64_fallback; /* FP32 form: reserve FP64 space for refactoring */
+  int32_t fp64_fallback; /* FP32 form: reserve FP64 factor space so that FP64
+                            factors take over when FP32 refinement cannot reach
+                            the accuracy an iteration needs (default 1) */
 } ipm_options;
 
 typedef struct kkt_symbolic_stats {
@@ -134,6 +136,18 @@ typedef struct ipm_result {
   int32_t inertia_corrections;
   double max_ir_residual; /* worst backward error of the KKT solves */
 } ipm_result;
+
+typedef struct ipm_profile {
+  int64_t gemm_launches;  /* Schur-update and panel-solve GEMM launches */
+  double gemm_ms;         /* their summed device time (HIP events per launch) */
+  double gemm_flops;      /* their algorithmic flops (useful multiply-adds) */
+  int32_t gemm_precision; /* PDIPM_FP64 or PDIPM_FP32 of the last factorisation */
+  int64_t factorizations;
+  double factor_ms;       /* device time of whole factorisations */
+  double factor_flops;    /* sum over factorisations of sum_j (c_j^2 - 1) */
+  int64_t solves;         /* triangular solve pairs */
+  double solve_bytes;     /* algorithmic bytes: 2 nnz(L) w + 4 n 8 per pair */
+} ipm_profile;
 
 typedef struct ipm_handle ipm_handle;
 
@@ -221,6 +235,12 @@ int ipm_solve(ipm_handle* h, const ipm_start* start, ipm_result* res);
  * NULL pointers are skipped. */
 int ipm_get_solution(ipm_handle* h, double* x, double* s, double* lam, double* zl, double* zu,
                      int memspace);
+
+/* Per-launch timing of the factorisation's GEMM kernel and phase totals
+ * (adds two HIP events per GEMM launch while enabled).  Enabling resets the
+ * counters. */
+int ipm_set_profiling(ipm_handle* h, int enable);
+int ipm_get_profile(ipm_handle* h, ipm_profile* out);
 
 void ipm_destroy(ipm_handle* h);
 

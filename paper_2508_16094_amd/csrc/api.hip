@@ -92,6 +92,10 @@ struct ipm_handle {
   // result
   bool solved = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // optional per-launch timing of the GEMM kernel and phase totals
+  bool profiling = false;
+  std::vector<hipEvent_t> pev;
+  ipm_profile prof{};
 };
 
 namespace {
@@ -321,12 +325,22 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
   int big = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(h->bad, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
   launch_fill_bytes0(h->ubuf, (int64_t)std::max<int64_t>(1, P.u_elems) * es, h->stream);
+  const bool prof = h->profiling;
+  if (prof && (int64_t)h->pev.size() < 2 * P.gemm_launches) {
+    size_t old = h->pev.size();
+    h->pev.resize(2 * P.gemm_launches);
+    for (size_t i = old; i < h->pev.size(); ++i) HIPCHK(h, hipEventCreate(&h->pev[i]));
+  }
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  int64_t gl = 0;
   for (const Op& op : P.ops) {
+    const bool timed = prof && (op.type == OP_TRSM || op.type == OP_UPDATE);
+    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * gl], h->stream));
     if (prec == PDIPM_FP64)
       launch_factor_op<double>(op, D, (double*)h->panel, (double*)h->ubuf, (double*)h->inv, h->bad, h->stream);
     else
       launch_factor_op<float>(op, D, (float*)h->panel, (float*)h->ubuf, (float*)h->inv, h->bad, h->stream);
+    if (timed) { HIPCHK(h, hipEventRecord(h->pev[2 * gl + 1], h->stream)); ++gl; }
   }
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   HIPCHK(h, hipGetLastError());
@@ -335,6 +349,21 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0;
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  if (prof) {
+    double gms = 0;
+    for (int64_t i = 0; i < gl; ++i) {
+      float t = 0;
+      hipEventElapsedTime(&t, h->pev[2 * i], h->pev[2 * i + 1]);
+      gms += t;
+    }
+    h->prof.gemm_launches += gl;
+    h->prof.gemm_ms += gms;
+    h->prof.gemm_flops += P.gemm_flops;
+    h->prof.factorizations += 1;
+    h->prof.factor_ms += ms;
+    h->prof.factor_flops += h->sym.flops;
+    h->prof.gemm_precision = prec;
+  }
   h->factor_prec = prec;
   h->factored = badcol == INT_MAX;
   if (info) {
@@ -351,6 +380,10 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
   const Plan& P = prec == PDIPM_FP64 ? h->plan64 : h->plan32;
   const DevPlan& D = prec == PDIPM_FP64 ? h->dpl64 : h->dpl32;
   const double* d = h->scaled ? h->dscale : nullptr;
+  if (h->profiling) {
+    h->prof.solves += 1;
+    h->prof.solve_bytes += 2.0 * (double)h->sym.nnz_L * (prec == PDIPM_FP64 ? 8 : 4) + 4.0 * h->sym.n * 8;
+  }
   launch_permute_in(D, rhs, d, h->xperm, h->stream);
   for (const std::vector<Op>* ops : {&P.fwd_ops, &P.bwd_ops}) {
     for (const Op& op : *ops) {
@@ -374,16 +407,20 @@ void kmul(ipm_handle* h, const double* x, double* out) {
                       h->v.tmp_n2, h->stream);
 }
 
-// Solve with the current factor; with an FP32 factor, FP64 refinement:
-// plain iterative refinement while the backward error
-// ||r|| / (kmax ||x|| + ||b||) halves each step, then preconditioned
-// conjugate gradients on K (SPD) with the FP32 factor as preconditioner.
-int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info* info) {
+// Solve with the current factor and refine in FP64: plain iterative
+// refinement while the residual halves each step, then (FP32 factor)
+// preconditioned conjugate gradients on K (SPD) with the factor as
+// preconditioner.  Converged when ||r||_inf <= target (target <= 0: the
+// backward-error target ir_tol (kmax ||x|| + ||b||)); refinement also stops
+// when the residual stagnates.
+int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info* info, double target,
+                  bool* converged) {
   const int64_t n = h->sym.n;
   trisolve(h, rhs, out);
   int steps = 0;
-  double omega = 0, nb = 0;
-  const bool refine = h->factor_prec == PDIPM_FP32;
+  double omega = 0, rnorm = 0, nb = 0, nx = 0;
+  const bool fp32 = h->factor_prec == PDIPM_FP32;
+  auto goal = [&]() { return target > 0 ? target : h->opt.ir_tol * (h->kmax * nx + nb); };
   double prev = INFINITY;
   for (int it = 0;; ++it) {
     kmul(h, out, h->ir_kx);
@@ -391,16 +428,15 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
     double nr[3];
     int rc = read_back(h, red_out(h), nr, 3);
     if (rc) return rc;
-    nb = nr[1];
-    omega = nr[0] / (h->kmax * nr[2] + nb + 1e-300);
-    if (!refine || omega <= h->opt.ir_tol || it >= h->opt.ir_max || !(omega < 0.5 * prev)) break;
-    prev = omega;
+    rnorm = nr[0]; nb = nr[1]; nx = nr[2];
+    if (!std::isfinite(rnorm) || rnorm <= goal() || it >= h->opt.ir_max || !(rnorm < 0.5 * prev)) break;
+    prev = rnorm;
     trisolve(h, h->ir_r, h->ir_c);
     launch_add(n, out, h->ir_c, h->stream);
     ++steps;
   }
   int cg = 0;
-  if (refine && omega > h->opt.ir_tol && std::isfinite(omega)) {
+  if (fp32 && std::isfinite(rnorm) && rnorm > goal()) {
     // PCG from the refined point; ir_r holds its residual
     double* r = h->ir_r; double* z = h->ir_c; double* q = h->ir_kx; double* p = h->cg_p;
     trisolve(h, r, z);
@@ -409,7 +445,9 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
     double rho;
     int rc = read_back(h, red_out(h), &rho, 1);
     if (rc) return rc;
-    const int max_cg = 4 * std::max(1, h->opt.ir_max);
+    const int max_cg = 2 * std::max(1, h->opt.ir_max);
+    double best = rnorm;
+    int since_best = 0;
     for (cg = 0; cg < max_cg && rho > 0; ++cg) {
       kmul(h, p, q);
       launch_dot(n, p, q, h->partials, h->stream);
@@ -420,8 +458,10 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
       launch_cg_step(n, alpha, p, q, out, r, h->partials, h->stream);
       double nr[2];
       if ((rc = read_back(h, red_out(h), nr, 2))) return rc;
-      omega = nr[0] / (h->kmax * nr[1] + nb + 1e-300);
-      if (omega <= h->opt.ir_tol || !std::isfinite(omega)) { ++cg; break; }
+      rnorm = nr[0]; nx = nr[1];
+      if (rnorm <= goal() || !std::isfinite(rnorm)) { ++cg; break; }
+      if (rnorm < 0.9 * best) { best = rnorm; since_best = 0; }
+      else if (++since_best >= 5) { ++cg; break; }   // stagnation
       trisolve(h, r, z);
       launch_dot(n, r, z, h->partials, h->stream);
       double rho2;
@@ -430,8 +470,10 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
       rho = rho2;
     }
   }
+  omega = rnorm / (h->kmax * nx + nb + 1e-300);
+  if (converged) *converged = std::isfinite(rnorm) && rnorm <= goal();
   if (info) { info->ir_steps = steps + cg; info->residual = omega; info->fallback = 0; }
-  if (!std::isfinite(omega)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
+  if (!std::isfinite(rnorm)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
   return PDIPM_OK;
 }
 
@@ -553,6 +595,7 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     launch_init_point(P, v, h->stream);
   }
   double delta_w_last = 0.0;
+  bool stay64 = false;  // FP32 form: switched to FP64 factors for the rest of the solve
   int status = PDIPM_MAX_ITER;
   int it = 0;
   double Pm = 0, Dm = 0, Cm = 0, mu = 0, f = 0;
@@ -571,7 +614,8 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     Cm = S.comp / (1.0 + std::fabs(f));
     mu = nc > 0 ? S.comp / nc : 0.0;
     if (O.print_level > 0)
-      fprintf(stderr, "it %3d f %+.10e P %.2e D %.2e C %.2e mu %.2e\n", it, f, Pm, Dm, Cm, mu);
+      fprintf(stderr, "it %3d f %+.10e P %.2e D %.2e C %.2e mu %.2e fac %s ir %d\n", it, f, Pm, Dm, Cm, mu,
+              stay64 || prec == PDIPM_FP64 ? "fp64" : "fp32", R.ir_steps);
     if (S.nonfinite > 0 || !std::isfinite(f)) { status = PDIPM_ERR_NUMERICAL; break; }
     if (Pm <= O.tol && Dm <= O.tol && Cm <= O.tol) { status = PDIPM_OK; break; }
     if (it >= O.max_iter) { status = PDIPM_MAX_ITER; break; }
@@ -580,7 +624,7 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     // assemble + factor.  FP32: scaled factor with shift retries, then an
     // FP64 refactor when allowed; a non-positive pivot in FP64 triggers the
     // inertia correction (delta_w added to the diagonal of K).
-    int fprec = prec;
+    int fprec = stay64 ? PDIPM_FP64 : prec;
     double delta_w = 0.0;
     auto ta = clk::now();
     assemble_values(h, O.delta_p);
@@ -591,6 +635,7 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     rc = factor_k(h, fprec, &fi, &R.ms_factor, &shifts);
     if (rc == PDIPM_ERR_NOT_PD && fprec == PDIPM_FP32 && h->need64) {
       fprec = PDIPM_FP64;
+      stay64 = true;
       R.fp64_refactors++;
       rc = factor_k(h, fprec, &fi, &R.ms_factor, nullptr);
     }
@@ -612,18 +657,23 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     }
     auto ts0 = clk::now();
     kkt_solve_info si{};
+    // refinement target: the stationarity error a solve leaves behind stays
+    // below 1% of the tolerance on the scaled dual infeasibility
+    const double target = 1e-2 * O.tol * (1.0 + S.maxgf);
     auto direction = [&](const double* tsv, const double* tlv, const double* tuv, double* dx, double* ds,
                          double* dl, double* dzl, double* dzu) -> int {
       launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
-      int r2 = solve_refined(h, h->rhs, dx, &si);
+      bool conv = false;
+      int r2 = solve_refined(h, h->rhs, dx, &si, target, &conv);
       if (r2) return r2;
-      if (h->factor_prec == PDIPM_FP32 && si.residual > 1e-10 && h->need64) {
-        // refinement stalled: refactor in FP64 for the rest of the iteration
+      if (!conv && h->factor_prec == PDIPM_FP32 && h->need64) {
+        // FP32 refinement cannot reach the target: FP64 factors from here on
         kkt_factor_info f64{};
         r2 = factor_k(h, PDIPM_FP64, &f64, &R.ms_factor, nullptr);
         if (r2) return r2;
         R.fp64_refactors++;
-        r2 = solve_refined(h, h->rhs, dx, &si);
+        stay64 = true;
+        r2 = solve_refined(h, h->rhs, dx, &si, target, &conv);
         if (r2) return r2;
       }
       R.ir_steps += si.ir_steps;
@@ -706,7 +756,7 @@ void ipm_default_options(ipm_options* o) {
   o->nd_leaf = 64;
   o->amalg_menu = 0;
   o->print_level = 0;
-  o->fp64_fallback = 0;
+  o->fp64_fallback = 1;
 }
 
 const char* ipm_status_string(int s) {
@@ -950,7 +1000,7 @@ int kkt_solve(ipm_handle* h, const double* rhs, double* x, kkt_solve_info* info)
   if (!h->factored) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no valid factor");
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   kkt_solve_info si{};
-  rc = solve_refined(h, rhs, x, &si);
+  rc = solve_refined(h, rhs, x, &si, 0.0, nullptr);
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0;
@@ -988,6 +1038,19 @@ int ipm_evaluate(ipm_handle* h, const double* x, const double* lam, double* f, d
   if (jval && P.nnz_j) HIPCHK(h, hipMemcpyAsync(jval, v.jv, P.nnz_j * 8, hipMemcpyDeviceToDevice, h->stream));
   if (hval) HIPCHK(h, hipMemcpyAsync(hval, v.hv, P.nnz_h * 8, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+int ipm_set_profiling(ipm_handle* h, int enable) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  h->profiling = enable != 0;
+  h->prof = ipm_profile{};
+  return PDIPM_OK;
+}
+
+int ipm_get_profile(ipm_handle* h, ipm_profile* out) {
+  if (!h || !out) return PDIPM_ERR_INVALID_ARG;
+  *out = h->prof;
   return PDIPM_OK;
 }
 
@@ -1033,6 +1096,7 @@ void ipm_destroy(ipm_handle* h) {
   if (!h) return;
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (hipEvent_t e : h->pev) hipEventDestroy(e);
   delete h;
 }
 

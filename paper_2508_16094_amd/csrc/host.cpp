@@ -272,7 +272,8 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
   Plan& P = *pl;
   P = Plan();
   P.esize = esize;
-  P.nb = esize == 8 ? 64 : 128;
+  P.nb = 128;
+  const int nbo = esize == 8 ? 256 : 512;  // outer block: rank of the trailing update
   P.small_h = 64;
   const int64_t ns = s.nsuper();
   P.ns = ns;
@@ -378,83 +379,99 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
     if (large.empty()) continue;
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
-    const int tm = esize == 8 ? 64 : 128;  // gemm tile
-    for (int32_t c0 = 0; c0 < maxw; c0 += nb) {
-      int64_t pb = (int64_t)P.potrf.size();
-      std::vector<int64_t> slot_of(large.size(), -1);
-      for (size_t q = 0; q < large.size(); ++q) {
-        int32_t k = large[q];
-        if (P.sw[k] <= c0) continue;
-        int32_t bw = std::min(nb, P.sw[k] - c0);
-        PotrfDesc d;
-        d.d_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0;
-        d.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
-        d.ld = P.sld[k];
-        d.bw = bw;
-        d.col0 = P.sfirst[k] + c0;
-        d.pad = 0;
-        slot_of[q] = d.inv_off;
-        P.potrf.push_back(d);
+    const int tm = 128;  // gemm tile
+    auto add_gemm = [&](int64_t c_off, int64_t a_off, int64_t b_off, int32_t ldc, int32_t lda, int32_t ldb,
+                        int32_t M, int32_t N, int32_t K, int32_t c_buf, int32_t b_buf, int32_t mode,
+                        int32_t lower, int64_t& tiles) {
+      GemmDesc g{};
+      g.c_off = c_off; g.a_off = a_off; g.b_off = b_off;
+      g.ldc = ldc; g.lda = lda; g.ldb = ldb;
+      g.M = M; g.N = N; g.K = K;
+      g.c_buf = c_buf; g.b_buf = b_buf; g.mode = mode; g.lower = lower;
+      g.tiles_m = (M + tm - 1) / tm; g.tiles_n = (N + tm - 1) / tm;
+      g.tile_begin = tiles;
+      tiles += (int64_t)g.tiles_m * g.tiles_n;
+      P.gemm.push_back(g);
+    };
+    // two-level blocking: inner blocks of nb columns (diagonal factor, panel
+    // solve, update of the rest of the outer block), then one rank-nbo update
+    // of everything to the right of the outer block
+    for (int32_t o0 = 0; o0 < maxw; o0 += nbo) {
+      for (int32_t c0 = o0; c0 < std::min(o0 + nbo, maxw); c0 += nb) {
+        int64_t pb = (int64_t)P.potrf.size();
+        std::vector<int64_t> inv_of(large.size(), -1);
+        for (size_t q = 0; q < large.size(); ++q) {
+          int32_t k = large[q];
+          if (P.sw[k] <= c0) continue;
+          int32_t bw = std::min(nb, P.sw[k] - c0);
+          PotrfDesc d;
+          d.d_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0;
+          d.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
+          d.ld = P.sld[k];
+          d.bw = bw;
+          d.col0 = P.sfirst[k] + c0;
+          d.pad = 0;
+          inv_of[q] = d.inv_off;
+          P.potrf.push_back(d);
+        }
+        P.ops.push_back({OP_POTRF, pb, (int64_t)P.potrf.size(), (int64_t)P.potrf.size() - pb});
+        // panel solve below the diagonal block, in place: C = A * inv(L_JJ)^T
+        int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
+        for (size_t q = 0; q < large.size(); ++q) {
+          int32_t k = large[q];
+          if (inv_of[q] < 0) continue;
+          int32_t bw = std::min(nb, P.sw[k] - c0);
+          int32_t M = P.sh[k] - c0 - bw;
+          if (M <= 0) continue;
+          int64_t off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0 + bw;
+          add_gemm(off, off, inv_of[q], P.sld[k], P.sld[k], nb, M, bw, bw, 0, 1, 1, 0, tiles);
+        }
+        if (tiles) P.ops.push_back({OP_TRSM, gb, (int64_t)P.gemm.size(), tiles});
+        // update of the remaining columns of the outer block
+        gb = (int64_t)P.gemm.size();
+        tiles = 0;
+        for (size_t q = 0; q < large.size(); ++q) {
+          int32_t k = large[q];
+          if (inv_of[q] < 0) continue;
+          int32_t h = P.sh[k], w = P.sw[k], ld = P.sld[k];
+          int32_t bw = std::min(nb, w - c0);
+          int32_t r0 = c0 + bw, o1 = std::min(o0 + nbo, w);
+          if (o1 - r0 <= 0) continue;
+          add_gemm(P.spanel[k] + (int64_t)r0 * ld + r0, P.spanel[k] + (int64_t)c0 * ld + r0,
+                   P.spanel[k] + (int64_t)c0 * ld + r0, ld, ld, ld, h - r0, o1 - r0, bw, 0, 0, 0, 1, tiles);
+        }
+        if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
       }
-      P.ops.push_back({OP_POTRF, pb, (int64_t)P.potrf.size(), (int64_t)P.potrf.size() - pb});
-      // TRSM: rows below the diagonal block, in place, C = A * Dinv^T
+      // rank-(outer block) update of the trailing panel columns and of U
       int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
       for (size_t q = 0; q < large.size(); ++q) {
         int32_t k = large[q];
-        if (slot_of[q] < 0) continue;
-        int32_t bw = std::min(nb, P.sw[k] - c0);
-        int32_t M = P.sh[k] - c0 - bw;
-        if (M <= 0) continue;
-        GemmDesc g{};
-        g.c_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0 + bw;
-        g.a_off = g.c_off;
-        g.b_off = slot_of[q];
-        g.ldc = P.sld[k]; g.lda = P.sld[k]; g.ldb = nb;
-        g.M = M; g.N = bw; g.K = bw;
-        g.c_buf = 0; g.b_buf = 1; g.mode = 1; g.lower = 0;
-        g.tiles_m = (M + tm - 1) / tm; g.tiles_n = 1;
-        g.tile_begin = tiles;
-        tiles += (int64_t)g.tiles_m * g.tiles_n;
-        P.gemm.push_back(g);
-      }
-      if (tiles) P.ops.push_back({OP_TRSM, gb, (int64_t)P.gemm.size(), tiles});
-      // update: trailing panel columns and the update matrix
-      gb = (int64_t)P.gemm.size();
-      tiles = 0;
-      for (size_t q = 0; q < large.size(); ++q) {
-        int32_t k = large[q];
-        if (slot_of[q] < 0) continue;
         int32_t h = P.sh[k], w = P.sw[k], ld = P.sld[k];
-        int32_t bw = std::min(nb, w - c0);
-        int32_t r0 = c0 + bw;
-        if (w - r0 > 0) {
-          GemmDesc g{};
-          g.c_off = P.spanel[k] + (int64_t)r0 * ld + r0;
-          g.a_off = P.spanel[k] + (int64_t)c0 * ld + r0;
-          g.b_off = g.a_off;
-          g.ldc = ld; g.lda = ld; g.ldb = ld;
-          g.M = h - r0; g.N = w - r0; g.K = bw;
-          g.c_buf = 0; g.b_buf = 0; g.mode = 0; g.lower = 1;
-          g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
-          g.tile_begin = tiles;
-          tiles += (int64_t)g.tiles_m * g.tiles_n;
-          P.gemm.push_back(g);
-        }
-        if (h - w > 0) {
-          GemmDesc g{};
-          g.c_off = P.su[k];
-          g.a_off = P.spanel[k] + (int64_t)c0 * ld + w;
-          g.b_off = g.a_off;
-          g.ldc = h - w; g.lda = ld; g.ldb = ld;
-          g.M = h - w; g.N = h - w; g.K = bw;
-          g.c_buf = 1; g.b_buf = 0; g.mode = 0; g.lower = 1;
-          g.tiles_m = (g.M + tm - 1) / tm; g.tiles_n = (g.N + tm - 1) / tm;
-          g.tile_begin = tiles;
-          tiles += (int64_t)g.tiles_m * g.tiles_n;
-          P.gemm.push_back(g);
-        }
+        if (w <= o0) continue;
+        int32_t o1 = std::min(o0 + nbo, w), K = o1 - o0;
+        if (w - o1 > 0)
+          add_gemm(P.spanel[k] + (int64_t)o1 * ld + o1, P.spanel[k] + (int64_t)o0 * ld + o1,
+                   P.spanel[k] + (int64_t)o0 * ld + o1, ld, ld, ld, h - o1, w - o1, K, 0, 0, 0, 1, tiles);
+        if (h - w > 0)
+          add_gemm(P.su[k], P.spanel[k] + (int64_t)o0 * ld + w, P.spanel[k] + (int64_t)o0 * ld + w, h - w, ld,
+                   ld, h - w, h - w, K, 1, 0, 0, 1, tiles);
       }
       if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
+    }
+  }
+  for (const Op& op : P.ops) {
+    if (op.type != OP_TRSM && op.type != OP_UPDATE) continue;
+    ++P.gemm_launches;
+    for (int64_t q = op.begin; q < op.end; ++q) {
+      const GemmDesc& g = P.gemm[q];
+      if (g.mode == 1) {
+        P.gemm_flops += (double)g.M * g.K * g.K;                 // triangular solve
+      } else if (g.lower) {
+        const double n = std::min(g.M, g.N);
+        P.gemm_flops += 2.0 * g.K * ((double)g.M * g.N - n * (n - 1) / 2);
+      } else {
+        P.gemm_flops += 2.0 * g.K * (double)g.M * g.N;
+      }
     }
   }
   // ---- triangular solve schedule (same levels; large fronts blocked by nb)

@@ -121,6 +121,10 @@ struct Plan {
   std::vector<SolveDesc> sdesc;
   std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
   int64_t part_elems = 1;
+  // algorithmic work of the Schur-update / panel-solve GEMM launches of one
+  // factorisation (useful multiply-add flops, triangles not double counted)
+  double gemm_flops = 0;
+  int64_t gemm_launches = 0;
 };
 
 std::string build_problem(const ::ipm_problem_desc* d, HostProblem* p);

@@ -55,6 +55,12 @@ class kkt_solve_info(ctypes.Structure):
     _fields_ = [("ir_steps", _i32), ("residual", _f64), ("fallback", _i32), ("ms", _f64)]
 
 
+class ipm_profile(ctypes.Structure):
+    _fields_ = [("gemm_launches", _i64), ("gemm_ms", _f64), ("gemm_flops", _f64),
+                ("gemm_precision", _i32), ("factorizations", _i64), ("factor_ms", _f64),
+                ("factor_flops", _f64), ("solves", _i64), ("solve_bytes", _f64)]
+
+
 class ipm_start(ctypes.Structure):
     _fields_ = [("x", _p), ("lam", _p), ("memspace", _i32)]
 
@@ -89,6 +95,8 @@ _SIGS = {
     "ipm_get_patterns": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "ipm_solve": (ctypes.c_int, [_p, _p, _p]),
     "ipm_get_solution": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, ctypes.c_int]),
+    "ipm_set_profiling": (ctypes.c_int, [_p, ctypes.c_int]),
+    "ipm_get_profile": (ctypes.c_int, [_p, _p]),
     "ipm_destroy": (None, [_p]),
 }
 
@@ -212,6 +220,14 @@ class _Handle:
         self._check(lib().ipm_set_workspace(self.h, ctypes.c_void_p(base + off), nbytes),
                     "ipm_set_workspace")
         return self
+
+    def set_profiling(self, enable=True):
+        self._check(lib().ipm_set_profiling(self.h, int(enable)), "ipm_set_profiling")
+
+    def profile(self):
+        p = ipm_profile()
+        self._check(lib().ipm_get_profile(self.h, ctypes.byref(p)), "ipm_get_profile")
+        return {k: getattr(p, k) for k, _ in p._fields_}
 
     def factor(self, precision=PDIPM_FP64):
         info = kkt_factor_info()
