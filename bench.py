@@ -50,8 +50,8 @@ def cpu_baseline(args, flops_full, iters_full):
     from oracle import symbolic as osym
     from paper_2508_16094_amd import workloads as w
     if args.workload == "lp_block":
-        p = w.lp_block(nblocks=1, block_rows=1000, block_cols=2000, n_link_rows=0)
-        sample = "oracle IPM, 5 iterations on a 1000x2000 block of the block-angular LP generator"
+        p = w.lp_block(nblocks=1, block_rows=1500, block_cols=3000, n_link_rows=0)
+        sample = "oracle IPM, 5 iterations on a 1500x3000 block of the block-angular LP generator"
     elif args.workload == "nlp_grid":
         p = w.nlp_grid(60, 60)
         sample = "oracle IPM, 5 iterations on the 60x60 grid instance of the same generator"
@@ -127,9 +127,15 @@ def main():
     prof = s.profile()
     last = results[-1]
     iters = sum(r["iterations"] for r in results)
-    gemm_tf = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12 if prof["gemm_ms"] > 0 else 0.0
-    pkey = "fp32" if prof["gemm_precision"] == L.PDIPM_FP32 else "fp64"
-    factor_tf = prof["factor_flops"] / (prof["factor_ms"] * 1e-3) / 1e12 if prof["factor_ms"] > 0 else 0.0
+    def rate(flops, ms):
+        return flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    # dominant kernel: the Schur-update GEMM of the form's own precision
+    key = "32" if prec == L.PDIPM_FP32 else "64"
+    pkey = "fp" + key
+    gemm_tf = rate(prof["gemm" + key + "_flops"], prof["gemm" + key + "_ms"])
+    launches = prof["gemm" + key + "_launches"]
+    factor_tf = rate(prof["factor_flops"], prof["factor_ms"])
+    nfac = prof["factorizations32"] + prof["factorizations64"]
     out = {
         "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
         "value": args.steps / elapsed,
@@ -149,14 +155,16 @@ def main():
         "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],
         "P": last["P"], "D": last["D"], "C": last["C"],
         "factor_tflops": factor_tf,
-        "factor_ms_per_iter": prof["factor_ms"] / max(1, prof["factorizations"]),
+        "factorizations": {"fp32": prof["factorizations32"], "fp64": prof["factorizations64"]},
+        "factor_ms_per_iter": prof["factor_ms"] / max(1, nfac),
         "solve_gbps": prof["solve_bytes"] / (last["ms_solve"] * 1e-3 * len(results)) / 1e9
         if last["ms_solve"] > 0 else None,
         "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
                      "frac": gemm_tf / PEAK[pkey], "traffic": None,
                      "kernel": "k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
-                     "launches": prof["gemm_launches"],
-                     "avg_launch_us": 1e3 * prof["gemm_ms"] / max(1, prof["gemm_launches"])},
+                     "launches": launches,
+                     "avg_launch_us": 1e3 * prof["gemm" + key + "_ms"] / max(1, launches),
+                     "fp64_fallback_gemm_tflops": rate(prof["gemm64_flops"], prof["gemm64_ms"])},
     }
     if not args.no_cpu_baseline:
         t = time.time()

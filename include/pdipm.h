@@ -138,15 +138,17 @@ typedef struct ipm_result {
 } ipm_result;
 
 typedef struct ipm_profile {
-  int64_t gemm_launches;  /* Schur-update and panel-solve GEMM launches */
-  double gemm_ms;         /* their summed device time (HIP events per launch) */
-  double gemm_flops;      /* their algorithmic flops (useful multiply-adds) */
-  int32_t gemm_precision; /* PDIPM_FP64 or PDIPM_FP32 of the last factorisation */
-  int64_t factorizations;
-  double factor_ms;       /* device time of whole factorisations */
-  double factor_flops;    /* sum over factorisations of sum_j (c_j^2 - 1) */
-  int64_t solves;         /* triangular solve pairs */
-  double solve_bytes;     /* algorithmic bytes: 2 nnz(L) w + 4 n 8 per pair */
+  int64_t gemm32_launches; /* FP32 Schur-update and panel-solve GEMM launches */
+  double gemm32_ms;        /* their summed device time (HIP events per launch) */
+  double gemm32_flops;     /* their algorithmic flops (useful multiply-adds) */
+  int64_t gemm64_launches; /* the same for FP64 factorisations */
+  double gemm64_ms;
+  double gemm64_flops;
+  int64_t factorizations32, factorizations64;
+  double factor_ms;        /* device time of whole factorisations */
+  double factor_flops;     /* sum over factorisations of sum_j (c_j^2 - 1) */
+  int64_t solves;          /* triangular solve pairs */
+  double solve_bytes;      /* algorithmic bytes: 2 nnz(L) w + 4 n 8 per pair */
 } ipm_profile;
 
 typedef struct ipm_handle ipm_handle;

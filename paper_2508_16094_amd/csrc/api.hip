@@ -356,13 +356,15 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
       hipEventElapsedTime(&t, h->pev[2 * i], h->pev[2 * i + 1]);
       gms += t;
     }
-    h->prof.gemm_launches += gl;
-    h->prof.gemm_ms += gms;
-    h->prof.gemm_flops += P.gemm_flops;
-    h->prof.factorizations += 1;
+    if (prec == PDIPM_FP32) {
+      h->prof.gemm32_launches += gl; h->prof.gemm32_ms += gms; h->prof.gemm32_flops += P.gemm_flops;
+      h->prof.factorizations32 += 1;
+    } else {
+      h->prof.gemm64_launches += gl; h->prof.gemm64_ms += gms; h->prof.gemm64_flops += P.gemm_flops;
+      h->prof.factorizations64 += 1;
+    }
     h->prof.factor_ms += ms;
     h->prof.factor_flops += h->sym.flops;
-    h->prof.gemm_precision = prec;
   }
   h->factor_prec = prec;
   h->factored = badcol == INT_MAX;
@@ -445,7 +447,7 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
     double rho;
     int rc = read_back(h, red_out(h), &rho, 1);
     if (rc) return rc;
-    const int max_cg = 2 * std::max(1, h->opt.ir_max);
+    const int max_cg = 5 * std::max(1, h->opt.ir_max);
     double best = rnorm;
     int since_best = 0;
     for (cg = 0; cg < max_cg && rho > 0; ++cg) {
@@ -461,7 +463,7 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
       rnorm = nr[0]; nx = nr[1];
       if (rnorm <= goal() || !std::isfinite(rnorm)) { ++cg; break; }
       if (rnorm < 0.9 * best) { best = rnorm; since_best = 0; }
-      else if (++since_best >= 5) { ++cg; break; }   // stagnation
+      else if (++since_best >= 8) { ++cg; break; }   // stagnation
       trisolve(h, r, z);
       launch_dot(n, r, z, h->partials, h->stream);
       double rho2;

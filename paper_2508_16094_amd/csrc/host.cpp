@@ -272,7 +272,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
   Plan& P = *pl;
   P = Plan();
   P.esize = esize;
-  P.nb = 128;
+  P.nb = esize == 8 ? 64 : 128;            // diagonal block / panel-solve width
   const int nbo = esize == 8 ? 256 : 512;  // outer block: rank of the trailing update
   P.small_h = 64;
   const int64_t ns = s.nsuper();
@@ -379,7 +379,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
     if (large.empty()) continue;
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
-    const int tm = 128;  // gemm tile
+    const int tm = esize == 8 ? 64 : 128;  // gemm tile
     auto add_gemm = [&](int64_t c_off, int64_t a_off, int64_t b_off, int32_t ldc, int32_t lda, int32_t ldb,
                         int32_t M, int32_t N, int32_t K, int32_t c_buf, int32_t b_buf, int32_t mode,
                         int32_t lower, int64_t& tiles) {

@@ -460,12 +460,12 @@ __device__ inline double2u load2(const double* p, int valid) {
   return v;
 }
 
-// C (-)= A * B^T, FP64 MFMA 16x16x4.  128x128 tile per workgroup, each of
-// the four waves owns a 64x64 quadrant (4x4 MFMA blocks); K chunks of 16
-// staged through LDS with the next chunk prefetched into registers.
+// C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup, each of the
+// four waves owns a 32x32 quadrant (2x2 MFMA blocks); K chunks of 32 staged
+// through LDS with the next chunk prefetched into registers.
 __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, double* panel,
                                                  double* ubuf, const double* inv) {
-  constexpr int TM = 128, KC = 16, LDS_LD = TM + 2;
+  constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS;  // 8 per operand
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
   const int64_t bid = blockIdx.x;
@@ -477,22 +477,22 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
   const double* A = panel + d.a_off;
   const double* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 4 r
-  const int ii = (tid & 63) * 2, kb = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 8 r
+  const int ii = (tid & 31) * 2, kb = tid >> 5;
   const double* Ap = A + (i0 + ii);
   const double* Bp = B + (j0 + ii);
   const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
-  doublex4 acc[4][4];
+  doublex4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
-  double2u ra[4], rb[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
+  double2u ra[PER / 2], rb[PER / 2];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gk = k0 + kb + 4 * r;
+    for (int r = 0; r < PER / 2; ++r) {
+      const int gk = k0 + kb + 8 * r;
       ra[r] = load2(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load2(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
     }
@@ -500,32 +500,32 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
   load(0);
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      *(double2u*)&As[(kb + 4 * r) * LDS_LD + ii] = ra[r];
-      *(double2u*)&Bs[(kb + 4 * r) * LDS_LD + ii] = rb[r];
+    for (int r = 0; r < PER / 2; ++r) {
+      *(double2u*)&As[(kb + 8 * r) * LDS_LD + ii] = ra[r];
+      *(double2u*)&Bs[(kb + 8 * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
     if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      double a[4], b[4];
+      double a[2], b[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 2; ++q) {
         a[q] = As[(kk + (lane >> 4)) * LDS_LD + wm + q * 16 + (lane & 15)];
         b[q] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + q * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // operands swapped: lanes run along rows of C (contiguous stores)
@@ -1151,7 +1151,8 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
     case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf); break;
     case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad); break;
     case OP_POTRF:
-      k_potrf<T, 128><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
+      if constexpr (sizeof(T) == 8) k_potrf<T, 64><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
+      else k_potrf<T, 128><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
       break;
     case OP_TRSM:
     case OP_UPDATE:
