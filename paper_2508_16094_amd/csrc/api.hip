@@ -61,7 +61,7 @@ struct ipm_handle {
     size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
-    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part;
+    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
     size_t vec[49];
   } o{};
   DevProblem dp{};
@@ -173,11 +173,13 @@ void layout(ipm_handle* h) {
   if (h->need64) {
     o.gemm64 = r.take(bytes_of(h->plan64.gemm)); o.potrf64 = r.take(bytes_of(h->plan64.potrf));
     o.sdesc64 = r.take(bytes_of(h->plan64.sdesc)); o.ssmall64 = r.take(bytes_of(h->plan64.ssmall));
+    o.sinv64 = r.take(bytes_of(h->plan64.sinv));
     o.slarge64 = r.take(bytes_of(h->plan64.slarge));
   }
   if (h->need32) {
     o.gemm32 = r.take(bytes_of(h->plan32.gemm)); o.potrf32 = r.take(bytes_of(h->plan32.potrf));
     o.sdesc32 = r.take(bytes_of(h->plan32.sdesc)); o.ssmall32 = r.take(bytes_of(h->plan32.ssmall));
+    o.sinv32 = r.take(bytes_of(h->plan32.sinv));
     o.slarge32 = r.take(bytes_of(h->plan32.slarge));
   }
   const size_t es = h->need64 ? 8 : 4;
@@ -239,11 +241,11 @@ int bind_workspace(ipm_handle* h) {
   UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
   UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv); UP(ext, P.ext); UP(small, P.small);
   if (h->need64) {
-    UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc);
+    UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc); UP(sinv64, h->plan64.sinv);
     UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge);
   }
   if (h->need32) {
-    UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc);
+    UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc); UP(sinv32, h->plan32.sinv);
     UP(ssmall32, h->plan32.ssmall); UP(slarge32, h->plan32.slarge);
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -281,6 +283,7 @@ int bind_workspace(ipm_handle* h) {
     q.sdesc = at<SolveDesc>(h, prec == 0 ? o.sdesc64 : o.sdesc32);
     q.ssmall = at<int32_t>(h, prec == 0 ? o.ssmall64 : o.ssmall32);
     q.slarge = at<int32_t>(h, prec == 0 ? o.slarge64 : o.slarge32);
+    q.sinv = at<int64_t>(h, prec == 0 ? o.sinv64 : o.sinv32);
   }
   h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;
   h->bad = at<int>(h, o.bad); h->partials = at<double>(h, o.partials);

@@ -390,7 +390,10 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       g.c_buf = c_buf; g.b_buf = b_buf; g.mode = mode; g.lower = lower;
       g.tiles_m = (M + tm - 1) / tm; g.tiles_n = (N + tm - 1) / tm;
       g.tile_begin = tiles;
-      tiles += (int64_t)g.tiles_m * g.tiles_n;
+      // lower-masked blocks start on the diagonal (M >= N): only tiles on or
+      // below the diagonal are enumerated
+      if (lower) tiles += (int64_t)g.tiles_n * g.tiles_m - (int64_t)g.tiles_n * (g.tiles_n - 1) / 2;
+      else tiles += (int64_t)g.tiles_m * g.tiles_n;
       P.gemm.push_back(g);
     };
     // two-level blocking: inner blocks of nb columns (diagonal factor, panel
@@ -475,8 +478,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
     }
   }
   // ---- triangular solve schedule (same levels; large fronts blocked by nb)
-  const int RB = 256;  // rows per work item
-  int64_t max_parts = 1;
+  const int RB = 256;  // rows per forward work item
   for (int l = 0; l < P.nlevels; ++l) {
     std::vector<int32_t> large;
     int64_t sb = (int64_t)P.ssmall.size();
@@ -498,22 +500,20 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       for (int32_t k : large) {
         if (P.sw[k] <= c0) continue;
         int32_t bw = std::min(nb, P.sw[k] - c0);
-        int64_t inv = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
-        int32_t rbeg = c0 + bw;
-        bool first = true;
-        for (int32_t r0 = rbeg; r0 < P.sh[k] || first; r0 += RB) {
+        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RB) {
           SolveDesc d{};
-          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = std::min(r0, P.sh[k]);
-          d.r1 = std::min(r0 + RB, P.sh[k]); d.owner = first ? 1 : 0; d.inv_off = inv;
+          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RB, P.sh[k]);
+          d.owner = (r0 == c0 + bw && c0 + bw < P.sw[k]) ? 1 : 0;
           P.sdesc.push_back(d);
-          first = false;
-          if (r0 >= P.sh[k]) break;
         }
       }
-      P.fwd_ops.push_back({OP_FWD_STEP, db, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - db});
+      if ((int64_t)P.sdesc.size() > db)
+        P.fwd_ops.push_back({OP_FWD_STEP, db, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - db});
     }
   }
-  // backward: levels from the root down; large fronts from their last block
+  // backward: levels from the root down; column blocks from the last one:
+  // partial products over row ranges below the block, then the block solve
+  const int RBB = 256;  // rows per backward partial item
   for (int l = P.nlevels - 1; l >= 0; --l) {
     std::vector<int32_t> large;
     int64_t sb = (int64_t)P.ssmall.size();
@@ -537,13 +537,11 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
         if (P.sw[k] <= c0) continue;
         int32_t bw = std::min(nb, P.sw[k] - c0);
         SolveDesc dd{};
-        dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.r0 = dd.r1 = 0; dd.owner = 1;
-        dd.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
-        dd.part_off = part;
+        dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.owner = 1; dd.part_off = part;
         int32_t np = 0;
-        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RB) {
+        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RBB) {
           SolveDesc d{};
-          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RB, P.sh[k]);
+          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RBB, P.sh[k]);
           d.part_off = part;
           part += nb;
           ++np;
@@ -552,7 +550,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
         dd.nparts = np;
         diag.push_back(dd);
       }
-      max_parts = std::max(max_parts, part);
+      P.part_elems = std::max(P.part_elems, part);
       if ((int64_t)P.sdesc.size() > pb)
         P.bwd_ops.push_back({OP_BWD_PART, pb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - pb});
       int64_t qb = (int64_t)P.sdesc.size();
@@ -560,7 +558,6 @@ void build_plan(const Symbolic& s, int esize, Plan* pl) {
       P.bwd_ops.push_back({OP_BWD_DIAG, qb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - qb});
     }
   }
-  P.part_elems = max_parts;
 }
 
 void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {

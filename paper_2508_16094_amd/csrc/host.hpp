@@ -73,13 +73,14 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
   int32_t sn, t0, t1, pad;
 };
 
-// Blocked triangular-solve work item: rows [r0, r1) of supernode sn against
-// its column block [c0, c0 + bw).
+// Blocked triangular-solve work item of supernode sn and column block
+// [c0, c0 + bw) over rows [r0, r1) below the block.  Forward: the owner
+// item also forms y of the next block.  Backward: partial products go to
+// part[part_off ..]; a diagonal item sums its nparts partials and solves.
 struct SolveDesc {
   int32_t sn, c0, bw, r0, r1, owner;
-  int64_t inv_off;         // inverse of the diagonal block (ld = nb)
-  int64_t part_off;        // backward partial sums of this item (bw values)
-  int32_t nparts, pad;     // backward diagonal item: number of partial items
+  int64_t part_off;
+  int32_t nparts, pad;
 };
 
 enum OpType {
@@ -120,7 +121,7 @@ struct Plan {
   std::vector<Op> fwd_ops, bwd_ops;
   std::vector<SolveDesc> sdesc;
   std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
-  int64_t part_elems = 1;
+  int64_t part_elems = 1;              // backward partial sums (max per step)
   // algorithmic work of the Schur-update / panel-solve GEMM launches of one
   // factorisation (useful multiply-add flops, triangles not double counted)
   double gemm_flops = 0;

@@ -428,6 +428,32 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
     }
 }
 
+// Tile (ti, tj) of descriptor-local tile index t; lower-masked descriptors
+// enumerate column by column only the tiles with ti >= tj.
+__device__ inline void tile_of(const GemmDesc& d, int64_t t, int& ti, int& tj) {
+  if (!d.lower) {
+    ti = (int)(t % d.tiles_m);
+    tj = (int)(t / d.tiles_m);
+    return;
+  }
+  const int64_t m = d.tiles_m;
+  int lo = 0, hi = d.tiles_n - 1;   // largest tj with C(tj) <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t c = (int64_t)mid * m - (int64_t)mid * (mid - 1) / 2;
+    if (c <= t) lo = mid; else hi = mid - 1;
+  }
+  tj = lo;
+  ti = lo + (int)(t - ((int64_t)lo * m - (int64_t)lo * (lo - 1) / 2));
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// run of tiles (neighbouring tiles share A and B panels in that XCD's L2).
+__device__ inline int64_t xcd_tile(int64_t bid, int64_t grid) {
+  const int64_t per = grid >> 3;   // grid is a multiple of 8
+  return (bid & 7) * per + (bid >> 3);
+}
+
 __device__ inline int64_t find_desc(const GemmDesc* g, int64_t d0, int64_t d1, int64_t bid) {
   int64_t lo = d0, hi = d1 - 1;
   while (lo < hi) {
@@ -463,16 +489,17 @@ __device__ inline double2u load2(const double* p, int valid) {
 // C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup, each of the
 // four waves owns a 32x32 quadrant (2x2 MFMA blocks); K chunks of 32 staged
 // through LDS with the next chunk prefetched into registers.
-__global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, double* panel,
+__global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
                                                  double* ubuf, const double* inv) {
   constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS;  // 8 per operand
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
-  const int64_t bid = blockIdx.x;
+  const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+  if (bid >= ntiles) return;
   const GemmDesc d = P.gemm[find_desc(P.gemm, d0, d1, bid)];
-  const int64_t t = bid - d.tile_begin;
-  const int i0 = (int)(t % d.tiles_m) * TM, j0 = (int)(t / d.tiles_m) * TM;
-  if (d.lower && i0 + TM - 1 < j0) return;
+  int ti, tj;
+  tile_of(d, bid - d.tile_begin, ti, tj);
+  const int i0 = ti * TM, j0 = tj * TM;
   double* C = (d.c_buf ? ubuf : panel) + d.c_off;
   const double* A = panel + d.a_off;
   const double* B = (d.b_buf ? inv : panel) + d.b_off;
@@ -542,16 +569,17 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
 // per workgroup, each wave a 64x64 quadrant (2x2 MFMA blocks); K is staged
 // through LDS in chunks of 32 with the next chunk prefetched into registers.
-__global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, float* panel,
+__global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
                                                  float* ubuf, const float* inv) {
   constexpr int TM = 128, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS;  // 16 per operand
   __shared__ float As[KC * LDS_LD];
   __shared__ float Bs[KC * LDS_LD];
-  const int64_t bid = blockIdx.x;
+  const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
+  if (bid >= ntiles) return;
   const GemmDesc d = P.gemm[find_desc(P.gemm, d0, d1, bid)];
-  const int64_t t = bid - d.tile_begin;
-  const int i0 = (int)(t % d.tiles_m) * TM, j0 = (int)(t / d.tiles_m) * TM;
-  if (d.lower && i0 + TM - 1 < j0) return;
+  int ti, tj;
+  tile_of(d, bid - d.tile_begin, ti, tj);
+  const int i0 = ti * TM, j0 = tj * TM;
   float* C = (d.c_buf ? ubuf : panel) + d.c_off;
   const float* A = panel + d.a_off;
   const float* B = (d.b_buf ? inv : panel) + d.b_off;
@@ -658,8 +686,23 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
   else if ((int)threadIdx.x < h) uvec[P.suv[S] + threadIdx.x - w] = t[threadIdx.x];
 }
 
-// Forward solve, large supernodes: collect the children's update vectors.
-__global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, double* xp, double* uvec) {
+// y = inv(L_JJ) t for a diagonal block (inverse lower triangular, ld nb);
+// t in LDS, result to ys.  Threads k < bw.
+template <typename T>
+__device__ inline void block_inv_lower(const T* I, int nb, int bw, const double* t, double* ys) {
+  const int k = threadIdx.x;
+  if (k < bw) {
+    double acc = 0.0;
+    for (int j = 0; j <= k; ++j) acc += (double)I[k + (int64_t)j * nb] * t[j];
+    ys[k] = acc;
+  }
+}
+// Forward solve, large supernodes: collect the children's update vectors,
+// then y for the first column block.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, const T* inv, double* xp, double* ys,
+                                                  double* uvec) {
+  __shared__ double tb[128];
   const int32_t S = P.slarge[d0 + blockIdx.x];
   const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
   const int64_t uo = P.suv[S];
@@ -677,37 +720,95 @@ __global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, double
     }
     __syncthreads();
   }
+  const int bw = w < P.nb ? w : P.nb;
+  if ((int)threadIdx.x < bw) tb[threadIdx.x] = xp[f + threadIdx.x];
+  __syncthreads();
+  block_inv_lower(inv + P.sinv[S], P.nb, bw, tb, ys + f);
 }
 
-// Forward solve step of a column block: y_J = inv(L_JJ) t_J (every item
-// recomputes it), the owner stores y_J, each item updates its row range.
+template <int C>
+__device__ inline void halve_step(double* acc, bool upper, int o) {
+#pragma unroll
+  for (int j = 0; j < C / 2; ++j) {
+    const double send = upper ? acc[j] : acc[j + C / 2];
+    const double keep = upper ? acc[j + C / 2] : acc[j];
+    acc[j] = keep + __shfl_xor(send, o, 64);
+  }
+}
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct VecOf<double> { typedef double2 type; static constexpr int n = 2; };
+
+// Forward solve step of column block J: every item updates its rows with
+// y_J; the owner item (its rows start with block J+1) then forms y_{J+1}.
+// Lanes load VEC consecutive rows of a column with one vector load; the four
+// waves split the block's columns and are summed through LDS in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
                                                 double* xp, double* ys, double* uvec) {
-  __shared__ double b[128], y[128];
+  constexpr int VEC = VecOf<T>::n, CPW = 32, RW = 64 * VEC;
+  typedef typename VecOf<T>::type V;
+  __shared__ double y[128], tb[128];
+  __shared__ double red[4 * RW];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int32_t S = d.sn;
-  const int w = P.sw[S], f = P.sfirst[S], h = P.sld[S];  // h: leading dimension
+  const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
   const int64_t uo = P.suv[S];
-  const T* L = panel + P.spanel[S];
-  const T* I = inv + d.inv_off;
-  const int nb = P.nb, bw = d.bw, c0 = d.c0;
-  if ((int)threadIdx.x < bw) b[threadIdx.x] = xp[f + c0 + threadIdx.x];
+  const int bw = d.bw, c0 = d.c0, nc0 = c0 + bw;
+  const T* L = panel + P.spanel[S] + (int64_t)c0 * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cb = wave * CPW;
+  const int ncol = bw - cb < CPW ? bw - cb : CPW;
+  if (tid < bw) y[tid] = ys[f + c0 + tid];
   __syncthreads();
-  if ((int)threadIdx.x < bw) {
-    const int k = threadIdx.x;
-    double acc = 0.0;
-    for (int j = 0; j <= k; ++j) acc += (double)I[k + (int64_t)j * nb] * b[j];
-    y[k] = acc;
-    if (d.owner) ys[f + c0 + k] = acc;
+  for (int rb = d.r0 & ~(VEC - 1); rb < d.r1; rb += RW) {
+    const int i0 = rb + lane * VEC;
+    double a[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) a[e] = 0.0;
+    const bool full = i0 >= d.r0 && i0 + VEC <= d.r1;
+    const bool any = i0 + VEC > d.r0 && i0 < d.r1;
+    if (any) {
+#pragma unroll
+      for (int m = 0; m < CPW; ++m) {
+        if (m < ncol) {
+          const T* p = L + (int64_t)(cb + m) * ld + i0;
+          T v[VEC];
+          if (full) {
+            const V q = *(const V*)p;
+            v[0] = q.x; v[1] = q.y;
+            if constexpr (VEC == 4) { v[2] = q.z; v[3] = q.w; }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = (i0 + e >= d.r0 && i0 + e < d.r1) ? p[e] : (T)0;
+          }
+          const double yk = y[cb + m];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) a[e] += (double)v[e] * yk;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[wave * RW + lane * VEC + e] = a[e];
+    __syncthreads();
+    if (tid < RW) {
+      const int i = rb + tid;
+      if (i >= d.r0 && i < d.r1) {
+        const double sum = (red[tid] + red[RW + tid]) + (red[2 * RW + tid] + red[3 * RW + tid]);
+        if (i < w) {
+          const double v = xp[f + i] - sum;
+          xp[f + i] = v;
+          if (d.owner && i - nc0 < 128) tb[i - nc0] = v;
+        } else {
+          uvec[uo + i - w] -= sum;
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int i = d.r0 + threadIdx.x; i < d.r1; i += BS) {
-    double acc = 0.0;
-    const T* Lr = L + i + (int64_t)c0 * h;
-    for (int k = 0; k < bw; ++k) acc += (double)Lr[(int64_t)k * h] * y[k];
-    if (i < w) xp[f + i] -= acc;
-    else uvec[uo + i - w] -= acc;
+  if (d.owner) {
+    const int bw2 = w - nc0 < P.nb ? w - nc0 : P.nb;
+    block_inv_lower(inv + P.sinv[S] + (int64_t)(nc0 / P.nb) * P.nb * P.nb, P.nb, bw2, tb, ys + f + nc0);
   }
 }
 
@@ -739,52 +840,118 @@ __global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T
 }
 
 // Backward solve, large supernodes: partial products L(rows, J)' x(rows)
-// over a row range (one wave per column, fixed summation order).
+// over a row range below column block J.  Each lane loads VEC consecutive
+// rows of a column with one vector load (coalesced along the column), each
+// wave owns 32 columns of the block and keeps one FP64 accumulator per
+// column; the 64 lanes are combined by recursive halving (32 exchanges in
+// all instead of 6 per column).
 template <typename T>
 __global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
                                                 double* part) {
-  __shared__ double xv[256];
+  constexpr int CPW = 32, VEC = VecOf<T>::n;
+  typedef typename VecOf<T>::type V;
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int32_t S = d.sn;
-  const int h = P.sld[S], w = P.sw[S], f = P.sfirst[S];  // h: leading dimension
-  const T* L = panel + P.spanel[S];
+  const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
+  const T* L = panel + P.spanel[S] + (int64_t)d.c0 * ld;   // 16-byte aligned columns
   const int32_t* rows = P.sn_rows + P.srow[S];
-  const int nr = d.r1 - d.r0;
-  for (int i = threadIdx.x; i < nr; i += BS) {
-    const int r = d.r0 + i;
-    xv[i] = r < w ? ys[f + r] : ys[rows[r]];
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < d.bw; c += BS / 64) {
-    const T* Lc = L + d.r0 + (int64_t)(d.c0 + c) * h;
-    double s = 0.0;
-    for (int i = lane; i < nr; i += 64) s += (double)Lc[i] * xv[i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) part[d.part_off + c] = s;
+  const int cb = wave * CPW;
+  double acc[CPW];
+#pragma unroll
+  for (int m = 0; m < CPW; ++m) acc[m] = 0.0;
+  if (cb < d.bw) {
+    const int ncol = d.bw - cb < CPW ? d.bw - cb : CPW;
+    for (int rb = d.r0 & ~(VEC - 1); rb < d.r1; rb += 64 * VEC) {
+      const int i0 = rb + lane * VEC;
+      double xv[VEC];
+      bool any = false;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int i = i0 + e;
+        const bool in = i >= d.r0 && i < d.r1;
+        xv[e] = in ? (i < w ? ys[f + i] : ys[rows[i]]) : 0.0;
+        any |= in;
+      }
+      const bool full = i0 >= d.r0 && i0 + VEC <= d.r1;
+      if (!any) continue;
+#pragma unroll
+      for (int m = 0; m < CPW; ++m) {
+        if (m < ncol) {
+          const T* p = L + (int64_t)(cb + m) * ld + i0;
+          T v[VEC];
+          if (full) {
+            const V q = *(const V*)p;
+            v[0] = q.x; v[1] = q.y;
+            if constexpr (VEC == 4) { v[2] = q.z; v[3] = q.w; }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = (i0 + e >= d.r0 && i0 + e < d.r1) ? p[e] : (T)0;
+          }
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[m] += (double)v[e] * xv[e];
+        }
+      }
+    }
   }
+  halve_step<32>(acc, lane & 32, 32);
+  halve_step<16>(acc, lane & 16, 16);
+  halve_step<8>(acc, lane & 8, 8);
+  halve_step<4>(acc, lane & 4, 4);
+  halve_step<2>(acc, lane & 2, 2);
+  acc[0] += __shfl_xor(acc[0], 1, 64);
+  const int c = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+                ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  if ((lane & 1) == 0 && c < d.bw) part[d.part_off + c] = acc[0];
 }
 
 // Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of partials).
+// Two threads per column sum the partials (fixed order, four independent
+// accumulators each); column k of the inverse is contiguous, so lanes run
+// along it and each wave reduces its 32 columns by recursive halving.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
                                                 const double* part) {
-  __shared__ double z[128];
+  __shared__ double z[128], zp[128];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int f = P.sfirst[d.sn], nb = P.nb, bw = d.bw;
-  const T* I = inv + d.inv_off;
-  const int tid = threadIdx.x;
-  if (tid < bw) {
-    double s = 0.0;
-    for (int q = 0; q < d.nparts; ++q) s += part[d.part_off + (int64_t)q * nb + tid];
-    z[tid] = ys[f + d.c0 + tid] - s;
+  const int tid = threadIdx.x, c = tid & 127, half = tid >> 7;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c < bw) {
+    const double* pp = part + d.part_off + c;
+    int q = half;
+    for (; q + 6 < d.nparts; q += 8) {
+      s0 += pp[(int64_t)q * nb];
+      s1 += pp[(int64_t)(q + 2) * nb];
+      s2 += pp[(int64_t)(q + 4) * nb];
+      s3 += pp[(int64_t)(q + 6) * nb];
+    }
+    for (; q < d.nparts; q += 2) s0 += pp[(int64_t)q * nb];
   }
+  if (half) zp[c] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (tid < bw) {
-    double acc = 0.0;
-    for (int c = tid; c < bw; ++c) acc += (double)I[c + (int64_t)tid * nb] * z[c];
-    ys[f + d.c0 + tid] = acc;
+  if (!half) z[c] = c < bw ? ys[f + d.c0 + c] - (((s0 + s1) + (s2 + s3)) + zp[c]) : 0.0;
+  __syncthreads();
+  const T* I = inv + P.sinv[d.sn] + (int64_t)(d.c0 / nb) * nb * nb;
+  const int lane = tid & 63, wave = tid >> 6, cb = wave * 32;
+  const double z1 = z[lane], z2 = z[lane + 64];
+  double acc[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const int k = cb + m;
+    const T v1 = (k < bw && lane >= k && lane < bw) ? I[lane + (int64_t)k * nb] : (T)0;
+    const T v2 = (k < bw && lane + 64 < bw) ? I[lane + 64 + (int64_t)k * nb] : (T)0;
+    acc[m] = (double)v1 * z1 + (double)v2 * z2;
   }
+  halve_step<32>(acc, lane & 32, 32);
+  halve_step<16>(acc, lane & 16, 16);
+  halve_step<8>(acc, lane & 8, 8);
+  halve_step<4>(acc, lane & 4, 4);
+  halve_step<2>(acc, lane & 2, 2);
+  acc[0] += __shfl_xor(acc[0], 1, 64);
+  const int col = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+                  ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  if ((lane & 1) == 0 && col < bw) ys[f + d.c0 + col] = acc[0];
 }
 
 // -------------------------------------------------------- IPM vectors
@@ -1155,10 +1322,12 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
       else k_potrf<T, 128><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
       break;
     case OP_TRSM:
-    case OP_UPDATE:
-      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g, BS, 0, s>>>(P, op.begin, op.end, panel, ubuf, inv);
-      else k_gemm_f32<<<g, BS, 0, s>>>(P, op.begin, op.end, panel, ubuf, inv);
+    case OP_UPDATE: {
+      const unsigned g8 = (unsigned)((op.grid + 7) / 8 * 8);
+      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g8, BS, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      else k_gemm_f32<<<g8, BS, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
       break;
+    }
   }
 }
 template void launch_factor_op<double>(const Op&, const DevPlan&, double*, double*, double*, int*, hipStream_t);
@@ -1191,7 +1360,7 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
   const unsigned g = (unsigned)op.grid;
   switch (op.type) {
     case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec); break;
-    case OP_FWD_GATHER: k_fwd_gather<<<g, BS, 0, s>>>(P, op.begin, xp, uvec); break;
+    case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec); break;
     case OP_FWD_STEP: k_fwd_step<T><<<g, BS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
     case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
     case OP_BWD_PART: k_bwd_part<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, part); break;

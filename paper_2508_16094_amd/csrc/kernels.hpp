@@ -23,7 +23,7 @@ struct DevPlan {
   int64_t ns, n;
   int nb, small_h;
   const int32_t *sfirst, *sw, *sh, *sld, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
-  const int64_t *spanel, *su, *srow, *suv;
+  const int64_t *spanel, *su, *srow, *suv, *sinv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
   const SolveDesc* sdesc; const int32_t *ssmall, *slarge;
 };
