@@ -88,8 +88,8 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the hot path is single-GPU (see DESIGN.md, "
-              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        print(f"--gpus {args.gpus}: the solver runs one instance on one GPU; multi-GPU sharding "
+              "(etree subtrees per GPU) is not implemented, run with --gpus 1", file=sys.stderr)
         return 2
     import torch
     from paper_2508_16094_amd import lib as L
