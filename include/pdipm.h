@@ -90,6 +90,8 @@ typedef struct ipm_options {
   int32_t fp64_fallback; /* FP32 form: reserve FP64 factor space so that FP64
                             factors take over when FP32 refinement cannot reach
                             the accuracy an iteration needs (default 1) */
+  int32_t use_graphs;    /* batched solve: 1 replays captured HIP graphs
+                            (default), 0 launches the same kernels eagerly */
 } ipm_options;
 
 typedef struct kkt_symbolic_stats {
@@ -245,6 +247,68 @@ int ipm_set_profiling(ipm_handle* h, int enable);
 int ipm_get_profile(ipm_handle* h, ipm_profile* out);
 
 void ipm_destroy(ipm_handle* h);
+
+/* ---------------------------------------------------------------------------
+ * Batched solve (many independent LP/QP instances, Section 5 on throughput
+ * for small instances): the instances are held as one block-diagonal
+ * problem, so symbolic analysis, assembly, factorisation and the triangular
+ * solves run once over all of them (each level of the elimination forest is
+ * one launch across instances), while step lengths, centring and
+ * termination are per instance.  An iteration is two replays of captured
+ * HIP graphs (termination measures; Newton step); the host only reads the
+ * count of running instances between them.  FP32 form: FP32 factor, a fixed
+ * number min(ir_max, 3) of FP64 refinement steps per solve, and FP64 factors
+ * for all instances from the first iteration in which a running instance
+ * misses its refinement target 1e-2 tol (1 + ||grad f||) (when fp64_fallback).
+ * Instances must have W empty and q4 NULL (LP or QP).
+ * ------------------------------------------------------------------------- */
+typedef struct ipm_batch ipm_batch;
+
+typedef struct ipm_batch_info {
+  int32_t iterations;      /* Newton iterations run (the slowest instance) */
+  int32_t solved;          /* instances that reached status PDIPM_OK */
+  int32_t graph_launches;  /* HIP graph replays */
+  int32_t fp64_from;       /* iteration from which FP64 factors were used, -1 never */
+  int32_t factor_failures; /* factorisations that met a non-positive pivot */
+  int32_t refine_misses;   /* iterations in which an instance missed its target */
+  int32_t blocking;        /* blocking candidate used */
+  int32_t pad;
+  double ms_total;         /* wall time of ipm_batch_solve */
+  double ms_capture;       /* of which graph capture and instantiation */
+} ipm_batch_info;
+
+/* Create a batch of count instances (host arrays copied; count >= 1).
+ * Instance i owns columns xoff[i]..xoff[i+1]-1 and rows roff[i]..roff[i+1]-1
+ * of the concatenated vectors (ipm_batch_offsets).  Errors as ipm_create,
+ * message in ipm_batch_last_error(NULL). */
+int ipm_batch_create(int32_t count, const ipm_problem_desc* probs, const ipm_options* opts,
+                     ipm_batch** out);
+int ipm_batch_analyze(ipm_batch* b, kkt_symbolic_stats* out);
+/* xoff, roff: host arrays of count + 1 entries */
+int ipm_batch_offsets(ipm_batch* b, int64_t* xoff, int64_t* roff);
+int ipm_batch_workspace_query(ipm_batch* b, size_t* bytes);
+/* Device workspace (caller-owned, 256-byte aligned, >= queried bytes) */
+int ipm_batch_set_workspace(ipm_batch* b, void* d_workspace, size_t bytes);
+/* Stream of the graph launches; with the null stream the batch creates a
+ * private non-blocking stream (graph capture needs one). */
+int ipm_batch_set_stream(ipm_batch* b, void* hip_stream);
+/* Blocking candidates of the autotuner: small_h (fronts of at most this
+ * height factor in one workgroup) and outer_blocks (trailing-update rank in
+ * diagonal blocks); arrays of *count entries, either may be NULL. */
+int ipm_batch_blockings(ipm_batch* b, int32_t* count, int32_t* small_h, int32_t* outer_blocks);
+int ipm_batch_set_blocking(ipm_batch* b, int32_t index);
+/* Times reps factorisations per candidate at the cold start point, keeps the
+ * fastest; ms (NULL or count entries) receives each candidate's best time. */
+int ipm_batch_autotune(ipm_batch* b, int32_t reps, int32_t* chosen, double* ms);
+/* Solve every instance.  start: NULL (cold) or concatenated x (sum n_i) and
+ * lambda (sum m_i), pushed into the interior per instance.  res: NULL or
+ * count results (status, iterations, f, P, D, C, mu per instance). */
+int ipm_batch_solve(ipm_batch* b, const ipm_start* start, ipm_result* res, ipm_batch_info* info);
+/* Concatenated final iterates (memspace PDIPM_HOST/DEVICE; NULL skipped). */
+int ipm_batch_get_solution(ipm_batch* b, double* x, double* s, double* lam, double* zl, double* zu,
+                           int memspace);
+const char* ipm_batch_last_error(const ipm_batch* b);
+void ipm_batch_destroy(ipm_batch* b);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
 #include "pdipm.h"
@@ -33,6 +34,20 @@ struct Region {
 
 template <typename T>
 size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
+
+// Largest plan arrays over the blocking candidates of a batch (the
+// workspace is laid out for all of them, so switching needs no new memory).
+struct PlanCaps {
+  size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0;
+  int64_t inv = 0, part = 1;
+  void add(const Plan& P) {
+    gemm = std::max(gemm, bytes_of(P.gemm)); potrf = std::max(potrf, bytes_of(P.potrf));
+    ext = std::max(ext, bytes_of(P.ext)); small = std::max(small, bytes_of(P.small));
+    sdesc = std::max(sdesc, bytes_of(P.sdesc)); ssmall = std::max(ssmall, bytes_of(P.ssmall));
+    slarge = std::max(slarge, bytes_of(P.slarge));
+    inv = std::max(inv, P.inv_elems); part = std::max(part, P.part_elems);
+  }
+};
 
 }  // namespace
 
@@ -96,6 +111,18 @@ struct ipm_handle {
   bool profiling = false;
   std::vector<hipEvent_t> pev;
   ipm_profile prof{};
+  // batched solve: bcount > 0 when the handle holds a block-diagonal batch
+  int32_t bcount = 0;
+  std::vector<int64_t> bxoff, broff;
+  std::vector<int32_t> bix, bir, blp;
+  std::vector<double> bnc;
+  std::vector<Blocking> bcand;
+  int32_t bblocking = 0;
+  PlanCaps cap64, cap32;
+  BatchDev bd{};
+  hipStream_t own_stream = nullptr;
+  hipGraphExec_t gstats = nullptr, gstep[2] = {nullptr, nullptr};
+  struct BOff { size_t xoff, roff, ix, ir, nc, lp, st, ist, flags; } bo{};
 };
 
 namespace {
@@ -114,8 +141,23 @@ int fail(ipm_handle* h, int code, const std::string& msg) {
   } while (0)
 
 void finish_analysis(ipm_handle* h) {
-  build_plan(h->sym, 8, &h->plan64);
-  build_plan(h->sym, 4, &h->plan32);
+  if (h->bcount > 0) {
+    // blocking candidates of the autotuner; the workspace fits each of them
+    for (int sh : {64, 32})
+      for (int ob : {4, 2, 1}) h->bcand.push_back(Blocking{sh, ob});
+    for (const Blocking& b : h->bcand) {
+      Plan t;
+      build_plan(h->sym, 8, &t, b);
+      h->cap64.add(t);
+      build_plan(h->sym, 4, &t, b);
+      h->cap32.add(t);
+    }
+    build_plan(h->sym, 8, &h->plan64, h->bcand[0]);
+    build_plan(h->sym, 4, &h->plan32, h->bcand[0]);
+  } else {
+    build_plan(h->sym, 8, &h->plan64);
+    build_plan(h->sym, 4, &h->plan32);
+  }
   map_k_to_panels(h->sym, h->plan64, &h->km);
   if (h->standalone) {
     // symmetric pattern of the stored lower K for products K v
@@ -169,31 +211,36 @@ void layout(ipm_handle* h) {
   o.lsn = r.take(bytes_of(P.level_sn)); o.snrows = r.take(bytes_of(h->sym.sn_rows));
   o.perm = r.take(bytes_of(h->sym.perm)); o.spanel = r.take(bytes_of(P.spanel)); o.su = r.take(bytes_of(P.su));
   o.srow = r.take(bytes_of(P.srow)); o.suv = r.take(bytes_of(P.suv));
-  o.ext = r.take(bytes_of(P.ext)); o.small = r.take(bytes_of(P.small));
+  // plan arrays: a batch reserves the largest size over its blocking candidates
+  PlanCaps c64, c32;
+  c64.add(h->plan64);
+  c32.add(h->plan32);
+  if (h->bcount > 0) { c64 = h->cap64; c32 = h->cap32; }
+  o.ext = r.take(std::max(c64.ext, c32.ext)); o.small = r.take(std::max(c64.small, c32.small));
   if (h->need64) {
-    o.gemm64 = r.take(bytes_of(h->plan64.gemm)); o.potrf64 = r.take(bytes_of(h->plan64.potrf));
-    o.sdesc64 = r.take(bytes_of(h->plan64.sdesc)); o.ssmall64 = r.take(bytes_of(h->plan64.ssmall));
+    o.gemm64 = r.take(c64.gemm); o.potrf64 = r.take(c64.potrf);
+    o.sdesc64 = r.take(c64.sdesc); o.ssmall64 = r.take(c64.ssmall);
     o.sinv64 = r.take(bytes_of(h->plan64.sinv));
-    o.slarge64 = r.take(bytes_of(h->plan64.slarge));
+    o.slarge64 = r.take(c64.slarge);
   }
   if (h->need32) {
-    o.gemm32 = r.take(bytes_of(h->plan32.gemm)); o.potrf32 = r.take(bytes_of(h->plan32.potrf));
-    o.sdesc32 = r.take(bytes_of(h->plan32.sdesc)); o.ssmall32 = r.take(bytes_of(h->plan32.ssmall));
+    o.gemm32 = r.take(c32.gemm); o.potrf32 = r.take(c32.potrf);
+    o.sdesc32 = r.take(c32.sdesc); o.ssmall32 = r.take(c32.ssmall);
     o.sinv32 = r.take(bytes_of(h->plan32.sinv));
-    o.slarge32 = r.take(bytes_of(h->plan32.slarge));
+    o.slarge32 = r.take(c32.slarge);
   }
   const size_t es = h->need64 ? 8 : 4;
   o.panel = r.take((size_t)P.panel_elems * es);
   o.ubuf = r.take((size_t)std::max<int64_t>(1, P.u_elems) * es);
-  size_t inv64 = h->need64 ? (size_t)h->plan64.inv_elems * 8 : 0;
-  size_t inv32 = h->need32 ? (size_t)h->plan32.inv_elems * 4 : 0;
+  size_t inv64 = h->need64 ? (size_t)c64.inv * 8 : 0;
+  size_t inv32 = h->need32 ? (size_t)c32.inv * 4 : 0;
   o.inv = r.take(std::max(inv64, inv32));
   o.bad = r.take(64);
   o.partials = r.take((8 * RED_BLOCKS + 16) * sizeof(double));
   o.xperm = r.take(n * 8);
   o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
   o.ysol = r.take(n * 8);
-  o.part = r.take((size_t)std::max(h->need64 ? h->plan64.part_elems : 1, h->need32 ? h->plan32.part_elems : 1) * 8);
+  o.part = r.take((size_t)std::max(h->need64 ? c64.part : 1, h->need32 ? c32.part : 1) * 8);
   // vectors: 0..47 (n or m sized)
   const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
@@ -210,6 +257,14 @@ void layout(ipm_handle* h) {
       nv, nv, nv, nv, mv,          // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
       nv};                         // 48 cg direction
   for (int i = 0; i < 49; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+  if (h->bcount > 0) {
+    auto& b = h->bo;
+    b.xoff = r.take(bytes_of(h->bxoff)); b.roff = r.take(bytes_of(h->broff));
+    b.ix = r.take(bytes_of(h->bix)); b.ir = r.take(std::max<size_t>(4, bytes_of(h->bir)));
+    b.nc = r.take(bytes_of(h->bnc)); b.lp = r.take(bytes_of(h->blp));
+    b.st = r.take((size_t)h->bcount * BST_N * 8); b.ist = r.take((size_t)h->bcount * IST_N * 4);
+    b.flags = r.take(BF_N * 4);
+  }
   h->ws_need = r.off;
 }
 
@@ -223,6 +278,21 @@ int upload(ipm_handle* h, size_t off, const void* src, size_t bytes) {
 }
 
 #define UP(off, vec) do { int rc_ = upload(h, h->o.off, vec.data(), bytes_of(vec)); if (rc_) return rc_; } while (0)
+
+// Launch descriptors of the current plans (they change with the blocking).
+int upload_plans(ipm_handle* h) {
+  const Plan& P = h->plan64;
+  UP(ext, P.ext); UP(small, P.small);
+  if (h->need64) {
+    UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc); UP(sinv64, h->plan64.sinv);
+    UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge);
+  }
+  if (h->need32) {
+    UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc); UP(sinv32, h->plan32.sinv);
+    UP(ssmall32, h->plan32.ssmall); UP(slarge32, h->plan32.slarge);
+  }
+  return PDIPM_OK;
+}
 
 int bind_workspace(ipm_handle* h) {
   auto& o = h->o;
@@ -239,14 +309,24 @@ int bind_workspace(ipm_handle* h) {
   const Plan& P = h->plan64;
   UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(sld, P.sld); UP(cptr, P.child_ptr); UP(child, P.child);
   UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
-  UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv); UP(ext, P.ext); UP(small, P.small);
-  if (h->need64) {
-    UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc); UP(sinv64, h->plan64.sinv);
-    UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge);
-  }
-  if (h->need32) {
-    UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc); UP(sinv32, h->plan32.sinv);
-    UP(ssmall32, h->plan32.ssmall); UP(slarge32, h->plan32.slarge);
+  UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv);
+  int rcp = upload_plans(h);
+  if (rcp) return rcp;
+  if (h->bcount > 0) {
+    auto& b = h->bo;
+    int rc2;
+    if ((rc2 = upload(h, b.xoff, h->bxoff.data(), bytes_of(h->bxoff)))) return rc2;
+    if ((rc2 = upload(h, b.roff, h->broff.data(), bytes_of(h->broff)))) return rc2;
+    if ((rc2 = upload(h, b.ix, h->bix.data(), bytes_of(h->bix)))) return rc2;
+    if ((rc2 = upload(h, b.ir, h->bir.data(), bytes_of(h->bir)))) return rc2;
+    if ((rc2 = upload(h, b.nc, h->bnc.data(), bytes_of(h->bnc)))) return rc2;
+    if ((rc2 = upload(h, b.lp, h->blp.data(), bytes_of(h->blp)))) return rc2;
+    BatchDev& d = h->bd;
+    d.count = h->bcount;
+    d.xoff = at<int64_t>(h, b.xoff); d.roff = at<int64_t>(h, b.roff);
+    d.ix = at<int32_t>(h, b.ix); d.ir = at<int32_t>(h, b.ir);
+    d.nc = at<double>(h, b.nc); d.lp = at<int32_t>(h, b.lp);
+    d.st = at<double>(h, b.st); d.ist = at<int32_t>(h, b.ist); d.flags = at<int32_t>(h, b.flags);
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   // device views
@@ -743,6 +823,259 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
   return status;
 }
 
+// ------------------------------------------------------------ batched solve
+// Many LP/QP instances are held as one block-diagonal problem: symbolic
+// analysis, assembly, factorisation and triangular solves treat them as
+// one matrix (instances are independent diagonal blocks, so every level of
+// the plan is one launch over all instances), while step lengths, centring
+// and termination are per instance.  Each iteration is two captured HIP
+// graphs: termination measures, then the Newton step.
+
+int set_blocking(ipm_handle* h, int idx) {
+  if (idx < 0 || idx >= (int)h->bcand.size()) return fail(h, PDIPM_ERR_INVALID_ARG, "blocking index out of range");
+  build_plan(h->sym, 8, &h->plan64, h->bcand[idx]);
+  build_plan(h->sym, 4, &h->plan32, h->bcand[idx]);
+  h->bblocking = idx;
+  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
+    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  if (!h->ws_ready) return PDIPM_OK;
+  int rc = upload_plans(h);
+  if (rc) return rc;
+  h->dpl64.small_h = h->plan64.small_h;
+  h->dpl32.small_h = h->plan32.small_h;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
+// Panels of the current K values and the factorisation, all on the device
+// (a non-positive pivot is recorded in h->bad and replaced by one).
+void batch_factor(ipm_handle* h, int prec) {
+  const Plan& P = prec == PDIPM_FP64 ? h->plan64 : h->plan32;
+  const DevPlan& D = prec == PDIPM_FP64 ? h->dpl64 : h->dpl32;
+  const size_t es = prec == PDIPM_FP64 ? 8 : 4;
+  launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
+  if (prec == PDIPM_FP64) {
+    launch_set_values<double>(h->dk, h->kval, (double*)h->panel, h->stream);
+    h->scaled = false;
+  } else {
+    launch_diag_scale(h->sym.n, at<int64_t>(h, h->o.kmkp), h->kval, h->dscale, h->partials, h->stream);
+    launch_set_scaled<float>(h->dk, h->kval, h->dscale, 0.0, (float*)h->panel, h->stream);
+    h->scaled = true;
+  }
+  launch_set_int(h->bad, INT_MAX, h->stream);
+  launch_fill_bytes0(h->ubuf, (int64_t)std::max<int64_t>(1, P.u_elems) * es, h->stream);
+  for (const Op& op : P.ops) {
+    if (prec == PDIPM_FP64)
+      launch_factor_op<double>(op, D, (double*)h->panel, (double*)h->ubuf, (double*)h->inv, h->bad, h->stream);
+    else
+      launch_factor_op<float>(op, D, (float*)h->panel, (float*)h->ubuf, (float*)h->inv, h->bad, h->stream);
+  }
+  h->factor_prec = prec;
+}
+
+// Solve with a fixed number of FP64 refinement steps, then flag the running
+// instances whose residual misses their target.
+void batch_solve_fixed(ipm_handle* h, const double* rhs, double* out, int steps) {
+  const int64_t n = h->sym.n;
+  trisolve(h, rhs, out);
+  for (int k = 0; k < steps; ++k) {
+    kmul(h, out, h->ir_kx);
+    launch_residual_norms(n, rhs, h->ir_kx, out, h->ir_r, h->partials, h->stream);
+    trisolve(h, h->ir_r, h->ir_c);
+    launch_add(n, out, h->ir_c, h->stream);
+  }
+  kmul(h, out, h->ir_kx);
+  launch_residual_norms(n, rhs, h->ir_kx, out, h->ir_r, h->partials, h->stream);
+  launch_batch_check_residual(h->bd, h->ir_r, h->stream);
+}
+
+void batch_stats_ops(ipm_handle* h) {
+  evaluate_point(h, h->v, true);
+  launch_set_int(h->bd.flags + BF_ACTIVE, 0, h->stream);
+  launch_batch_stats(h->dp, h->bd, h->v, h->opt.tol, h->opt.max_iter, h->stream);
+}
+
+void batch_step_ops(ipm_handle* h, int prec) {
+  const DevProblem& P = h->dp;
+  IpmVecs& v = h->v;
+  const ipm_options& O = h->opt;
+  const int steps = prec == PDIPM_FP64 ? 1 : std::max(1, std::min(O.ir_max, 3));
+  launch_batch_clear_miss(h->bd, h->stream);
+  launch_sigmas(P, v, O.delta_d, h->stream);
+  assemble_values(h, O.delta_p);
+  batch_factor(h, prec);
+  auto direction = [&](const double* tsv, const double* tlv, const double* tuv, double* dx, double* ds,
+                       double* dl, double* dzl, double* dzu) {
+    launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
+    batch_solve_fixed(h, h->rhs, dx, steps);
+    launch_recover(P, v, dx, tsv, tlv, tuv, O.delta_d, ds, dl, dzl, dzu, h->stream);
+  };
+  direction(nullptr, nullptr, nullptr, h->dxa, h->dsa, h->dla, h->dzla, h->dzua);
+  launch_batch_predict(P, h->bd, v, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, h->stream);
+  launch_batch_targets(P, h->bd, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, h->ts, h->tl, h->tu, h->stream);
+  direction(h->ts, h->tl, h->tu, h->dx, h->ds, h->dl, h->dzl, h->dzu);
+  launch_batch_correct(P, h->bd, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->stream);
+  launch_batch_update(P, h->bd, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->stream);
+  launch_batch_next(h->bd, h->stream);
+}
+
+template <typename F>
+int capture(ipm_handle* h, hipGraphExec_t* out, F&& record) {
+  hipGraph_t g = nullptr;
+  HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+  record();
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (e != hipSuccess) return fail(h, PDIPM_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, PDIPM_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return PDIPM_OK;
+}
+
+int ensure_stream(ipm_handle* h) {
+  if (h->stream) return PDIPM_OK;
+  if (!h->own_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+  HIPCHK(h, hipDeviceSynchronize());
+  h->stream = h->own_stream;
+  return PDIPM_OK;
+}
+
+// Start point of every instance (cold, or a pushed warm start).
+int batch_start(ipm_handle* h, const ipm_start* st) {
+  const DevProblem& P = h->dp;
+  IpmVecs& v = h->v;
+  launch_copy(P.nnz_j, v.jv, P.ja, h->stream);
+  launch_copy(P.nnz_h, v.hv, P.hq, h->stream);
+  launch_batch_init(h->bd, h->stream);
+  if (st) {
+    const hipMemcpyKind kd = st->memspace == PDIPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(h, hipMemcpyAsync(h->xhat, st->x, P.n * 8, kd, h->stream));
+    if (P.m) HIPCHK(h, hipMemcpyAsync(h->lamhat, st->lam, P.m * 8, kd, h->stream));
+    launch_push_start(P, v, h->xhat, h->lamhat, 0, h->stream);
+    launch_batch_push_duals(P, h->bd, v, h->stream);
+  } else {
+    launch_init_point(P, v, h->stream);
+  }
+  return PDIPM_OK;
+}
+
+int run_batch(ipm_handle* h, const ipm_start* st, ipm_result* res, ipm_batch_info* info) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto ms_since = [&](clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); };
+  int rc = ensure_stream(h);
+  if (rc) return rc;
+  h->profiling = false;
+  const ipm_options& O = h->opt;
+  ipm_batch_info I{};
+  I.blocking = h->bblocking;
+  I.fp64_from = -1;
+  if ((rc = batch_start(h, st))) return rc;
+  const bool graphs = O.use_graphs != 0;
+  const auto tc = clk::now();
+  if (graphs && !h->gstats && (rc = capture(h, &h->gstats, [&] { batch_stats_ops(h); }))) return rc;
+  I.ms_capture += ms_since(tc);
+  bool stay64 = O.precision == PDIPM_FP64;
+  int it = 0;
+  int32_t hflags[BF_N];
+  int hbad = INT_MAX;
+  bool timed_out = false;
+  while (true) {
+    if (graphs) HIPCHK(h, hipGraphLaunch(h->gstats, h->stream));
+    else batch_stats_ops(h);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hflags, h->bd.flags, sizeof(hflags), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&hbad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (graphs) I.graph_launches++;
+    if (it > 0) {
+      if (hbad != INT_MAX) I.factor_failures++;
+      if ((hflags[BF_REFINE_MISS] > 0 || hbad != INT_MAX) && !stay64 && O.fp64_fallback && h->need64) {
+        stay64 = true;
+        I.fp64_from = it;
+      }
+      if (hflags[BF_REFINE_MISS] > 0) I.refine_misses++;
+    }
+    if (O.print_level > 0)
+      fprintf(stderr, "batch it %3d running %d refine-miss %d bad %d fac %s\n", it, hflags[BF_ACTIVE],
+              hflags[BF_REFINE_MISS], hbad == INT_MAX ? -1 : hbad, stay64 ? "fp64" : "fp32");
+    if (hflags[BF_ACTIVE] == 0 || it > O.max_iter) break;
+    if (ms_since(t0) > O.max_wall_time * 1e3) { timed_out = true; break; }
+    const int gi = stay64 ? 1 : 0;
+    const int sprec = stay64 ? PDIPM_FP64 : PDIPM_FP32;
+    if (graphs) {
+      if (!h->gstep[gi]) {
+        const auto tg = clk::now();
+        if ((rc = capture(h, &h->gstep[gi], [&] { batch_step_ops(h, sprec); }))) return rc;
+        I.ms_capture += ms_since(tg);
+      }
+      HIPCHK(h, hipGraphLaunch(h->gstep[gi], h->stream));
+      I.graph_launches++;
+    } else {
+      batch_step_ops(h, sprec);
+    }
+    HIPCHK(h, hipGetLastError());
+    ++it;
+  }
+  std::vector<double> hst((size_t)h->bcount * BST_N);
+  std::vector<int32_t> hist((size_t)h->bcount * IST_N);
+  HIPCHK(h, hipMemcpyAsync(hst.data(), h->bd.st, hst.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(hist.data(), h->bd.ist, hist.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  I.iterations = it;
+  I.ms_total = ms_since(t0);
+  for (int32_t b = 0; b < h->bcount; ++b) {
+    const double* s = hst.data() + (size_t)b * BST_N;
+    const int32_t* q = hist.data() + (size_t)b * IST_N;
+    int status = q[IST_STATUS];
+    if (!q[IST_DONE]) status = timed_out ? PDIPM_TIME_LIMIT : PDIPM_MAX_ITER;
+    if (status == PDIPM_OK) I.solved++;
+    if (res) {
+      ipm_result R{};
+      R.status = status;
+      R.iterations = q[IST_ITERS];
+      R.f = s[BST_F]; R.P = s[BST_P]; R.D = s[BST_D]; R.C = s[BST_C]; R.mu = s[BST_MU];
+      R.ms_total = I.ms_total;
+      res[b] = R;
+    }
+  }
+  h->solved = true;
+  if (info) *info = I;
+  return PDIPM_OK;
+}
+
+// Time one factorisation per blocking candidate at the cold start point and
+// keep the fastest (ties: the lower index).
+int batch_autotune(ipm_handle* h, int32_t* chosen, double* ms_out, int reps) {
+  int rc = ensure_stream(h);
+  if (rc) return rc;
+  const int prec = h->opt.precision;
+  double best = INFINITY;
+  int besti = 0;
+  for (int c = 0; c < (int)h->bcand.size(); ++c) {
+    if ((rc = set_blocking(h, c))) return rc;
+    if ((rc = batch_start(h, nullptr))) return rc;
+    evaluate_point(h, h->v, true);
+    launch_sigmas(h->dp, h->v, h->opt.delta_d, h->stream);
+    assemble_values(h, h->opt.delta_p);
+    double tmin = INFINITY;
+    for (int r = 0; r < std::max(1, reps); ++r) {
+      HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+      batch_factor(h, prec);
+      HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      float ms = 0;
+      hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      tmin = std::min(tmin, (double)ms);
+    }
+    if (ms_out) ms_out[c] = tmin;
+    if (tmin < best) { best = tmin; besti = c; }
+  }
+  if ((rc = set_blocking(h, besti))) return rc;
+  if (chosen) *chosen = besti;
+  return PDIPM_OK;
+}
+
 }  // namespace
 
 // ================================================================= ABI
@@ -762,6 +1095,7 @@ void ipm_default_options(ipm_options* o) {
   o->amalg_menu = 0;
   o->print_level = 0;
   o->fp64_fallback = 1;
+  o->use_graphs = 1;
 }
 
 const char* ipm_status_string(int s) {
@@ -1099,10 +1433,203 @@ int ipm_get_solution(ipm_handle* h, double* x, double* s, double* lam, double* z
 
 void ipm_destroy(ipm_handle* h) {
   if (!h) return;
+  for (hipGraphExec_t g : {h->gstats, h->gstep[0], h->gstep[1]})
+    if (g) hipGraphExecDestroy(g);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (hipEvent_t e : h->pev) hipEventDestroy(e);
+  if (h->own_stream) {
+    hipStreamSynchronize(h->own_stream);
+    hipStreamDestroy(h->own_stream);
+  }
   delete h;
+}
+
+// ------------------------------------------------------------ batch ABI
+struct ipm_batch {
+  ipm_handle* h = nullptr;
+};
+
+int ipm_batch_create(int32_t count, const ipm_problem_desc* probs, const ipm_options* opts, ipm_batch** out) {
+  if (!out) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !probs) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "count must be >= 1 with problems");
+  int64_t N = 0, M = 0, nnzA = 0, nnzQ = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const ipm_problem_desc& d = probs[i];
+    if (d.n <= 0 || d.m < 0) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": bad sizes");
+    if (d.W.rowptr && d.W.rowptr[d.m] > 0)
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": batches take LP/QP instances (W empty)");
+    if (d.q4)
+      for (int64_t j = 0; j < d.n; ++j)
+        if (d.q4[j] != 0.0)
+          return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": batches take LP/QP instances (q4 zero)");
+    if (d.m > 0 && (!d.A.rowptr || !d.b))
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": rows need A and b");
+    N += d.n; M += d.m;
+    nnzA += d.A.rowptr ? d.A.rowptr[d.m] : 0;
+    nnzQ += d.Q.rowptr ? d.Q.rowptr[d.n] : 0;
+  }
+  if (N >= (1ll << 31) || M >= (1ll << 31)) return fail(nullptr, PDIPM_ERR_INVALID_ARG, "batch too large for int32 indices");
+  // concatenated block-diagonal problem
+  std::vector<double> c(N), b(M), xl(N), xu(N), av, qv;
+  std::vector<int64_t> arp(M + 1, 0), qrp(N + 1, 0);
+  std::vector<int32_t> aci, qci;
+  av.reserve(nnzA); aci.reserve(nnzA); qv.reserve(nnzQ); qci.reserve(nnzQ);
+  ipm_handle* h = new (std::nothrow) ipm_handle();
+  if (!h) return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (opts) h->opt = *opts; else ipm_default_options(&h->opt);
+  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+  }
+  h->bcount = count;
+  h->bxoff.assign(count + 1, 0);
+  h->broff.assign(count + 1, 0);
+  h->bix.resize(N);
+  h->bir.resize(M);
+  h->blp.resize(count);
+  h->bnc.resize(count);
+  int64_t x0 = 0, r0 = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const ipm_problem_desc& d = probs[i];
+    if (!d.c) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": c is required"); }
+    int64_t nb = 0;
+    for (int64_t j = 0; j < d.n; ++j) {
+      c[x0 + j] = d.c[j];
+      xl[x0 + j] = d.xl ? d.xl[j] : -INFINITY;
+      xu[x0 + j] = d.xu ? d.xu[j] : INFINITY;
+      nb += std::isfinite(xl[x0 + j]) + std::isfinite(xu[x0 + j]);
+      h->bix[x0 + j] = i;
+      const int64_t e0 = d.Q.rowptr ? d.Q.rowptr[j] : 0, e1 = d.Q.rowptr ? d.Q.rowptr[j + 1] : 0;
+      for (int64_t e = e0; e < e1; ++e) {
+        qci.push_back((int32_t)(d.Q.colind[e] + x0));
+        qv.push_back(d.Q.val[e]);
+      }
+      qrp[x0 + j + 1] = (int64_t)qci.size();
+    }
+    for (int64_t k = 0; k < d.m; ++k) {
+      b[r0 + k] = d.b[k];
+      h->bir[r0 + k] = i;
+      for (int64_t e = d.A.rowptr[k]; e < d.A.rowptr[k + 1]; ++e) {
+        if (d.A.colind[e] < 0 || d.A.colind[e] >= d.n) {
+          delete h;
+          return fail(nullptr, PDIPM_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": A column out of range");
+        }
+        aci.push_back((int32_t)(d.A.colind[e] + x0));
+        av.push_back(d.A.val[e]);
+      }
+      arp[r0 + k + 1] = (int64_t)aci.size();
+    }
+    h->blp[i] = (d.Q.rowptr && d.Q.rowptr[d.n] > 0) ? 0 : 1;
+    h->bnc[i] = (double)(d.m + nb);
+    x0 += d.n; r0 += d.m;
+    h->bxoff[i + 1] = x0;
+    h->broff[i + 1] = r0;
+  }
+  ipm_problem_desc u{};
+  u.n = N; u.m = M; u.c = c.data(); u.b = M ? b.data() : nullptr;
+  u.A = pdipm_csr{M, N, arp.data(), aci.data(), av.data()};
+  if (nnzQ > 0) u.Q = pdipm_csr{N, N, qrp.data(), qci.data(), qv.data()};
+  u.xl = xl.data(); u.xu = xu.data();
+  std::string e = build_problem(&u, &h->hp);
+  if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
+  try {
+    build_graph_from_problem(h->hp, &h->graph);
+    build_kmap_problem(h->hp, &h->km);
+  } catch (const std::exception& ex) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());
+  }
+  ipm_handle* hh = nullptr;
+  int rc = finish_create(h, opts, &hh);
+  if (rc) return rc;
+  ipm_batch* bt = new (std::nothrow) ipm_batch();
+  if (!bt) { ipm_destroy(hh); return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed"); }
+  bt->h = hh;
+  *out = bt;
+  return PDIPM_OK;
+}
+
+int ipm_batch_analyze(ipm_batch* b, kkt_symbolic_stats* out) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  return kkt_analyze(b->h, out);
+}
+
+int ipm_batch_offsets(ipm_batch* b, int64_t* xoff, int64_t* roff) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  if (xoff) memcpy(xoff, b->h->bxoff.data(), bytes_of(b->h->bxoff));
+  if (roff) memcpy(roff, b->h->broff.data(), bytes_of(b->h->broff));
+  return PDIPM_OK;
+}
+
+int ipm_batch_workspace_query(ipm_batch* b, size_t* bytes) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  return ipm_workspace_query(b->h, bytes);
+}
+
+int ipm_batch_set_workspace(ipm_batch* b, void* ws, size_t bytes) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  ipm_handle* h = b->h;
+  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
+    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  int rc = ensure_stream(h);
+  if (rc) return rc;
+  return ipm_set_workspace(h, ws, bytes);
+}
+
+int ipm_batch_set_stream(ipm_batch* b, void* stream) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  ipm_handle* h = b->h;
+  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
+    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  h->stream = (hipStream_t)stream;
+  return ensure_stream(h);
+}
+
+int ipm_batch_blockings(ipm_batch* b, int32_t* count, int32_t* small_h, int32_t* outer_blocks) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  const auto& c = b->h->bcand;
+  if (count) *count = (int32_t)c.size();
+  for (size_t i = 0; i < c.size(); ++i) {
+    if (small_h) small_h[i] = c[i].small_h;
+    if (outer_blocks) outer_blocks[i] = c[i].outer_blocks;
+  }
+  return PDIPM_OK;
+}
+
+int ipm_batch_set_blocking(ipm_batch* b, int32_t index) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  return set_blocking(b->h, index);
+}
+
+int ipm_batch_autotune(ipm_batch* b, int32_t reps, int32_t* chosen, double* ms) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  int rc = check_ready(b->h);
+  if (rc) return rc;
+  return batch_autotune(b->h, chosen, ms, reps);
+}
+
+int ipm_batch_solve(ipm_batch* b, const ipm_start* start, ipm_result* res, ipm_batch_info* info) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  int rc = check_ready(b->h);
+  if (rc) return rc;
+  return run_batch(b->h, start, res, info);
+}
+
+int ipm_batch_get_solution(ipm_batch* b, double* x, double* s, double* lam, double* zl, double* zu, int memspace) {
+  if (!b) return PDIPM_ERR_INVALID_ARG;
+  return ipm_get_solution(b->h, x, s, lam, zl, zu, memspace);
+}
+
+const char* ipm_batch_last_error(const ipm_batch* b) {
+  return b ? b->h->err.c_str() : g_create_error.c_str();
+}
+
+void ipm_batch_destroy(ipm_batch* b) {
+  if (!b) return;
+  ipm_destroy(b->h);
+  delete b;
 }
 
 }  // extern "C"

@@ -268,13 +268,14 @@ void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km)
   km->tp.clear();
 }
 
-void build_plan(const Symbolic& s, int esize, Plan* pl) {
+void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   Plan& P = *pl;
   P = Plan();
   P.esize = esize;
   P.nb = esize == 8 ? 64 : 128;            // diagonal block / panel-solve width
-  const int nbo = esize == 8 ? 256 : 512;  // outer block: rank of the trailing update
-  P.small_h = 64;
+  // outer block: rank of the trailing update (a multiple of nb)
+  const int nbo = P.nb * (blk.outer_blocks > 0 ? blk.outer_blocks : 4);
+  P.small_h = blk.small_h > 0 && blk.small_h <= 64 ? blk.small_h : 64;
   const int64_t ns = s.nsuper();
   P.ns = ns;
   P.n = s.n;

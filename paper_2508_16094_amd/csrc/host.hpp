@@ -133,7 +133,14 @@ void build_graph_from_problem(const HostProblem& p, Graph* g);
 void build_graph_from_lower(int64_t n, const int64_t* rp, const int32_t* ci, Graph* g);
 void build_kmap_problem(const HostProblem& p, KMap* km);
 void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km);
-void build_plan(const Symbolic& s, int precision_bytes, Plan* plan);
+// Blocking of the numeric plan: fronts of height <= small_h (at most 64) use
+// the one-workgroup LDS kernel; larger fronts take rank-(outer_blocks * nb)
+// trailing updates.
+struct Blocking {
+  int small_h = 64;
+  int outer_blocks = 4;
+};
+void build_plan(const Symbolic& s, int precision_bytes, Plan* plan, const Blocking& blk = Blocking());
 void map_k_to_panels(const Symbolic& s, const Plan& plan, KMap* km);
 
 }  // namespace pdipm

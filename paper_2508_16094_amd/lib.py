@@ -38,7 +38,7 @@ class ipm_options(ctypes.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("max_wall_time", _f64), ("delta_p", _f64),
                 ("delta_d", _f64), ("precision", _i32), ("ir_max", _i32), ("ir_tol", _f64),
                 ("nd_leaf", _i32), ("amalg_menu", _i32), ("print_level", _i32),
-                ("fp64_fallback", _i32)]
+                ("fp64_fallback", _i32), ("use_graphs", _i32)]
 
 
 class kkt_symbolic_stats(ctypes.Structure):
@@ -73,6 +73,12 @@ class ipm_result(ctypes.Structure):
                 ("fp64_refactors", _i32), ("inertia_corrections", _i32), ("max_ir_residual", _f64)]
 
 
+class ipm_batch_info(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("solved", _i32), ("graph_launches", _i32), ("fp64_from", _i32),
+                ("factor_failures", _i32), ("refine_misses", _i32), ("blocking", _i32), ("pad", _i32),
+                ("ms_total", _f64), ("ms_capture", _f64)]
+
+
 _SIGS = {
     "ipm_default_options": (None, [_p]),
     "ipm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -99,6 +105,19 @@ _SIGS = {
     "ipm_set_profiling": (ctypes.c_int, [_p, ctypes.c_int]),
     "ipm_get_profile": (ctypes.c_int, [_p, _p]),
     "ipm_destroy": (None, [_p]),
+    "ipm_batch_create": (ctypes.c_int, [_i32, _p, _p, _p]),
+    "ipm_batch_analyze": (ctypes.c_int, [_p, _p]),
+    "ipm_batch_offsets": (ctypes.c_int, [_p, _p, _p]),
+    "ipm_batch_workspace_query": (ctypes.c_int, [_p, _p]),
+    "ipm_batch_set_workspace": (ctypes.c_int, [_p, _p, ctypes.c_size_t]),
+    "ipm_batch_set_stream": (ctypes.c_int, [_p, _p]),
+    "ipm_batch_blockings": (ctypes.c_int, [_p, _p, _p, _p]),
+    "ipm_batch_set_blocking": (ctypes.c_int, [_p, _i32]),
+    "ipm_batch_autotune": (ctypes.c_int, [_p, _i32, _p, _p]),
+    "ipm_batch_solve": (ctypes.c_int, [_p, _p, _p, _p]),
+    "ipm_batch_get_solution": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, ctypes.c_int]),
+    "ipm_batch_last_error": (ctypes.c_char_p, [_p]),
+    "ipm_batch_destroy": (None, [_p]),
 }
 
 _lib = None
@@ -157,6 +176,30 @@ def _csr(mat, nrows, ncols, keep):
     keep += [rp, ci, va]
     c.rowptr, c.colind, c.val = _ptr(rp), _ptr(ci), _ptr(va)
     return c
+
+
+def _desc(problem, keep):
+    """ipm_problem_desc viewing the problem's arrays (kept alive in keep)."""
+    d = ipm_problem_desc()
+    d.n, d.m = problem.n, problem.m
+
+    def vec(a, n):
+        if a is None:
+            return ctypes.c_void_p(0)
+        arr = np.ascontiguousarray(a, np.float64)
+        assert arr.shape == (n,)
+        keep.append(arr)
+        return _ptr(arr)
+
+    d.c = vec(problem.c, problem.n)
+    d.b = vec(problem.b if problem.m else None, problem.m)
+    d.A = _csr(problem.A, problem.m, problem.n, keep)
+    d.W = _csr(problem.W, problem.m, problem.n, keep)
+    d.Q = _csr(problem.Q, problem.n, problem.n, keep)
+    d.q4 = vec(problem.q4, problem.n)
+    d.xl = vec(problem.xl, problem.n)
+    d.xu = vec(problem.xu, problem.n)
+    return d
 
 
 class _Handle:
@@ -277,25 +320,7 @@ class IpmSolver(_Handle):
     def __init__(self, problem, options=None, **kw):
         super().__init__()
         keep = []
-        d = ipm_problem_desc()
-        d.n, d.m = problem.n, problem.m
-
-        def vec(a, n):
-            if a is None:
-                return ctypes.c_void_p(0)
-            arr = np.ascontiguousarray(a, np.float64)
-            assert arr.shape == (n,)
-            keep.append(arr)
-            return _ptr(arr)
-
-        d.c = vec(problem.c, problem.n)
-        d.b = vec(problem.b if problem.m else None, problem.m)
-        d.A = _csr(problem.A, problem.m, problem.n, keep)
-        d.W = _csr(problem.W, problem.m, problem.n, keep)
-        d.Q = _csr(problem.Q, problem.n, problem.n, keep)
-        d.q4 = vec(problem.q4, problem.n)
-        d.xl = vec(problem.xl, problem.n)
-        d.xu = vec(problem.xu, problem.n)
+        d = _desc(problem, keep)
         opts = options if options is not None else default_options(**kw)
         self.options = opts
         self.n, self.m = problem.n, problem.m
@@ -354,3 +379,112 @@ class IpmSolver(_Handle):
                                            _ptr(lam) if self.m else None, _ptr(zl), _ptr(zu),
                                            PDIPM_HOST), "ipm_get_solution")
         return dict(x=x, s=s, lam=lam, zl=zl, zu=zu)
+
+
+class BatchSolver:
+    """Batched interior-point solve of many LP/QP problem objects."""
+
+    def __init__(self, problems, options=None, **kw):
+        self.h = ctypes.c_void_p()
+        self.ws = None
+        keep = []
+        descs = (ipm_problem_desc * len(problems))()
+        for i, p in enumerate(problems):
+            descs[i] = _desc(p, keep)
+        opts = options if options is not None else default_options(**kw)
+        self.options = opts
+        self.count = len(problems)
+        rc = lib().ipm_batch_create(self.count, descs, ctypes.byref(opts), ctypes.byref(self.h))
+        if rc < 0:
+            raise PdipmError(rc, "ipm_batch_create: " + lib().ipm_batch_last_error(None).decode())
+        self.xoff = np.empty(self.count + 1, np.int64)
+        self.roff = np.empty(self.count + 1, np.int64)
+        self._check(lib().ipm_batch_offsets(self.h, _ptr(self.xoff), _ptr(self.roff)), "ipm_batch_offsets")
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise PdipmError(rc, f"{what}: " + lib().ipm_batch_last_error(self.h).decode())
+        return rc
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().ipm_batch_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def stats(self):
+        s = kkt_symbolic_stats()
+        self._check(lib().ipm_batch_analyze(self.h, ctypes.byref(s)), "ipm_batch_analyze")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(lib().ipm_batch_workspace_query(self.h, ctypes.byref(b)), "ipm_batch_workspace_query")
+        return b.value
+
+    def bind(self, device="cuda:0", workspace=None, stream=None):
+        import torch
+        nbytes = self.workspace_bytes()
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = workspace.data_ptr()
+        off = (-base) % 256
+        self.ws = workspace
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        torch.cuda.synchronize(device)
+        self._check(lib().ipm_batch_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)),
+                    "ipm_batch_set_stream")
+        self._check(lib().ipm_batch_set_workspace(self.h, ctypes.c_void_p(base + off), nbytes),
+                    "ipm_batch_set_workspace")
+        return self
+
+    def blockings(self):
+        c = ctypes.c_int32()
+        self._check(lib().ipm_batch_blockings(self.h, ctypes.byref(c), None, None), "ipm_batch_blockings")
+        sh = np.empty(c.value, np.int32); ob = np.empty(c.value, np.int32)
+        self._check(lib().ipm_batch_blockings(self.h, ctypes.byref(c), _ptr(sh), _ptr(ob)), "ipm_batch_blockings")
+        return list(zip(sh.tolist(), ob.tolist()))
+
+    def set_blocking(self, index):
+        self._check(lib().ipm_batch_set_blocking(self.h, index), "ipm_batch_set_blocking")
+
+    def autotune(self, reps=2):
+        n = len(self.blockings())
+        ms = np.empty(n, np.float64)
+        chosen = ctypes.c_int32()
+        self._check(lib().ipm_batch_autotune(self.h, reps, ctypes.byref(chosen), _ptr(ms)), "ipm_batch_autotune")
+        return chosen.value, ms
+
+    def solve(self, start=None):
+        res = (ipm_result * self.count)()
+        info = ipm_batch_info()
+        st = None
+        if start is not None:
+            xs, ls = start
+            st = ipm_start()
+            if hasattr(xs, "data_ptr"):
+                st.x, st.lam, st.memspace = _dptr(xs), _dptr(ls), PDIPM_DEVICE
+            else:
+                self._start_keep = (np.ascontiguousarray(xs, np.float64), np.ascontiguousarray(ls, np.float64))
+                st.x, st.lam, st.memspace = _ptr(self._start_keep[0]), _ptr(self._start_keep[1]), PDIPM_HOST
+        rc = lib().ipm_batch_solve(self.h, ctypes.byref(st) if st is not None else None, res, ctypes.byref(info))
+        self._check(rc, "ipm_batch_solve")
+        results = [{k: getattr(r, k) for k in ("status", "iterations", "f", "P", "D", "C", "mu")} for r in res]
+        return results, {k: getattr(info, k) for k, _ in info._fields_ if k != "pad"}
+
+    def solution(self):
+        N, M = int(self.xoff[-1]), int(self.roff[-1])
+        x = np.empty(N); s = np.empty(max(M, 1)); lam = np.empty(max(M, 1))
+        zl = np.empty(N); zu = np.empty(N)
+        self._check(lib().ipm_batch_get_solution(self.h, _ptr(x), _ptr(s) if M else None,
+                                                 _ptr(lam) if M else None, _ptr(zl), _ptr(zu), PDIPM_HOST),
+                    "ipm_batch_get_solution")
+        out = []
+        for i in range(self.count):
+            a, b = int(self.xoff[i]), int(self.xoff[i + 1])
+            r0, r1 = int(self.roff[i]), int(self.roff[i + 1])
+            out.append(dict(x=x[a:b], s=s[r0:r1], lam=lam[r0:r1], zl=zl[a:b], zu=zu[a:b]))
+        return out

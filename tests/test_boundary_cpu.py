@@ -79,3 +79,40 @@ def test_workspace_query_is_host_only():
     assert s.workspace_bytes() > 0
     st = s.stats()
     assert st["n"] == 400 and st["n_super"] >= 1 and st["flops"] > 0
+
+
+def test_batch_create_offsets_and_blockings():
+    ps = [w.qp_instance(n, 40 + i) for i, n in enumerate([50, 90, 140])] + [w.lp_small(2)]
+    b = L.BatchSolver(ps, precision=L.PDIPM_FP32)
+    assert b.xoff.tolist() == [0, 50, 140, 280, 780]
+    assert b.roff.tolist() == [0, 25, 70, 140, 340]
+    st = b.stats()
+    assert st["n"] == 780
+    cands = b.blockings()
+    assert len(cands) >= 2 and all(1 <= sh <= 64 and ob >= 1 for sh, ob in cands)
+    assert b.workspace_bytes() > 0
+
+
+def test_batch_symbolic_is_the_union_of_the_instances():
+    """The block-diagonal batch has the factor of each instance: its nnz(L)
+    and flops are the sums of the oracle's per-instance figures."""
+    ps = [w.qp_instance(n, 60 + i) for i, n in enumerate([70, 120, 66])]
+    b = L.BatchSolver(ps)
+    nnz = flops = 0
+    for p in ps:
+        s = L.IpmSolver(p)
+        (jrp, jci), (hrp, hci) = s.patterns()
+        ref = osym.analyze(osym.kkt_pattern(p.n, jrp, jci, hrp, hci), p.n)
+        nnz += ref["nnz_L"]
+        flops += ref["flops"]
+    st = b.stats()
+    assert st["nnz_L"] == nnz and st["flops"] == flops
+
+
+def test_batch_rejects_nonlinear_instances():
+    ps = [w.qp_instance(60, 1), w.nlp_grid(6, 5)]
+    with pytest.raises(L.PdipmError) as e:
+        L.BatchSolver(ps)
+    assert e.value.code == L.PDIPM_ERR_INVALID_ARG
+    with pytest.raises(L.PdipmError):
+        L.BatchSolver([])
