@@ -41,6 +41,100 @@ def make_problem(args):
     return p, name
 
 
+def bench_batch(args, log):
+    """Batched form: many independent QPs (n log-uniform in [50, 2000],
+    m = n/2) solved together; value = instances solved per second."""
+    import numpy as np
+    import torch
+    from paper_2508_16094_amd import lib as L
+    from paper_2508_16094_amd import workloads as w
+    t = time.time()
+    ps = w.qp_batch(args.count)
+    sizes = np.array([p.n for p in ps])
+    log(f"[bench] generated {len(ps)} QPs (sum n = {sizes.sum()}) in {time.time() - t:.1f}s")
+    prec = L.PDIPM_FP32 if args.precision == "fp32" else L.PDIPM_FP64
+    t = time.time()
+    b = L.BatchSolver(ps, precision=prec, print_level=1 if args.verbose else 0)
+    st = b.stats()
+    log(f"[bench] analysed in {time.time() - t:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
+        f"supernodes={st['n_super']} levels={st['n_levels']} workspace={b.workspace_bytes() / 1e9:.2f} GB")
+    b.bind()
+    chosen, ms = b.autotune(reps=2)
+    log(f"[bench] autotune: blockings {b.blockings()} factor ms {np.round(ms, 2).tolist()} -> {chosen}")
+    for i in range(args.warmup):
+        res, info = b.solve()
+        log(f"[bench] warmup {i}: {info}")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(args.steps):
+        res, info = b.solve()
+        log(f"[bench] step {i}: {info}")
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    ok = sum(r["status"] == 0 for r in res)
+    iters = np.array([r["iterations"] for r in res])
+    # the same instances one at a time through the FP64 single-instance path
+    # (a sample spread over the sizes; the loop time is its mean times count)
+    sample = list(range(0, len(ps), max(1, len(ps) // args.loop_sample)))[:args.loop_sample]
+    loop_t = []
+    for i in sample:
+        s = L.IpmSolver(ps[i], precision=L.PDIPM_FP64).bind()
+        s.solve()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        r = s.solve()
+        torch.cuda.synchronize()
+        loop_t.append(time.time() - t1)
+    loop_est = float(np.mean(loop_t)) * len(ps)
+    fac_tf = st["flops"] / (ms[chosen] * 1e-3) / 1e12
+    peak = PEAK[args.precision]
+    out = {
+        "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
+        "value": len(ps) * args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == L.PDIPM_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"qp_batch {len(ps)} QPs, n log-uniform [50, 2000], m = n/2, 4 nnz/col, "
+                               f"diagonal Q; one batched solve per step",
+                   "form": "batched, fp32 factor + fp64 refinement" if prec == L.PDIPM_FP32 else "batched, fp64",
+                   "tol": 1e-6, "parallelism": "single GPU"},
+        "solved": ok, "iterations_max": int(iters.max()), "iterations_mean": float(iters.mean()),
+        "batch_info": info,
+        "loop_fp64_single_path": {"sample": len(sample), "mean_s": float(np.mean(loop_t)),
+                                  "estimated_total_s": loop_est,
+                                  "batched_speedup": loop_est / (elapsed / args.steps)},
+        "roofline": {"bound": "mfma", "achieved": fac_tf, "peak": peak, "unit": "TFLOP/s",
+                     "frac": fac_tf / peak, "traffic": None,
+                     "kernel": "whole factorisation (sum c_j^2 / autotuned factor time)"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import ipm as oipm
+        from oracle import model
+        from oracle import symbolic as osym
+        import scipy.sparse as sp
+        # the oracle on instances of up to 700 columns spread over the sizes,
+        # scaled to the whole batch by factorisation work (sum c_j^2)
+        cs = [i for i in sample if ps[i].n <= 700][:6]
+        t = time.time()
+        fl = 0.0
+        for i in cs:
+            p = ps[i]
+            oipm.solve(p, tol=1e-6, dense_max=0)
+            J = model.jacobian(p, np.zeros(p.n)).tocsr()
+            H = sp.tril(model.hessian(p, np.zeros(p.n), np.ones(p.m))).tocsr()
+            fl += float(osym.analyze(osym.kkt_pattern(p.n, J.indptr, J.indices, H.indptr, H.indices), p.n)["flops"])
+        dt = time.time() - t
+        est = dt * st["flops"] / fl
+        out["cpu_baseline"] = {"value": len(ps) / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle IPM on {len(cs)} instances (n = {[int(ps[i].n) for i in cs]}): "
+                                         f"{dt:.1f} s for sum c_j^2 = {fl:.3g}; scaled to the batch's "
+                                         f"{st['flops']:.3g}"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(args, flops_full, iters_full):
     """The oracle (plain FP64 CPU IPM) on a bounded slice of the workload:
     its time per IPM iteration per factorisation flop, scaled to the full
@@ -86,6 +180,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--count", type=int, default=4096, help="qp_batch: number of instances")
+    ap.add_argument("--loop-sample", type=int, default=16, help="qp_batch: instances timed one at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"--gpus {args.gpus}: the solver runs one instance on one GPU; multi-GPU sharding "
@@ -96,6 +192,9 @@ def main():
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
+
+    if args.workload == "qp_batch":
+        return bench_batch(args, log)
 
     t = time.time()
     p, name = make_problem(args)
