@@ -306,126 +306,183 @@ __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* pan
   }
 }
 
-// Diagonal block Cholesky and inverse.  The NB x NB block lives in
-// registers: thread (tr, tc) of a 16 x 16 grid owns a TS x TS tile.  Column k
-// of the factor is published to LDS once (two barriers per column); the
-// inverse X = L^{-1} is then formed row by row in registers from the factor
-// columns kept in LDS (one barrier per row, double-buffered row exchange).
+// Broadcast of lane `src` (wave-uniform) through the scalar unit.
+__device__ inline float lane_bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ inline double lane_bcast(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky factor and inverse of one nb x nb diagonal block (bw <= nb
+// columns used; the rest is padded with the identity), blocked by panels of
+// PB columns in LDS:
+//   factor:  wave 0 factors the (nb - c0) x PB panel column by column with
+//            lane broadcasts (no workgroup barrier inside a panel), then all
+//            waves apply the rank-PB update to the trailing lower part with
+//            TS x TS register tiles;
+//   inverse: X = inv(L) by row panels of the identity: each of the first c1
+//            threads solves L_pp X_p = B_p for one column, then all waves
+//            subtract L(below, p) X_p from the rows below.
+// X is kept transposed in the (zero) upper triangle of the same LDS array
+// and its diagonal in xd, so one NB x (NB + 1) array holds both factors.
 template <typename T, int NB>
 __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
-  constexpr int TS = NB / 16, LD = NB + 1;
-  __shared__ T Lc[NB * LD];
-  __shared__ T xrow[2][NB];
-  __shared__ T pivs;
+  constexpr int PB = 16, NP = NB / PB, LDA = NB + 1, TS = NB / 16, S = NB / 64;
+  __shared__ T A[NB * LDA];
+  __shared__ T xd[NB];
   const PotrfDesc d = P.potrf[d0 + blockIdx.x];
   const int bw = d.bw;
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tr = tid >> 4, tc = tid & 15;
   T* g = panel + d.d_off;
-  T a[TS][TS];
+  for (int idx = tid; idx < NB * NB; idx += BS) {
+    const int i = idx % NB, j = idx / NB;
+    T v = (T)0;
+    if (i < bw && j < bw) { if (i >= j) v = g[i + (int64_t)j * d.ld]; }
+    else if (i == j) v = (T)1;
+    A[i + j * LDA] = v;
+  }
+  if (tid < NB) xd[tid] = (T)1;
+  __syncthreads();
+  // ---- factor
+  for (int p = 0; p < NP; ++p) {
+    const int c0 = p * PB, c1 = c0 + PB;
+    if (wave == 0) {
+      T a[S][PB];
 #pragma unroll
-  for (int r = 0; r < TS; ++r)
+      for (int s = 0; s < S; ++s) {
+        const int r = c0 + lane + 64 * s;
 #pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = tr * TS + r, j = tc * TS + c;
-      a[r][c] = (i < bw && j <= i) ? g[i + (int64_t)j * d.ld] : (T)0;
+        for (int j = 0; j < PB; ++j) a[s][j] = r < NB ? A[r + (c0 + j) * LDA] : (T)0;
+      }
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        T dk = lane_bcast(a[0][k], k);
+        if (!(dk > (T)0) || !isfinite((double)dk)) {
+          if (lane == 0 && c0 + k < bw) atomicMin(bad, d.col0 + c0 + k);
+          dk = (T)1;
+        }
+        const T piv = sqrt(dk), rp = (T)1 / piv;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int rel = lane + 64 * s;
+          if (rel > k) a[s][k] *= rp;
+          else if (rel == k) a[s][k] = piv;
+        }
+#pragma unroll
+        for (int j = k + 1; j < PB; ++j) {
+          const T ljk = lane_bcast(a[0][k], j);
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+            if (lane + 64 * s > k) a[s][j] -= a[s][k] * ljk;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = c0 + lane + 64 * s;
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          if (r < NB && r >= c0 + j) A[r + (c0 + j) * LDA] = a[s][j];
+      }
     }
-  for (int k = 0; k < bw; ++k) {
-    if (tr == k / TS && tc == k / TS) {
+    __syncthreads();
+    // trailing update of rows and columns >= c1 (lower part)
+    if (c1 < NB && tr >= tc && tr * TS + TS > c1 && tc * TS + TS > c1) {
+      T acc[TS][TS];
 #pragma unroll
       for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c)
-          if (r == k % TS && c == k % TS) {
-            T v = a[r][c];
-            const bool ok = v > (T)0 && isfinite((double)v);
-            if (!ok) { atomicMin(bad, d.col0 + k); v = (T)1; }
-            v = sqrt(v);
-            a[r][c] = v;
-            pivs = v;
-            Lc[k + k * LD] = v;
-          }
-    }
-    __syncthreads();
-    if (tc == k / TS) {
-      const T p = pivs;
+        for (int c = 0; c < TS; ++c) acc[r][c] = (T)0;
+#pragma unroll 4
+      for (int t = 0; t < PB; ++t) {
+        T li[TS], lj[TS];
+#pragma unroll
+        for (int r = 0; r < TS; ++r) li[r] = A[tr * TS + r + (c0 + t) * LDA];
+#pragma unroll
+        for (int c = 0; c < TS; ++c) lj[c] = A[tc * TS + c + (c0 + t) * LDA];
+#pragma unroll
+        for (int r = 0; r < TS; ++r)
+#pragma unroll
+          for (int c = 0; c < TS; ++c) acc[r][c] += li[r] * lj[c];
+      }
 #pragma unroll
       for (int r = 0; r < TS; ++r)
 #pragma unroll
         for (int c = 0; c < TS; ++c) {
-          const int i = tr * TS + r;
-          if (c == k % TS && i > k && i < bw) {
-            a[r][c] /= p;
-            Lc[i + k * LD] = a[r][c];
-          }
+          const int i = tr * TS + r, j = tc * TS + c;
+          if (j >= c1 && i >= j) A[i + j * LDA] -= acc[r][c];
         }
     }
     __syncthreads();
-    T li[TS], lj[TS];
-#pragma unroll
-    for (int r = 0; r < TS; ++r) {
-      const int i = tr * TS + r;
-      li[r] = (i > k && i < bw) ? Lc[i + k * LD] : (T)0;
-    }
-#pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int j = tc * TS + c;
-      lj[c] = (j > k && j < bw) ? Lc[j + k * LD] : (T)0;
-    }
-#pragma unroll
-    for (int r = 0; r < TS; ++r)
-#pragma unroll
-      for (int c = 0; c < TS; ++c)
-        if (tc * TS + c <= tr * TS + r) a[r][c] -= li[r] * lj[c];
   }
+  // ---- inverse: B starts as the identity (upper triangle of A is zero)
+  for (int p = 0; p < NP; ++p) {
+    const int c0 = p * PB, c1 = c0 + PB;
+    if (tid < c1) {
+      const int j = tid;
+      T x[PB];
 #pragma unroll
-  for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < PB; ++r) {
+        const int i = c0 + r;
+        T sum = j < i ? A[j + i * LDA] : (j == i ? xd[i] : (T)0);
 #pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = tr * TS + r, j = tc * TS + c;
-      if (i < bw && j <= i) g[i + (int64_t)j * d.ld] = a[r][c];
-    }
-  // X = L^{-1}: row k of X is final after dividing by L(k,k); rows below
-  // subtract L(i,k) times it.  X starts as the identity.
+        for (int t = 0; t < r; ++t) sum -= A[i + (c0 + t) * LDA] * x[t];
+        x[r] = sum / A[i + i * LDA];
+      }
 #pragma unroll
-  for (int r = 0; r < TS; ++r)
-#pragma unroll
-    for (int c = 0; c < TS; ++c) a[r][c] = (tr * TS + r == tc * TS + c) ? (T)1 : (T)0;
-  for (int k = 0; k < bw; ++k) {
-    T* xr = xrow[k & 1];
-    if (tr == k / TS) {
-      const T dk = Lc[k + k * LD];
-#pragma unroll
-      for (int r = 0; r < TS; ++r)
-        if (r == k % TS) {
-#pragma unroll
-          for (int c = 0; c < TS; ++c) {
-            a[r][c] /= dk;
-            xr[tc * TS + c] = a[r][c];
-          }
-        }
-    }
-    __syncthreads();
-    T xk[TS];
-#pragma unroll
-    for (int c = 0; c < TS; ++c) xk[c] = xr[tc * TS + c];
-#pragma unroll
-    for (int r = 0; r < TS; ++r) {
-      const int i = tr * TS + r;
-      if (i > k && i < bw) {
-        const T lik = Lc[i + k * LD];
-#pragma unroll
-        for (int c = 0; c < TS; ++c) a[r][c] -= lik * xk[c];
+      for (int r = 0; r < PB; ++r) {
+        const int i = c0 + r;
+        if (j < i) A[j + i * LDA] = x[r];
+        else if (j == i) xd[i] = x[r];
       }
     }
-  }
-  T* o = inv + d.inv_off;
+    __syncthreads();
+    // rows below the panel: B(i, j) -= sum_t L(i, c0+t) X(c0+t, j), j < c1 <= i
+    if (c1 < NB && tr * TS + TS > c1 && tc * TS < c1) {
+      T acc[TS][TS];
 #pragma unroll
-  for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < TS; ++r)
 #pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = tr * TS + r, j = tc * TS + c;
-      o[i + (int64_t)j * NB] = (i < bw && j <= i) ? a[r][c] : (T)0;
+        for (int c = 0; c < TS; ++c) acc[r][c] = (T)0;
+#pragma unroll 4
+      for (int t = 0; t < PB; ++t) {
+        const int q = c0 + t;
+        T li[TS], xj[TS];
+#pragma unroll
+        for (int r = 0; r < TS; ++r) li[r] = A[tr * TS + r + q * LDA];
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+          const int j = tc * TS + c;
+          xj[c] = j < q ? A[j + q * LDA] : (j == q ? xd[q] : (T)0);
+        }
+#pragma unroll
+        for (int r = 0; r < TS; ++r)
+#pragma unroll
+          for (int c = 0; c < TS; ++c) acc[r][c] += li[r] * xj[c];
+      }
+#pragma unroll
+      for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+          const int i = tr * TS + r, j = tc * TS + c;
+          if (i >= c1 && j < c1) A[j + i * LDA] -= acc[r][c];
+        }
     }
+    __syncthreads();
+  }
+  // ---- write back L (lower, bw x bw) and X = inv(L) (nb x nb, zero padded)
+  T* o = inv + d.inv_off;
+  for (int idx = tid; idx < NB * NB; idx += BS) {
+    const int i = idx % NB, j = idx / NB;
+    if (i < bw && j < bw && i >= j) g[i + (int64_t)j * d.ld] = A[i + j * LDA];
+    T x = (T)0;
+    if (i < bw && j < bw) x = i > j ? A[j + i * LDA] : (i == j ? xd[i] : (T)0);
+    o[i + (int64_t)j * NB] = x;
+  }
 }
 
 // Tile (ti, tj) of descriptor-local tile index t; lower-masked descriptors
