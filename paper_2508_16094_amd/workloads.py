@@ -288,3 +288,16 @@ def thetas(count: int, set_id: int, n_theta: int = 64) -> np.ndarray:
     """theta ~ N(0, I); set 0 = training, set 1 = fresh test (disjoint seeds)."""
     rng = np.random.default_rng(seed_for(5, 1 + set_id))
     return rng.standard_normal((count, n_theta))
+
+
+def mlp_init(dims, seed: int = seed_for(5, 777)):
+    """Initial MLP parameters [(W, b)] for layer sizes dims (W: out x in):
+    uniform(-sqrt(6/fan_in), sqrt(6/fan_in)) weights, zero biases; the last
+    layer is scaled by 0.1."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for l in range(len(dims) - 1):
+        fan_in, fan_out = dims[l], dims[l + 1]
+        a = math.sqrt(6.0 / fan_in) * (0.1 if l == len(dims) - 2 else 1.0)
+        params.append((rng.uniform(-a, a, size=(fan_out, fan_in)), np.zeros(fan_out)))
+    return params
