@@ -304,6 +304,9 @@ int ipm_batch_autotune(ipm_batch* b, int32_t reps, int32_t* chosen, double* ms);
  * lambda (sum m_i), pushed into the interior per instance.  res: NULL or
  * count results (status, iterations, f, P, D, C, mu per instance). */
 int ipm_batch_solve(ipm_batch* b, const ipm_start* start, ipm_result* res, ipm_batch_info* info);
+/* Replace the right-hand sides b of all instances (host array, concatenated,
+ * sum m_i entries): parametric problems re-solve on the same analysis. */
+int ipm_batch_set_b(ipm_batch* b, const double* h_b);
 /* Concatenated final iterates (memspace PDIPM_HOST/DEVICE; NULL skipped). */
 int ipm_batch_get_solution(ipm_batch* b, double* x, double* s, double* lam, double* zl, double* zu,
                            int memspace);

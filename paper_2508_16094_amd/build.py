@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpdipm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["symbolic.cpp", "host.cpp", "kernels.hip", "batch.hip", "api.hip"]
+SOURCES = ["symbolic.cpp", "host.cpp", "kernels.hip", "batch.hip", "api.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

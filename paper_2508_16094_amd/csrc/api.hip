@@ -1617,6 +1617,19 @@ int ipm_batch_solve(ipm_batch* b, const ipm_start* start, ipm_result* res, ipm_b
   return run_batch(b->h, start, res, info);
 }
 
+int ipm_batch_set_b(ipm_batch* b, const double* hb) {
+  if (!b || !hb) return PDIPM_ERR_INVALID_ARG;
+  ipm_handle* h = b->h;
+  int rc = check_ready(h);
+  if (rc) return rc;
+  for (int64_t k = 0; k < h->hp.m; ++k)
+    if (!std::isfinite(hb[k])) return fail(h, PDIPM_ERR_INVALID_ARG, "non-finite b");
+  std::copy(hb, hb + h->hp.m, h->hp.b.begin());
+  if ((rc = upload(h, h->o.b, h->hp.b.data(), bytes_of(h->hp.b)))) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PDIPM_OK;
+}
+
 int ipm_batch_get_solution(ipm_batch* b, double* x, double* s, double* lam, double* zl, double* zu, int memspace) {
   if (!b) return PDIPM_ERR_INVALID_ARG;
   return ipm_get_solution(b->h, x, s, lam, zl, zu, memspace);

@@ -116,8 +116,22 @@ _SIGS = {
     "ipm_batch_autotune": (ctypes.c_int, [_p, _i32, _p, _p]),
     "ipm_batch_solve": (ctypes.c_int, [_p, _p, _p, _p]),
     "ipm_batch_get_solution": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, ctypes.c_int]),
+    "ipm_batch_set_b": (ctypes.c_int, [_p, _p]),
     "ipm_batch_last_error": (ctypes.c_char_p, [_p]),
     "ipm_batch_destroy": (None, [_p]),
+    "mlp_create": (ctypes.c_int, [_i32, _p, _i32, _f64, _i32, _p]),
+    "mlp_num_params": (ctypes.c_int, [_p, _p]),
+    "mlp_workspace_query": (ctypes.c_int, [_p, _p]),
+    "mlp_set_workspace": (ctypes.c_int, [_p, _p, ctypes.c_size_t]),
+    "mlp_set_stream": (ctypes.c_int, [_p, _p]),
+    "mlp_set_params": (ctypes.c_int, [_p, _p]),
+    "mlp_get_params": (ctypes.c_int, [_p, _p]),
+    "mlp_forward": (ctypes.c_int, [_p, _p, _p, _i32]),
+    "mlp_gradients": (ctypes.c_int, [_p, _p, _p, _i32, _p, _p]),
+    "mlp_train_step": (ctypes.c_int, [_p, _p, _p, _i32, ctypes.c_float, _p]),
+    "mlp_flops": (ctypes.c_double, [_p, _i32, _i32]),
+    "mlp_last_error": (ctypes.c_char_p, [_p]),
+    "mlp_destroy": (None, [_p]),
 }
 
 _lib = None
@@ -458,6 +472,11 @@ class BatchSolver:
         self._check(lib().ipm_batch_autotune(self.h, reps, ctypes.byref(chosen), _ptr(ms)), "ipm_batch_autotune")
         return chosen.value, ms
 
+    def set_b(self, b):
+        self._b_keep = np.ascontiguousarray(b, np.float64)
+        assert self._b_keep.shape == (int(self.roff[-1]),)
+        self._check(lib().ipm_batch_set_b(self.h, _ptr(self._b_keep)), "ipm_batch_set_b")
+
     def solve(self, start=None):
         res = (ipm_result * self.count)()
         info = ipm_batch_info()
@@ -488,3 +507,95 @@ class BatchSolver:
             r0, r1 = int(self.roff[i]), int(self.roff[i + 1])
             out.append(dict(x=x[a:b], s=s[r0:r1], lam=lam[r0:r1], zl=zl[a:b], zu=zu[a:b]))
         return out
+
+
+class MlpModel:
+    """Warm-start MLP (pdipm_mlp.h): dims[0] -> ... -> dims[-1], the first n_x
+    outputs are x in (0, x_scale), the rest lambda > 0."""
+
+    def __init__(self, dims, n_x, x_scale=10.0, max_batch=256):
+        self.h = ctypes.c_void_p()
+        self.ws = None
+        self.dims = [int(d) for d in dims]
+        self.n_x = int(n_x)
+        d = np.asarray(self.dims, np.int32)
+        rc = lib().mlp_create(len(self.dims) - 1, _ptr(d), self.n_x, float(x_scale), int(max_batch),
+                              ctypes.byref(self.h))
+        if rc < 0:
+            raise PdipmError(rc, "mlp_create: " + lib().mlp_last_error(None).decode())
+        c = ctypes.c_int64()
+        self._check(lib().mlp_num_params(self.h, ctypes.byref(c)), "mlp_num_params")
+        self.num_params = c.value
+        self.max_batch = int(max_batch)
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise PdipmError(rc, f"{what}: " + lib().mlp_last_error(self.h).decode())
+        return rc
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().mlp_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def bind(self, device="cuda:0", stream=None):
+        import torch
+        b = ctypes.c_size_t()
+        self._check(lib().mlp_workspace_query(self.h, ctypes.byref(b)), "mlp_workspace_query")
+        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._check(lib().mlp_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "mlp_set_stream")
+        self._check(lib().mlp_set_workspace(self.h, ctypes.c_void_p(base + (-base) % 256), b.value),
+                    "mlp_set_workspace")
+        return self
+
+    @staticmethod
+    def flatten(params):
+        return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+    def unflatten(self, flat):
+        out, o = [], 0
+        for a, b in zip(self.dims[:-1], self.dims[1:]):
+            W = flat[o:o + a * b].reshape(b, a); o += a * b
+            bb = flat[o:o + b]; o += b
+            out.append((W, bb))
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.flatten(params), np.float32)
+        assert flat.size == self.num_params
+        self._check(lib().mlp_set_params(self.h, _ptr(flat)), "mlp_set_params")
+
+    def get_params(self):
+        flat = np.empty(self.num_params, np.float32)
+        self._check(lib().mlp_get_params(self.h, _ptr(flat)), "mlp_get_params")
+        return self.unflatten(flat)
+
+    def forward(self, theta, out=None):
+        import torch
+        B = theta.shape[0]
+        if out is None:
+            out = torch.empty((B, self.dims[-1]), dtype=torch.float32, device=theta.device)
+        self._check(lib().mlp_forward(self.h, _dptr(theta), _dptr(out), B), "mlp_forward")
+        return out
+
+    def gradients(self, theta, target):
+        loss = ctypes.c_float()
+        g = np.empty(self.num_params, np.float32)
+        self._check(lib().mlp_gradients(self.h, _dptr(theta), _dptr(target), theta.shape[0], ctypes.byref(loss),
+                                        _ptr(g)), "mlp_gradients")
+        return loss.value, self.unflatten(g)
+
+    def train_step(self, theta, target, lr, want_loss=True):
+        loss = ctypes.c_float()
+        self._check(lib().mlp_train_step(self.h, _dptr(theta), _dptr(target), theta.shape[0], float(lr),
+                                         ctypes.byref(loss) if want_loss else None), "mlp_train_step")
+        return loss.value if want_loss else None
+
+    def flops(self, B, training):
+        return lib().mlp_flops(self.h, int(B), int(training))

@@ -1,0 +1,54 @@
+"""Learned warm start on a small parametric QP (12 x 15 grid, 8 parameters):
+training set solved by the batched solver, MLP trained on the GPU, fresh
+parameters solved cold and from the network's prediction.
+
+Bar (the gain is measured, not pinned): every warm-started instance reaches
+status OK and passes the parity rule against the oracle (f within 1e-6
+relative of the oracle at tol 1e-9; the oracle's checker recomputes P, D, C
+<= 1e-6 from the returned vectors; x within the strong-convexity bound)."""
+import numpy as np
+import pytest
+
+from oracle import checker, ipm as oipm
+from paper_2508_16094_amd import lib as L
+from paper_2508_16094_amd import warm
+from paper_2508_16094_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def test_warm_start_from_trained_mlp():
+    pq = w.qp_param(12, 15, n_theta=8)
+    n, m = pq.base.n, pq.base.m
+    th_train = w.thetas(192, 0, n_theta=8)
+    th_test = w.thetas(24, 1, n_theta=8)
+    pb = warm.ParamBatch(pq, chunk=64)
+    res, X, Lm, _ = pb.solve(th_train)
+    assert all(r["status"] == 0 for r in res)
+    model = L.MlpModel([8, 64, 64, n + m], n_x=n, max_batch=64).bind()
+    model.set_params(w.mlp_init([8, 64, 64, n + m]))
+    losses = warm.train(model, th_train, np.concatenate([X, Lm], axis=1), steps=300, batch=64, lr=3e-3)
+    print("loss", losses[0], losses[-1], flush=True)
+    assert losses[-1][1] < losses[0][1]
+    xh, lh = warm.predict(model, th_test)
+    cold, _, _, _ = pb.solve(th_test)
+    warm_res, Xw, Lw, _ = pb.solve(th_test, starts=(xh, lh))
+    ic = np.array([r["iterations"] for r in cold]); iw = np.array([r["iterations"] for r in warm_res])
+    print(f"iterations cold mean {ic.mean():.2f} warm mean {iw.mean():.2f}", flush=True)
+    assert all(r["status"] == 0 for r in warm_res)
+    sol = pb.solver.solution()  # the test set fits one chunk: slots 0..23 are its instances
+    for i in range(len(th_test)):
+        p = pq.instance(th_test[i])
+        chk = checker.check(p, sol[i]["x"], sol[i]["s"], sol[i]["lam"], sol[i]["zl"], sol[i]["zu"])
+        assert chk["P"] <= 1e-6 and chk["D"] <= 1e-6 and chk["C"] <= 1e-6, (i, chk)
+        assert np.array_equal(sol[i]["x"], Xw[i])
+        if i % 4 == 0:
+            ref = oipm.solve(p, tol=1e-9)
+            f_ref = ref["f"]
+            assert abs(warm_res[i]["f"] - f_ref) / max(1.0, abs(f_ref)) <= 1e-6
+            assert abs(chk["f"] - f_ref) / max(1.0, abs(f_ref)) <= 1e-6
+            # Q = grid Laplacian + 0.1 I: strong convexity 0.1
+            gap = abs(chk["f"] - f_ref) + 1e-6 * (1 + abs(f_ref))
+            assert np.max(np.abs(sol[i]["x"] - ref["x"])) <= np.sqrt(2 * gap / 0.1) + 1e-6
