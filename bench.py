@@ -135,6 +135,74 @@ def bench_batch(args, log):
     return 0
 
 
+def bench_warm(args, log):
+    """Learned warm start on the parametric QP (100 x 200 grid, 64 parameters):
+    training set solved by the batched solver, MLP 64-512-512-(n+m) trained
+    on the GPU, fresh parameters solved cold and warm; value = warm solves/s
+    on the test set, MLP inference included."""
+    import numpy as np
+    import torch
+    from paper_2508_16094_amd import lib as L
+    from paper_2508_16094_amd import warm
+    from paper_2508_16094_amd import workloads as w
+    pq = w.qp_param()
+    n, m = pq.base.n, pq.base.m
+    th_train = w.thetas(args.n_train, 0)
+    th_test = w.thetas(args.n_test, 1)
+    t = time.time()
+    pb = warm.ParamBatch(pq, chunk=args.chunk)
+    log(f"[bench] parametric QP n={n} m={m}: batch of {args.chunk} analysed and bound in {time.time() - t:.1f}s")
+    res, X, Lm, t_train_solve = pb.solve(th_train)
+    ok_train = sum(r["status"] == 0 for r in res)
+    log(f"[bench] training set: {ok_train}/{len(res)} solved in {t_train_solve:.1f}s")
+    keep = np.array([r["status"] == 0 for r in res])
+    dims = [th_train.shape[1], 512, 512, n + m]
+    model = L.MlpModel(dims, n_x=n, max_batch=args.mlp_batch).bind()
+    model.set_params(w.mlp_init(dims))
+    torch.cuda.synchronize()
+    t = time.time()
+    losses = warm.train(model, th_train[keep], np.concatenate([X, Lm], axis=1)[keep], steps=args.mlp_steps,
+                        batch=args.mlp_batch, lr=args.mlp_lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t
+    train_tf = model.flops(args.mlp_batch, 1) * args.mlp_steps / t_train / 1e12
+    cold, _, _, t_cold = pb.solve(th_test)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    xh, lh = warm.predict(model, th_test)
+    torch.cuda.synchronize()
+    t_inf = time.time() - t0
+    wres, _, _, t_warm = pb.solve(th_test, starts=(xh, lh))
+    ic = np.array([r["iterations"] for r in cold])
+    iw = np.array([r["iterations"] for r in wres])
+    fails = int(sum(r["status"] != 0 for r in wres))
+    value = len(th_test) / (t_warm + t_inf)
+    out = {
+        "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * (t_warm + t_inf), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"qp_param warm start: 100x200 grid QP (n={n}, m={m}), 64 parameters; "
+                               f"MLP 64-512-512-{n + m} trained on {int(keep.sum())} solved instances, "
+                               f"tested on {len(th_test)} fresh ones (batches of {args.chunk})",
+                   "form": "warm start (bf16 MLP) + batched fp64 IPM", "tol": 1e-6,
+                   "parallelism": "single GPU"},
+        "cold": {"solves_per_s": len(th_test) / t_cold, "iterations_mean": float(ic.mean()),
+                 "iterations_p95": float(np.percentile(ic, 95))},
+        "warm": {"solves_per_s": value, "iterations_mean": float(iw.mean()),
+                 "iterations_p95": float(np.percentile(iw, 95)), "inference_s": t_inf,
+                 "failures": fails},
+        "training": {"instances": int(keep.sum()), "solve_s": t_train_solve, "mlp_steps": args.mlp_steps,
+                     "mlp_batch": args.mlp_batch, "mlp_s": t_train, "loss_first": losses[0][1],
+                     "loss_last": losses[-1][1]},
+        "roofline": {"bound": "mfma", "achieved": train_tf, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": train_tf / 2500.0, "traffic": None,
+                     "kernel": "MLP training step (k_gemm_bf16 products with epilogues, loss, Adam)"},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(args, flops_full, iters_full):
     """The oracle (plain FP64 CPU IPM) on a bounded slice of the workload:
     its time per IPM iteration per factorisation flop, scaled to the full
@@ -182,6 +250,12 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--count", type=int, default=4096, help="qp_batch: number of instances")
     ap.add_argument("--loop-sample", type=int, default=16, help="qp_batch: instances timed one at a time")
+    ap.add_argument("--n-train", type=int, default=1024, help="warm: training instances")
+    ap.add_argument("--n-test", type=int, default=256, help="warm: fresh test instances")
+    ap.add_argument("--chunk", type=int, default=128, help="warm: instances per batched solve")
+    ap.add_argument("--mlp-steps", type=int, default=600)
+    ap.add_argument("--mlp-batch", type=int, default=256)
+    ap.add_argument("--mlp-lr", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"--gpus {args.gpus}: the solver runs one instance on one GPU; multi-GPU sharding "
@@ -195,6 +269,8 @@ def main():
 
     if args.workload == "qp_batch":
         return bench_batch(args, log)
+    if args.workload == "warm":
+        return bench_warm(args, log)
 
     t = time.time()
     p, name = make_problem(args)
