@@ -39,8 +39,9 @@ size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
 // workspace is laid out for all of them, so switching needs no new memory).
 struct PlanCaps {
   size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0;
-  int64_t inv = 0, part = 1;
+  int64_t inv = 0, part = 1, pairs = 1;
   void add(const Plan& P) {
+    pairs = std::max(pairs, P.max_pairs);
     gemm = std::max(gemm, bytes_of(P.gemm)); potrf = std::max(potrf, bytes_of(P.potrf));
     ext = std::max(ext, bytes_of(P.ext)); small = std::max(small, bytes_of(P.small));
     sdesc = std::max(sdesc, bytes_of(P.sdesc)); ssmall = std::max(ssmall, bytes_of(P.ssmall));
@@ -76,7 +77,7 @@ struct ipm_handle {
     size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
-    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
+    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, bcnt, sinv64, sinv32;
     size_t vec[49];
   } o{};
   DevProblem dp{};
@@ -93,6 +94,7 @@ struct ipm_handle {
   double* dscale = nullptr;     // symmetric scaling of the FP32 factor
   double* ysol = nullptr;       // forward/backward solution (permuted)
   double* part = nullptr;       // backward partial sums
+  int* bcnt = nullptr;          // backward completion counters (zero between launches)
   bool scaled = false;          // current factor is of D K D
   double kmax = 1.0;            // max diagonal of K (norm estimate)
   double shift = 0.0;           // diagonal shift of the scaled FP32 factor
@@ -241,6 +243,7 @@ void layout(ipm_handle* h) {
   o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
   o.ysol = r.take(n * 8);
   o.part = r.take((size_t)std::max(h->need64 ? c64.part : 1, h->need32 ? c32.part : 1) * 8);
+  o.bcnt = r.take((size_t)std::max(c64.pairs, c32.pairs) * 4);
   // vectors: 0..47 (n or m sized)
   const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
@@ -371,6 +374,10 @@ int bind_workspace(ipm_handle* h) {
   h->dscale = at<double>(h, o.dscale);
   h->ysol = at<double>(h, o.ysol);
   h->part = at<double>(h, o.part);
+  h->bcnt = at<int>(h, o.bcnt);
+  const int64_t npairs = std::max(std::max(h->cap64.pairs, h->cap32.pairs), std::max(h->plan64.max_pairs, h->plan32.max_pairs));
+  launch_fill_bytes0(h->bcnt, npairs * 4, h->stream);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   double* V[49];
   for (int i = 0; i < 49; ++i) V[i] = at<double>(h, o.vec[i]);
   IpmVecs& v = h->v;
@@ -474,10 +481,10 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
     for (const Op& op : *ops) {
       if (prec == PDIPM_FP64)
         launch_solve_op<double>(op, D, (const double*)h->panel, (const double*)h->inv, h->xperm, h->ysol,
-                                h->uvec, h->part, h->stream);
+                                h->uvec, h->part, h->bcnt, h->stream);
       else
         launch_solve_op<float>(op, D, (const float*)h->panel, (const float*)h->inv, h->xperm, h->ysol,
-                               h->uvec, h->part, h->stream);
+                               h->uvec, h->part, h->bcnt, h->stream);
     }
   }
   launch_permute_out(D, h->ysol, d, out, h->stream);
@@ -557,6 +564,9 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
   }
   omega = rnorm / (h->kmax * nx + nb + 1e-300);
   if (converged) *converged = std::isfinite(rnorm) && rnorm <= goal();
+  if (h->opt.print_level > 2)
+    fprintf(stderr, "      refine: prec %s residual %.3e goal %.3e ir %d cg %d |b| %.3e |x| %.3e\n",
+            fp32 ? "fp32" : "fp64", rnorm, goal(), steps, cg, nb, nx);
   if (info) { info->ir_steps = steps + cg; info->residual = omega; info->fallback = 0; }
   if (!std::isfinite(rnorm)) return fail(h, PDIPM_ERR_NUMERICAL, "non-finite solve residual");
   return PDIPM_OK;
@@ -712,6 +722,9 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     int fprec = stay64 ? PDIPM_FP64 : prec;
     double delta_w = 0.0;
     auto ta = clk::now();
+    const double factor_ms_before = R.ms_factor;
+    const int ir_before = R.ir_steps;
+    const bool fp32_iter = !stay64 && prec == PDIPM_FP32;
     assemble_values(h, O.delta_p);
     HIPCHK(h, hipStreamSynchronize(h->stream));
     R.ms_assemble += ms_since(ta);
@@ -784,7 +797,22 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     if (rc) return rc;
     launch_step_limits(P, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->partials, h->stream);
     if ((rc = read_back(h, red_out(h), lim, 2))) return rc;
-    R.ms_solve += ms_since(ts0);
+    const double solve_ms = ms_since(ts0);
+    R.ms_solve += solve_ms;
+    // Cost-based switch of the FP32 form: once refinement makes an FP32
+    // iteration dearer than an FP64 one would be (FP64 factor about 2.3x the
+    // FP32 factor time, as the MFMA rates of the two precisions differ;
+    // FP64 solves need no refinement and cost about two FP32 solves), FP64
+    // factors take over for the remaining iterations, where the condition
+    // number and with it the refinement work only grow.
+    if (fp32_iter && !stay64 && O.fp64_fallback && h->need64) {
+      const int ntri = 2 + (R.ir_steps - ir_before);
+      const double t_tri = solve_ms / ntri, t32 = R.ms_factor - factor_ms_before;
+      if (ntri * t_tri > 1.3 * t32 + 4.0 * t_tri) {
+        stay64 = true;
+        R.fp64_refactors++;
+      }
+    }
     if (O.print_level > 1)
       fprintf(stderr, "    solve: ir %d omega %.2e shifts %d fp64 %d delta_w %.1e kmax %.2e sigma %.2e\n",
               si.ir_steps, si.residual, shifts, R.fp64_refactors, delta_w, h->kmax, sigma);

@@ -273,8 +273,9 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   P = Plan();
   P.esize = esize;
   P.nb = esize == 8 ? 64 : 128;            // diagonal block / panel-solve width
-  // outer block: rank of the trailing update (a multiple of nb)
-  const int nbo = P.nb * (blk.outer_blocks > 0 ? blk.outer_blocks : 4);
+  // outer block: rank of the trailing update (a multiple of nb); by default
+  // 512 columns in both precisions (FP64: eight 64-column blocks)
+  const int nbo = P.nb * (blk.outer_blocks > 0 ? blk.outer_blocks : (esize == 8 ? 8 : 4));
   P.small_h = blk.small_h > 0 && blk.small_h <= 64 ? blk.small_h : 64;
   const int64_t ns = s.nsuper();
   P.ns = ns;
@@ -512,8 +513,10 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
         P.fwd_ops.push_back({OP_FWD_STEP, db, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - db});
     }
   }
-  // backward: levels from the root down; column blocks from the last one:
-  // partial products over row ranges below the block, then the block solve
+  // backward: levels from the root down; column blocks from the last one.
+  // Each item forms partial products over up to RBB rows below its column
+  // block; the last item of a (supernode, block) pair to finish sums the
+  // partials in order and solves the diagonal block (one launch per step).
   const int RBB = 256;  // rows per backward partial item
   for (int l = P.nlevels - 1; l >= 0; --l) {
     std::vector<int32_t> large;
@@ -533,30 +536,30 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       const int32_t c0 = step * nb;
       int64_t pb = (int64_t)P.sdesc.size();
       int64_t part = 0;
-      std::vector<SolveDesc> diag;
+      int32_t pair = 0;
       for (int32_t k : large) {
         if (P.sw[k] <= c0) continue;
-        int32_t bw = std::min(nb, P.sw[k] - c0);
-        SolveDesc dd{};
-        dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.owner = 1; dd.part_off = part;
-        int32_t np = 0;
-        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RBB) {
+        const int32_t bw = std::min(nb, P.sw[k] - c0);
+        const int32_t below = P.sh[k] - (c0 + bw);
+        const int32_t np = std::max<int32_t>(1, (below + RBB - 1) / RBB);
+        for (int32_t q = 0; q < np; ++q) {
           SolveDesc d{};
-          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RBB, P.sh[k]);
-          d.part_off = part;
-          part += nb;
-          ++np;
+          d.sn = k; d.c0 = c0; d.bw = bw;
+          d.r0 = std::min(c0 + bw + q * RBB, P.sh[k]);
+          d.r1 = std::min(d.r0 + RBB, P.sh[k]);
+          d.part_off = part + (int64_t)q * nb;
+          d.owner = pair;
+          d.nparts = np;
+          d.pad = q;
           P.sdesc.push_back(d);
         }
-        dd.nparts = np;
-        diag.push_back(dd);
+        part += (int64_t)np * nb;
+        ++pair;
       }
       P.part_elems = std::max(P.part_elems, part);
+      P.max_pairs = std::max<int64_t>(P.max_pairs, pair);
       if ((int64_t)P.sdesc.size() > pb)
         P.bwd_ops.push_back({OP_BWD_PART, pb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - pb});
-      int64_t qb = (int64_t)P.sdesc.size();
-      for (auto& d : diag) P.sdesc.push_back(d);
-      P.bwd_ops.push_back({OP_BWD_DIAG, qb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - qb});
     }
   }
 }

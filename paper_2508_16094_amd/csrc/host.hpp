@@ -75,8 +75,9 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
 
 // Blocked triangular-solve work item of supernode sn and column block
 // [c0, c0 + bw) over rows [r0, r1) below the block.  Forward: the owner
-// item also forms y of the next block.  Backward: partial products go to
-// part[part_off ..]; a diagonal item sums its nparts partials and solves.
+// item also forms y of the next block.  Backward: item pad (of nparts) of
+// the pair with counter slot owner writes its partial products to
+// part[part_off ..]; the last of them to finish solves the block.
 struct SolveDesc {
   int32_t sn, c0, bw, r0, r1, owner;
   int64_t part_off;
@@ -86,7 +87,7 @@ struct SolveDesc {
 enum OpType {
   OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE,   // factorisation
   OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_STEP,                      // forward solve
-  OP_BWD_SMALL, OP_BWD_PART, OP_BWD_DIAG                         // backward solve
+  OP_BWD_SMALL, OP_BWD_PART                                      // backward solve
 };
 
 struct Op {
@@ -122,6 +123,7 @@ struct Plan {
   std::vector<SolveDesc> sdesc;
   std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
   int64_t part_elems = 1;              // backward partial sums (max per step)
+  int64_t max_pairs = 1;               // backward completion counters (max per step)
   // algorithmic work of the Schur-update / panel-solve GEMM launches of one
   // factorisation (useful multiply-add flops, triangles not double counted)
   double gemm_flops = 0;
@@ -138,7 +140,7 @@ void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km)
 // trailing updates.
 struct Blocking {
   int small_h = 64;
-  int outer_blocks = 4;
+  int outer_blocks = 0;  // 0: the precision's default (8 FP64, 4 FP32)
 };
 void build_plan(const Symbolic& s, int precision_bytes, Plan* plan, const Blocking& blk = Blocking());
 void map_k_to_panels(const Symbolic& s, const Plan& plan, KMap* km);
