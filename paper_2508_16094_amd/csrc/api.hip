@@ -39,9 +39,8 @@ size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
 // workspace is laid out for all of them, so switching needs no new memory).
 struct PlanCaps {
   size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0;
-  int64_t inv = 0, part = 1, pairs = 1;
+  int64_t inv = 0, part = 1;
   void add(const Plan& P) {
-    pairs = std::max(pairs, P.max_pairs);
     gemm = std::max(gemm, bytes_of(P.gemm)); potrf = std::max(potrf, bytes_of(P.potrf));
     ext = std::max(ext, bytes_of(P.ext)); small = std::max(small, bytes_of(P.small));
     sdesc = std::max(sdesc, bytes_of(P.sdesc)); ssmall = std::max(ssmall, bytes_of(P.ssmall));
@@ -77,7 +76,7 @@ struct ipm_handle {
     size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
-    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, bcnt, sinv64, sinv32;
+    size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
     size_t vec[49];
   } o{};
   DevProblem dp{};
@@ -94,7 +93,6 @@ struct ipm_handle {
   double* dscale = nullptr;     // symmetric scaling of the FP32 factor
   double* ysol = nullptr;       // forward/backward solution (permuted)
   double* part = nullptr;       // backward partial sums
-  int* bcnt = nullptr;          // backward completion counters (zero between launches)
   bool scaled = false;          // current factor is of D K D
   double kmax = 1.0;            // max diagonal of K (norm estimate)
   double shift = 0.0;           // diagonal shift of the scaled FP32 factor
@@ -243,7 +241,6 @@ void layout(ipm_handle* h) {
   o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
   o.ysol = r.take(n * 8);
   o.part = r.take((size_t)std::max(h->need64 ? c64.part : 1, h->need32 ? c32.part : 1) * 8);
-  o.bcnt = r.take((size_t)std::max(c64.pairs, c32.pairs) * 4);
   // vectors: 0..47 (n or m sized)
   const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
@@ -374,10 +371,6 @@ int bind_workspace(ipm_handle* h) {
   h->dscale = at<double>(h, o.dscale);
   h->ysol = at<double>(h, o.ysol);
   h->part = at<double>(h, o.part);
-  h->bcnt = at<int>(h, o.bcnt);
-  const int64_t npairs = std::max(std::max(h->cap64.pairs, h->cap32.pairs), std::max(h->plan64.max_pairs, h->plan32.max_pairs));
-  launch_fill_bytes0(h->bcnt, npairs * 4, h->stream);
-  HIPCHK(h, hipStreamSynchronize(h->stream));
   double* V[49];
   for (int i = 0; i < 49; ++i) V[i] = at<double>(h, o.vec[i]);
   IpmVecs& v = h->v;
@@ -481,10 +474,10 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
     for (const Op& op : *ops) {
       if (prec == PDIPM_FP64)
         launch_solve_op<double>(op, D, (const double*)h->panel, (const double*)h->inv, h->xperm, h->ysol,
-                                h->uvec, h->part, h->bcnt, h->stream);
+                                h->uvec, h->part, h->stream);
       else
         launch_solve_op<float>(op, D, (const float*)h->panel, (const float*)h->inv, h->xperm, h->ysol,
-                               h->uvec, h->part, h->bcnt, h->stream);
+                               h->uvec, h->part, h->stream);
     }
   }
   launch_permute_out(D, h->ysol, d, out, h->stream);

@@ -513,10 +513,8 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
         P.fwd_ops.push_back({OP_FWD_STEP, db, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - db});
     }
   }
-  // backward: levels from the root down; column blocks from the last one.
-  // Each item forms partial products over up to RBB rows below its column
-  // block; the last item of a (supernode, block) pair to finish sums the
-  // partials in order and solves the diagonal block (one launch per step).
+  // backward: levels from the root down; column blocks from the last one:
+  // partial products over row ranges below the block, then the block solve
   const int RBB = 256;  // rows per backward partial item
   for (int l = P.nlevels - 1; l >= 0; --l) {
     std::vector<int32_t> large;
@@ -536,30 +534,30 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       const int32_t c0 = step * nb;
       int64_t pb = (int64_t)P.sdesc.size();
       int64_t part = 0;
-      int32_t pair = 0;
+      std::vector<SolveDesc> diag;
       for (int32_t k : large) {
         if (P.sw[k] <= c0) continue;
-        const int32_t bw = std::min(nb, P.sw[k] - c0);
-        const int32_t below = P.sh[k] - (c0 + bw);
-        const int32_t np = std::max<int32_t>(1, (below + RBB - 1) / RBB);
-        for (int32_t q = 0; q < np; ++q) {
+        int32_t bw = std::min(nb, P.sw[k] - c0);
+        SolveDesc dd{};
+        dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.owner = 1; dd.part_off = part;
+        int32_t np = 0;
+        for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RBB) {
           SolveDesc d{};
-          d.sn = k; d.c0 = c0; d.bw = bw;
-          d.r0 = std::min(c0 + bw + q * RBB, P.sh[k]);
-          d.r1 = std::min(d.r0 + RBB, P.sh[k]);
-          d.part_off = part + (int64_t)q * nb;
-          d.owner = pair;
-          d.nparts = np;
-          d.pad = q;
+          d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RBB, P.sh[k]);
+          d.part_off = part;
+          part += nb;
+          ++np;
           P.sdesc.push_back(d);
         }
-        part += (int64_t)np * nb;
-        ++pair;
+        dd.nparts = np;
+        diag.push_back(dd);
       }
       P.part_elems = std::max(P.part_elems, part);
-      P.max_pairs = std::max<int64_t>(P.max_pairs, pair);
       if ((int64_t)P.sdesc.size() > pb)
         P.bwd_ops.push_back({OP_BWD_PART, pb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - pb});
+      int64_t qb = (int64_t)P.sdesc.size();
+      for (auto& d : diag) P.sdesc.push_back(d);
+      P.bwd_ops.push_back({OP_BWD_DIAG, qb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - qb});
     }
   }
 }

@@ -75,9 +75,8 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
 
 // Blocked triangular-solve work item of supernode sn and column block
 // [c0, c0 + bw) over rows [r0, r1) below the block.  Forward: the owner
-// item also forms y of the next block.  Backward: item pad (of nparts) of
-// the pair with counter slot owner writes its partial products to
-// part[part_off ..]; the last of them to finish solves the block.
+// item also forms y of the next block.  Backward: partial products go to
+// part[part_off ..]; a diagonal item sums its nparts partials and solves.
 struct SolveDesc {
   int32_t sn, c0, bw, r0, r1, owner;
   int64_t part_off;
@@ -87,7 +86,7 @@ struct SolveDesc {
 enum OpType {
   OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE,   // factorisation
   OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_STEP,                      // forward solve
-  OP_BWD_SMALL, OP_BWD_PART                                      // backward solve
+  OP_BWD_SMALL, OP_BWD_PART, OP_BWD_DIAG                         // backward solve
 };
 
 struct Op {
@@ -123,7 +122,6 @@ struct Plan {
   std::vector<SolveDesc> sdesc;
   std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
   int64_t part_elems = 1;              // backward partial sums (max per step)
-  int64_t max_pairs = 1;               // backward completion counters (max per step)
   // algorithmic work of the Schur-update / panel-solve GEMM launches of one
   // factorisation (useful multiply-add flops, triangles not double counted)
   double gemm_flops = 0;

@@ -896,54 +896,6 @@ __global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T
   if (tid < w) ys[f + tid] = y[tid] / (double)L[tid + (int64_t)tid * ld];
 }
 
-// Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of the pair's
-// partials).  Two threads per column sum the partials (fixed order, four
-// independent accumulators each); column k of the inverse is contiguous, so
-// lanes run along it and each wave reduces its 32 columns by recursive halving.
-template <typename T>
-__device__ void bwd_diag_block(const DevPlan& P, int32_t sn, int c0, int bw, int64_t base, int nparts,
-                               const T* inv, double* ys, const double* part) {
-  __shared__ double z[128], zp[128];
-  const int f = P.sfirst[sn], nb = P.nb;
-  const int tid = threadIdx.x, c = tid & 127, half = tid >> 7;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  if (c < bw) {
-    const double* pp = part + base + c;
-    int q = half;
-    for (; q + 6 < nparts; q += 8) {
-      s0 += pp[(int64_t)q * nb];
-      s1 += pp[(int64_t)(q + 2) * nb];
-      s2 += pp[(int64_t)(q + 4) * nb];
-      s3 += pp[(int64_t)(q + 6) * nb];
-    }
-    for (; q < nparts; q += 2) s0 += pp[(int64_t)q * nb];
-  }
-  if (half) zp[c] = (s0 + s1) + (s2 + s3);
-  __syncthreads();
-  if (!half) z[c] = c < bw ? ys[f + c0 + c] - (((s0 + s1) + (s2 + s3)) + zp[c]) : 0.0;
-  __syncthreads();
-  const T* I = inv + P.sinv[sn] + (int64_t)(c0 / nb) * nb * nb;
-  const int lane = tid & 63, wave = tid >> 6, cb = wave * 32;
-  const double z1 = z[lane], z2 = z[lane + 64];
-  double acc[32];
-#pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    const int k = cb + m;
-    const T v1 = (k < bw && lane >= k && lane < bw) ? I[lane + (int64_t)k * nb] : (T)0;
-    const T v2 = (k < bw && lane + 64 < bw) ? I[lane + 64 + (int64_t)k * nb] : (T)0;
-    acc[m] = (double)v1 * z1 + (double)v2 * z2;
-  }
-  halve_step<32>(acc, lane & 32, 32);
-  halve_step<16>(acc, lane & 16, 16);
-  halve_step<8>(acc, lane & 8, 8);
-  halve_step<4>(acc, lane & 4, 4);
-  halve_step<2>(acc, lane & 2, 2);
-  acc[0] += __shfl_xor(acc[0], 1, 64);
-  const int col = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-                  ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-  if ((lane & 1) == 0 && col < bw) ys[f + c0 + col] = acc[0];
-}
-
 // Backward solve, large supernodes: partial products L(rows, J)' x(rows)
 // over a row range below column block J.  Each lane loads VEC consecutive
 // rows of a column with one vector load (coalesced along the column), each
@@ -951,8 +903,8 @@ __device__ void bwd_diag_block(const DevPlan& P, int32_t sn, int c0, int bw, int
 // column; the 64 lanes are combined by recursive halving (32 exchanges in
 // all instead of 6 per column).
 template <typename T>
-__global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const T* inv, double* ys,
-                                                double* part, int* cnt) {
+__global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
+                                                double* part) {
   constexpr int CPW = 32, VEC = VecOf<T>::n;
   typedef typename VecOf<T>::type V;
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
@@ -1008,16 +960,55 @@ __global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T*
   const int c = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
                 ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
   if ((lane & 1) == 0 && c < d.bw) part[d.part_off + c] = acc[0];
-  // the last item of the pair to finish solves the diagonal block
-  __shared__ int last;
-  __threadfence();
+}
+
+// Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of partials).
+// Two threads per column sum the partials (fixed order, four independent
+// accumulators each); column k of the inverse is contiguous, so lanes run
+// along it and each wave reduces its 32 columns by recursive halving.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
+                                                const double* part) {
+  __shared__ double z[128], zp[128];
+  const SolveDesc d = P.sdesc[d0 + blockIdx.x];
+  const int f = P.sfirst[d.sn], nb = P.nb, bw = d.bw;
+  const int tid = threadIdx.x, c = tid & 127, half = tid >> 7;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c < bw) {
+    const double* pp = part + d.part_off + c;
+    int q = half;
+    for (; q + 6 < d.nparts; q += 8) {
+      s0 += pp[(int64_t)q * nb];
+      s1 += pp[(int64_t)(q + 2) * nb];
+      s2 += pp[(int64_t)(q + 4) * nb];
+      s3 += pp[(int64_t)(q + 6) * nb];
+    }
+    for (; q < d.nparts; q += 2) s0 += pp[(int64_t)q * nb];
+  }
+  if (half) zp[c] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(cnt + d.owner, 1) == d.nparts - 1;
+  if (!half) z[c] = c < bw ? ys[f + d.c0 + c] - (((s0 + s1) + (s2 + s3)) + zp[c]) : 0.0;
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  bwd_diag_block<T>(P, S, d.c0, d.bw, d.part_off - (int64_t)d.pad * P.nb, d.nparts, inv, ys, part);
-  if (threadIdx.x == 0) cnt[d.owner] = 0;
+  const T* I = inv + P.sinv[d.sn] + (int64_t)(d.c0 / nb) * nb * nb;
+  const int lane = tid & 63, wave = tid >> 6, cb = wave * 32;
+  const double z1 = z[lane], z2 = z[lane + 64];
+  double acc[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const int k = cb + m;
+    const T v1 = (k < bw && lane >= k && lane < bw) ? I[lane + (int64_t)k * nb] : (T)0;
+    const T v2 = (k < bw && lane + 64 < bw) ? I[lane + 64 + (int64_t)k * nb] : (T)0;
+    acc[m] = (double)v1 * z1 + (double)v2 * z2;
+  }
+  halve_step<32>(acc, lane & 32, 32);
+  halve_step<16>(acc, lane & 16, 16);
+  halve_step<8>(acc, lane & 8, 8);
+  halve_step<4>(acc, lane & 4, 4);
+  halve_step<2>(acc, lane & 2, 2);
+  acc[0] += __shfl_xor(acc[0], 1, 64);
+  const int col = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+                  ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  if ((lane & 1) == 0 && col < bw) ys[f + d.c0 + col] = acc[0];
 }
 
 // -------------------------------------------------------- IPM vectors
@@ -1421,7 +1412,7 @@ template void launch_set_scaled<float>(const DevKMap&, const double*, const doub
 template void launch_set_scaled<double>(const DevKMap&, const double*, const double*, double, double*, hipStream_t);
 template <typename T>
 void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* inv, double* xp, double* ys,
-                     double* uvec, double* part, int* cnt, hipStream_t s) {
+                     double* uvec, double* part, hipStream_t s) {
   if (op.grid <= 0) return;
   const unsigned g = (unsigned)op.grid;
   switch (op.type) {
@@ -1429,13 +1420,14 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
     case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec); break;
     case OP_FWD_STEP: k_fwd_step<T><<<g, BS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
     case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
-    case OP_BWD_PART: k_bwd_part<T><<<g, BS, 0, s>>>(P, op.begin, panel, inv, ys, part, cnt); break;
+    case OP_BWD_PART: k_bwd_part<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, part); break;
+    case OP_BWD_DIAG: k_bwd_diag<T><<<g, BS, 0, s>>>(P, op.begin, inv, ys, part); break;
   }
 }
 template void launch_solve_op<double>(const Op&, const DevPlan&, const double*, const double*, double*, double*,
-                                      double*, double*, int*, hipStream_t);
+                                      double*, double*, hipStream_t);
 template void launch_solve_op<float>(const Op&, const DevPlan&, const float*, const float*, double*, double*,
-                                     double*, double*, int*, hipStream_t);
+                                     double*, double*, hipStream_t);
 
 void launch_residuals(const DevProblem& P, IpmVecs& v, hipStream_t s) {
   // J' lambda into tmp_n

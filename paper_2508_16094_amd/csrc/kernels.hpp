@@ -74,7 +74,7 @@ void launch_set_scaled(const DevKMap& K, const double* kval, const double* d, do
                        hipStream_t s);
 template <typename T>
 void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* inv, double* xp, double* ys,
-                     double* uvec, double* part, int* cnt, hipStream_t s);
+                     double* uvec, double* part, hipStream_t s);
 // symmetric product with stored K values (lower CSR, original numbering)
 void launch_k_mul_stored(int64_t n, const int64_t* kp, const int32_t* kc, const int64_t* ksp,
                          const int32_t* ksc, const int64_t* kss, const double* kval,
