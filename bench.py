@@ -203,6 +203,42 @@ def bench_warm(args, log):
     return 0
 
 
+def bench_copy(args, log):
+    """Plain device copy of a known size (calibration of the HBM byte
+    counters): 1 GiB copied args.steps times."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.time() - t0) / args.steps
+    print(json.dumps({"workload": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": 1e3 * dt,
+                      "gbps": 8 * n / dt / 1e9}), flush=True)
+    return 0
+
+
+def traffic_of(kernel, workload):
+    """HBM bytes per launch of kernel on workload measured with hardware
+    counters (profiles/traffic.json), or None when the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path)).get(f"{kernel}@{workload}")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernels_hip_sha256") != digest:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(args, flops_full, iters_full):
     """The oracle (plain FP64 CPU IPM) on a bounded slice of the workload:
     its time per IPM iteration per factorisation flop, scaled to the full
@@ -267,6 +303,8 @@ def main():
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
+    if args.workload == "copy":
+        return bench_copy(args, log)
     if args.workload == "qp_batch":
         return bench_batch(args, log)
     if args.workload == "warm":
@@ -335,9 +373,12 @@ def main():
         "solve_gbps": prof["solve_bytes"] / (last["ms_solve"] * 1e-3 * len(results)) / 1e9
         if last["ms_solve"] > 0 else None,
         "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
-                     "frac": gemm_tf / PEAK[pkey], "traffic": None,
+                     "frac": gemm_tf / PEAK[pkey],
+                     "traffic": traffic_of("k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
+                                           f"lp_block{args.nblocks}") if args.workload == "lp_block" else None,
                      "kernel": "k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
                      "launches": launches,
+                     "algorithmic_bytes_per_launch": prof["gemm" + key + "_bytes"] / max(1, launches),
                      "avg_launch_us": 1e3 * prof["gemm" + key + "_ms"] / max(1, launches),
                      "fp64_fallback_gemm_tflops": rate(prof["gemm64_flops"], prof["gemm64_ms"])},
     }

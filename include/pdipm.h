@@ -151,6 +151,9 @@ typedef struct ipm_profile {
   double factor_flops;     /* sum over factorisations of sum_j (c_j^2 - 1) */
   int64_t solves;          /* triangular solve pairs */
   double solve_bytes;      /* algorithmic bytes: 2 nnz(L) w + 4 n 8 per pair */
+  double gemm32_bytes;     /* algorithmic bytes of the FP32 GEMM launches: each
+                              operand block read once, C read and written once */
+  double gemm64_bytes;     /* the same for FP64 */
 } ipm_profile;
 
 typedef struct ipm_handle ipm_handle;

@@ -441,9 +441,11 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
     }
     if (prec == PDIPM_FP32) {
       h->prof.gemm32_launches += gl; h->prof.gemm32_ms += gms; h->prof.gemm32_flops += P.gemm_flops;
+      h->prof.gemm32_bytes += P.gemm_bytes;
       h->prof.factorizations32 += 1;
     } else {
       h->prof.gemm64_launches += gl; h->prof.gemm64_ms += gms; h->prof.gemm64_flops += P.gemm_flops;
+      h->prof.gemm64_bytes += P.gemm_bytes;
       h->prof.factorizations64 += 1;
     }
     h->prof.factor_ms += ms;

@@ -469,6 +469,12 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     ++P.gemm_launches;
     for (int64_t q = op.begin; q < op.end; ++q) {
       const GemmDesc& g = P.gemm[q];
+      {
+        const double n = std::min(g.M, g.N);
+        const double c = g.lower ? (double)g.M * g.N - n * (n - 1) / 2 : (double)g.M * g.N;
+        P.gemm_bytes += (double)esize * ((double)g.M * g.K + (g.mode == 1 ? (double)g.K * g.K : (double)g.N * g.K) +
+                                         (g.mode == 1 ? 1.0 : 2.0) * c);
+      }
       if (g.mode == 1) {
         P.gemm_flops += (double)g.M * g.K * g.K;                 // triangular solve
       } else if (g.lower) {

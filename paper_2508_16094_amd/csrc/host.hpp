@@ -125,6 +125,7 @@ struct Plan {
   // algorithmic work of the Schur-update / panel-solve GEMM launches of one
   // factorisation (useful multiply-add flops, triangles not double counted)
   double gemm_flops = 0;
+  double gemm_bytes = 0;   // operand blocks read once, C read and written once
   int64_t gemm_launches = 0;
 };
 

@@ -59,7 +59,8 @@ class ipm_profile(ctypes.Structure):
     _fields_ = [("gemm32_launches", _i64), ("gemm32_ms", _f64), ("gemm32_flops", _f64),
                 ("gemm64_launches", _i64), ("gemm64_ms", _f64), ("gemm64_flops", _f64),
                 ("factorizations32", _i64), ("factorizations64", _i64), ("factor_ms", _f64),
-                ("factor_flops", _f64), ("solves", _i64), ("solve_bytes", _f64)]
+                ("factor_flops", _f64), ("solves", _i64), ("solve_bytes", _f64), ("gemm32_bytes", _f64),
+                ("gemm64_bytes", _f64)]
 
 
 class ipm_start(ctypes.Structure):
