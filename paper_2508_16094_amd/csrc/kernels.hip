@@ -485,23 +485,48 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
   }
 }
 
-// Tile (ti, tj) of descriptor-local tile index t; lower-masked descriptors
-// enumerate column by column only the tiles with ti >= tj.
-__device__ inline void tile_of(const GemmDesc& d, int64_t t, int& ti, int& tj) {
+// Tile (ti, tj) of descriptor-local tile index t.  Tile columns are taken in
+// groups of TG; inside a group the tiles run row by row, so the tiles one
+// XCD holds at a time share the A row block and the group's B blocks in its
+// L2.  Lower-masked descriptors (M >= N) enumerate only tiles with ti >= tj:
+// a group is a triangle of tg rows followed by full rows of tg tiles.
+constexpr int TG = 8;
+__host__ __device__ inline void tile_of(const GemmDesc& d, int64_t t, int& ti, int& tj) {
+  const int64_t m = d.tiles_m, n = d.tiles_n;
   if (!d.lower) {
-    ti = (int)(t % d.tiles_m);
-    tj = (int)(t / d.tiles_m);
+    const int64_t full = n / TG;                 // groups of TG columns
+    const int64_t per = (int64_t)TG * m;
+    int64_t g = t / per;
+    if (g > full) g = full;
+    const int64_t u = t - g * per;
+    const int64_t w = (g < full) ? TG : n - full * TG;
+    ti = (int)(u / w);
+    tj = (int)(g * TG + u % w);
     return;
   }
-  const int64_t m = d.tiles_m;
-  int lo = 0, hi = d.tiles_n - 1;   // largest tj with C(tj) <= t
+  // tiles before group g (all groups before g are full): g (T + TG (m - TG)) - TG^2 g (g - 1) / 2
+  const int64_t T = (int64_t)TG * (TG + 1) / 2;
+  auto start = [&](int64_t g) { return g * (T + (int64_t)TG * (m - TG)) - (int64_t)TG * TG * g * (g - 1) / 2; };
+  const int64_t ng = (n + TG - 1) / TG;
+  int64_t lo = 0, hi = ng - 1;                    // last group with start <= t
   while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int64_t c = (int64_t)mid * m - (int64_t)mid * (mid - 1) / 2;
-    if (c <= t) lo = mid; else hi = mid - 1;
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (start(mid) <= t) lo = mid; else hi = mid - 1;
   }
-  tj = lo;
-  ti = lo + (int)(t - ((int64_t)lo * m - (int64_t)lo * (lo - 1) / 2));
+  const int64_t g = lo, c0 = g * TG;
+  const int64_t w = n - c0 < TG ? n - c0 : TG;
+  int64_t u = t - start(g);
+  const int64_t tri = w * (w + 1) / 2;
+  if (u < tri) {
+    int64_t r = 0;
+    while ((r + 1) * (r + 2) / 2 <= u) ++r;
+    ti = (int)(c0 + r);
+    tj = (int)(c0 + (u - r * (r + 1) / 2));
+  } else {
+    u -= tri;
+    ti = (int)(c0 + w + u / w);
+    tj = (int)(c0 + u % w);
+  }
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
