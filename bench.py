@@ -157,7 +157,7 @@ def bench_warm(args, log):
     log(f"[bench] training set: {ok_train}/{len(res)} solved in {t_train_solve:.1f}s")
     keep = np.array([r["status"] == 0 for r in res])
     dims = [th_train.shape[1], 512, 512, n + m]
-    model = L.MlpModel(dims, n_x=n, max_batch=args.mlp_batch).bind()
+    model = L.MlpModel(dims, n_x=n, max_batch=args.mlp_batch, x_weight=args.mlp_xweight).bind()
     model.set_params(w.mlp_init(dims))
     torch.cuda.synchronize()
     t = time.time()
@@ -286,12 +286,14 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--count", type=int, default=4096, help="qp_batch: number of instances")
     ap.add_argument("--loop-sample", type=int, default=16, help="qp_batch: instances timed one at a time")
-    ap.add_argument("--n-train", type=int, default=1024, help="warm: training instances")
+    ap.add_argument("--n-train", type=int, default=4096, help="warm: training instances")
     ap.add_argument("--n-test", type=int, default=256, help="warm: fresh test instances")
     ap.add_argument("--chunk", type=int, default=128, help="warm: instances per batched solve")
-    ap.add_argument("--mlp-steps", type=int, default=600)
+    ap.add_argument("--mlp-steps", type=int, default=3000)
     ap.add_argument("--mlp-batch", type=int, default=256)
     ap.add_argument("--mlp-lr", type=float, default=1e-3)
+    ap.add_argument("--mlp-xweight", type=float, default=10000.0,
+                    help="warm: weight of the x term of the loss (the log-lambda term dominates otherwise)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"--gpus {args.gpus}: the solver runs one instance on one GPU; multi-GPU sharding "

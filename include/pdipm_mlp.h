@@ -8,7 +8,7 @@
  *   h_0 = theta, h_l = relu(W_l h_{l-1} + b_l) for l < L, z = W_L h_{L-1} + b_L,
  *   x_hat = x_scale * sigmoid(z[0..n_x)), lambda_hat = softplus(z[n_x..dims[L])),
  * trained on the loss
- *   mean (sigmoid(z_x) - x / x_scale)^2 + mean (log(softplus(z_l) + 1e-6) - log(lambda + 1e-6))^2
+ *   x_weight mean (sigmoid(z_x) - x / x_scale)^2 + mean (log(softplus(z_l) + 1e-6) - log(lambda + 1e-6))^2
  * (means over batch rows and the x or lambda outputs) with Adam (beta1 0.9,
  * beta2 0.999, eps 1e-8, bias correction).
  *
@@ -40,10 +40,11 @@ extern "C" {
 typedef struct mlp_handle mlp_handle;
 
 /* n_layers >= 1 linear layers, dims[0..n_layers] (each >= 1), the first n_x
- * outputs are x (0 <= n_x <= dims[n_layers]), max_batch >= 1 rows per call.
+ * outputs are x (0 <= n_x <= dims[n_layers]) in (0, x_scale), x_weight > 0
+ * weighs the x term of the loss, max_batch >= 1 rows per call.
  * Errors: PDIPM_ERR_INVALID_ARG (message in mlp_last_error(NULL)). */
-int mlp_create(int32_t n_layers, const int32_t* dims, int32_t n_x, double x_scale, int32_t max_batch,
-               mlp_handle** out);
+int mlp_create(int32_t n_layers, const int32_t* dims, int32_t n_x, double x_scale, double x_weight,
+               int32_t max_batch, mlp_handle** out);
 int mlp_num_params(mlp_handle* h, int64_t* count);
 int mlp_workspace_query(mlp_handle* h, size_t* bytes);
 /* Device workspace (caller-owned, 256-byte aligned, >= queried bytes). */

@@ -9,7 +9,7 @@ the order a reader would write it:
   h_0 = theta,  h_l = relu(W_l h_{l-1} + b_l)  (hidden layers),
   z = W_L h_{L-1} + b_L,
   x_hat = x_scale * sigmoid(z[:n_x]),  lambda_hat = softplus(z[n_x:]),
-  loss = mean over batch and x outputs of (sigmoid(z_x) - x / x_scale)^2
+  loss = w_x * mean over batch and x outputs of (sigmoid(z_x) - x / x_scale)^2
        + mean over batch and lambda outputs of
          (log(softplus(z_l) + eps) - log(lambda + eps))^2,   eps = 1e-6.
 
@@ -42,7 +42,7 @@ def transform(z, n_x, x_scale=10.0):
     return np.concatenate([x_scale * sigmoid(z[:, :n_x]), softplus(z[:, n_x:])], axis=1)
 
 
-def loss_and_dz(z, target, n_x, x_scale=10.0):
+def loss_and_dz(z, target, n_x, x_scale=10.0, x_weight=1.0):
     """Loss and its gradient with respect to z (target: raw x and lambda)."""
     B = z.shape[0]
     zx, zl = z[:, :n_x], z[:, n_x:]
@@ -52,10 +52,10 @@ def loss_and_dz(z, target, n_x, x_scale=10.0):
     ex = sx - tx
     el = np.log(sp + EPS) - tl
     nx, nl = ex.size, el.size
-    loss = (np.sum(ex * ex) / nx if nx else 0.0) + (np.sum(el * el) / nl if nl else 0.0)
+    loss = (x_weight * np.sum(ex * ex) / nx if nx else 0.0) + (np.sum(el * el) / nl if nl else 0.0)
     dz = np.empty_like(z)
     if nx:
-        dz[:, :n_x] = 2.0 / nx * ex * sx * (1.0 - sx)
+        dz[:, :n_x] = 2.0 * x_weight / nx * ex * sx * (1.0 - sx)
     if nl:
         dz[:, n_x:] = 2.0 / nl * el / (sp + EPS) * sigmoid(zl)
     return loss, dz
@@ -74,14 +74,14 @@ def backward(params, hs, dz):
     return grads
 
 
-def loss_of(params, X, target, n_x, x_scale=10.0):
+def loss_of(params, X, target, n_x, x_scale=10.0, x_weight=1.0):
     _, z = forward(params, X)
-    return loss_and_dz(z, target, n_x, x_scale)[0]
+    return loss_and_dz(z, target, n_x, x_scale, x_weight)[0]
 
 
-def gradients(params, X, target, n_x, x_scale=10.0):
+def gradients(params, X, target, n_x, x_scale=10.0, x_weight=1.0):
     hs, z = forward(params, X)
-    loss, dz = loss_and_dz(z, target, n_x, x_scale)
+    loss, dz = loss_and_dz(z, target, n_x, x_scale, x_weight)
     return loss, backward(params, hs, dz)
 
 

@@ -268,6 +268,7 @@ struct Reg {
 struct mlp_handle {
   int L = 0, n_x = 0, bmax = 0;
   float xs = 10.0f;
+  double xw = 1.0;  // weight of the x term of the loss
   std::vector<int> dims;
   std::vector<int64_t> woff, boff;  // parameter offsets (elements) of W_l, b_l
   int64_t np = 0;
@@ -348,12 +349,12 @@ void backward_pass(mlp_handle* h, const float* target, int B) {
   const int D = d[L];
   const int64_t n = (int64_t)B * D;
   const int nl = D - h->n_x;
-  const float wx = h->n_x ? 1.0f / ((float)B * h->n_x) : 0.0f;
+  const float wx = h->n_x ? (float)(h->xw / ((double)B * h->n_x)) : 0.0f;
   const float wl = nl ? 1.0f / ((float)B * nl) : 0.0f;
   double* lp = h->at<double>(h->o.lpart);
   k_loss<<<RB, BS, 0, h->stream>>>(h->at<float>(h->o.z), target, n, D, h->n_x, h->xs, wx, wl, h->at<float>(h->o.dz),
                                    h->at<bf16>(h->o.dzb), lp);
-  k_loss_final<<<1, 64, 0, h->stream>>>(lp, RB, h->n_x ? 1.0 / ((double)B * h->n_x) : 0.0,
+  k_loss_final<<<1, 64, 0, h->stream>>>(lp, RB, h->n_x ? h->xw / ((double)B * h->n_x) : 0.0,
                                         nl ? 1.0 / ((double)B * nl) : 0.0, h->at<float>(h->o.loss));
   float* g = h->at<float>(h->o.g);
   const bf16* pb = h->at<bf16>(h->o.pb);
@@ -390,8 +391,8 @@ int check_batch(mlp_handle* h, int B) {
 
 extern "C" {
 
-int mlp_create(int32_t n_layers, const int32_t* dims, int32_t n_x, double x_scale, int32_t max_batch,
-               mlp_handle** out) {
+int mlp_create(int32_t n_layers, const int32_t* dims, int32_t n_x, double x_scale, double x_weight,
+               int32_t max_batch, mlp_handle** out) {
   if (!out) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (n_layers < 1 || !dims || max_batch < 1) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "bad layer count or batch");
@@ -399,12 +400,14 @@ int mlp_create(int32_t n_layers, const int32_t* dims, int32_t n_x, double x_scal
     if (dims[l] < 1 || dims[l] > (1 << 24)) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "bad layer size");
   if (n_x < 0 || n_x > dims[n_layers]) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "n_x outside 0..dims[L]");
   if (!(x_scale > 0)) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "x_scale must be positive");
+  if (!(x_weight > 0) || !std::isfinite(x_weight)) return mfail(nullptr, PDIPM_ERR_INVALID_ARG, "x_weight must be positive");
   mlp_handle* h = new (std::nothrow) mlp_handle();
   if (!h) return mfail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
   h->L = n_layers;
   h->dims.assign(dims, dims + n_layers + 1);
   h->n_x = n_x;
   h->xs = (float)x_scale;
+  h->xw = x_weight;
   h->bmax = max_batch;
   int64_t off = 0;
   for (int l = 0; l < n_layers; ++l) {

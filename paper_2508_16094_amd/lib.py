@@ -120,7 +120,7 @@ _SIGS = {
     "ipm_batch_set_b": (ctypes.c_int, [_p, _p]),
     "ipm_batch_last_error": (ctypes.c_char_p, [_p]),
     "ipm_batch_destroy": (None, [_p]),
-    "mlp_create": (ctypes.c_int, [_i32, _p, _i32, _f64, _i32, _p]),
+    "mlp_create": (ctypes.c_int, [_i32, _p, _i32, _f64, _f64, _i32, _p]),
     "mlp_num_params": (ctypes.c_int, [_p, _p]),
     "mlp_workspace_query": (ctypes.c_int, [_p, _p]),
     "mlp_set_workspace": (ctypes.c_int, [_p, _p, ctypes.c_size_t]),
@@ -514,14 +514,14 @@ class MlpModel:
     """Warm-start MLP (pdipm_mlp.h): dims[0] -> ... -> dims[-1], the first n_x
     outputs are x in (0, x_scale), the rest lambda > 0."""
 
-    def __init__(self, dims, n_x, x_scale=10.0, max_batch=256):
+    def __init__(self, dims, n_x, x_scale=10.0, max_batch=256, x_weight=1.0):
         self.h = ctypes.c_void_p()
         self.ws = None
         self.dims = [int(d) for d in dims]
         self.n_x = int(n_x)
         d = np.asarray(self.dims, np.int32)
-        rc = lib().mlp_create(len(self.dims) - 1, _ptr(d), self.n_x, float(x_scale), int(max_batch),
-                              ctypes.byref(self.h))
+        rc = lib().mlp_create(len(self.dims) - 1, _ptr(d), self.n_x, float(x_scale), float(x_weight),
+                              int(max_batch), ctypes.byref(self.h))
         if rc < 0:
             raise PdipmError(rc, "mlp_create: " + lib().mlp_last_error(None).decode())
         c = ctypes.c_int64()

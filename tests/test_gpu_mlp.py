@@ -35,8 +35,8 @@ def _bf16_params(params):
     return [(bf16_round(W), b.astype(np.float32).astype(np.float64)) for W, b in params]
 
 
-def _model(params, max_batch=64):
-    m = L.MlpModel(DIMS, NX, max_batch=max_batch).bind()
+def _model(params, max_batch=64, x_weight=1.0):
+    m = L.MlpModel(DIMS, NX, max_batch=max_batch, x_weight=x_weight).bind()
     m.set_params(params)
     return m
 
@@ -55,11 +55,12 @@ def test_mlp_forward_matches_oracle(B):
     assert np.all(np.abs(out - ref) <= 1e-2 * (1 + np.abs(ref))), np.max(np.abs(out - ref))
 
 
-def test_mlp_gradients_match_oracle():
+@pytest.mark.parametrize("xw", [1.0, 50.0])
+def test_mlp_gradients_match_oracle(xw):
     params, X, T = _setup(seed=2, B=48)
-    m = _model(params)
+    m = _model(params, x_weight=xw)
     loss, grads = m.gradients(_dev(X), _dev(T))
-    lref, gref = omlp.gradients(_bf16_params(params), bf16_round(X), T, NX)
+    lref, gref = omlp.gradients(_bf16_params(params), bf16_round(X), T, NX, x_weight=xw)
     assert abs(loss - lref) <= 2e-2 * lref, (loss, lref)
     for (gW, gb), (rW, rb) in zip(grads, gref):
         for a, r in ((gW, rW), (gb, rb)):

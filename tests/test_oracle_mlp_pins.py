@@ -18,9 +18,10 @@ def _net(seed=3, dims=(5, 7, 6, 5)):
     return params, X, T
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("xw", [1.0, 7.0])
+def test_gradient_matches_central_differences(xw):
     params, X, T = _net()
-    loss, grads = mlp.gradients(params, X, T, n_x=3)
+    loss, grads = mlp.gradients(params, X, T, n_x=3, x_weight=xw)
     assert loss > 0
     worst = 0.0
     for l, (W, b) in enumerate(params):
@@ -29,9 +30,9 @@ def test_gradient_matches_central_differences():
                 h = 1e-6 * max(1.0, abs(arr[idx]))
                 old = arr[idx]
                 arr[idx] = old + h
-                fp = mlp.loss_of(params, X, T, 3)
+                fp = mlp.loss_of(params, X, T, 3, x_weight=xw)
                 arr[idx] = old - h
-                fm = mlp.loss_of(params, X, T, 3)
+                fm = mlp.loss_of(params, X, T, 3, x_weight=xw)
                 arr[idx] = old
                 fd = (fp - fm) / (2 * h)
                 worst = max(worst, abs(fd - g[idx]) / max(1e-3, abs(fd), abs(g[idx])))
