@@ -145,6 +145,13 @@ def lib():
         if not os.path.exists(SO_PATH):
             raise RuntimeError(f"{SO_PATH} is missing: build it with "
                                "`python -m paper_2508_16094_amd.build` (no CPU fallback exists)")
+        # torch ships its own HIP runtime: load it first so that the library
+        # binds to the same runtime instead of a second copy that would then
+        # hide the devices from torch
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(SO_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
