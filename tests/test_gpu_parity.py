@@ -96,6 +96,15 @@ def test_factor_fp32_with_fp64_refinement(n, seed, dense):
     Kn = np.max(np.abs(K).sum(1))
     assert sinfo["ir_steps"] >= 1
     assert np.max(np.abs(K @ x - b)) / (Kn * np.max(np.abs(x))) <= 1e-11
+    # the refined FP32 direction against the FP64 one: forward error within
+    # kappa(K) times the backward errors of both solves
+    s64, _, info64 = _factor_case(K, L.PDIPM_FP64)
+    x64, _ = s64.solve_kkt(dev(b))
+    x64 = x64.cpu().numpy()
+    kappa = np.linalg.cond(K.toarray()) if n <= 2000 else 1e8
+    rel = np.max(np.abs(x - x64)) / np.max(np.abs(x64))
+    print(f"fp32+refinement vs fp64 direction: {rel:.2e} (kappa {kappa:.1e})", flush=True)
+    assert rel <= 1e-12 * kappa
 
 
 def test_not_positive_definite_is_reported():
