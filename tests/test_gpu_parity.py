@@ -1,6 +1,6 @@
 """GPU parity of the HIP hot path against the CPU oracle (through the C ABI).
 
-Bars (written here, derived in the design doc):
+Bars (derived from the arithmetic of each step):
   factor      entries of L within 1e-10 * max|L| (FP64) of the oracle's
               L = chol(P'KP) for the same P; ||P'KP - LL'||_F/||K||_F <= 1e-12
   solve       ||K x - b||_inf / (||K||_inf ||x||_inf) <= 1e-13 (FP64), and
