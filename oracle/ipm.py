@@ -6,7 +6,7 @@ The paper describes the IPM only through its barrier KKT conditions
 primal condensation (eq. kkt_primal), with fixed regularisation
 delta_p = delta_d = 1e-8 as in the MadIPM options (Appendix, solver options)
 and inertia correction on failure (Section 3, Regularization).  Every other
-component is "map or reduce" (Section 1).  The iteration below is the
+component is an elementwise map or a reduction (Section 1).  The iteration below is the
 Mehrotra predictor-corrector scheme of the IPM literature the paper cites
 (Nocedal & Wright), in this order:
 
