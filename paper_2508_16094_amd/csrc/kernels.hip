@@ -772,12 +772,27 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
 // t in LDS, result to ys.  Threads k < bw.
 template <typename T>
 __device__ inline void block_inv_lower(const T* I, int nb, int bw, const double* t, double* ys) {
-  const int k = threadIdx.x;
+  // two threads per row k, each over half of the columns j <= k (coalesced
+  // along k for every j), four independent accumulators; the halves meet in
+  // LDS.  Must be reached by the whole workgroup.
+  __shared__ double hi_part[128];
+  const int k = threadIdx.x & 127, half = threadIdx.x >> 7, hw = nb >> 1;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (k < bw) {
-    double acc = 0.0;
-    for (int j = 0; j <= k; ++j) acc += (double)I[k + (int64_t)j * nb] * t[j];
-    ys[k] = acc;
+    const int j0 = half * hw, j1 = min(k + 1, j0 + hw);
+    const T* col = I + k;
+    int j = j0;
+    for (; j + 3 < j1; j += 4) {
+      a0 += (double)col[(int64_t)j * nb] * t[j];
+      a1 += (double)col[(int64_t)(j + 1) * nb] * t[j + 1];
+      a2 += (double)col[(int64_t)(j + 2) * nb] * t[j + 2];
+      a3 += (double)col[(int64_t)(j + 3) * nb] * t[j + 3];
+    }
+    for (; j < j1; ++j) a0 += (double)col[(int64_t)j * nb] * t[j];
   }
+  if (half) hi_part[k] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (!half && k < bw) ys[k] = ((a0 + a1) + (a2 + a3)) + hi_part[k];
 }
 // Forward solve, large supernodes: collect the children's update vectors,
 // then y for the first column block.
