@@ -222,19 +222,26 @@ def bench_copy(args, log):
     return 0
 
 
+# the GEMM kernels and their tile mapping, as hashed for the traffic record
+GEMM_SOURCE_BEGIN = "constexpr int TG = 8;"
+GEMM_SOURCE_END = "// --------------------------------------------------- triangular solves"
+
+
 def traffic_of(kernel, workload):
     """HBM bytes per launch of kernel on workload measured with hardware
-    counters (profiles/traffic.json), or None when the kernel source changed
-    since the counters were taken."""
+    counters (profiles/traffic.json), or None when the GEMM source (tile
+    mapping and kernels) changed since the counters were taken."""
     import hashlib
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path)).get(f"{kernel}@{workload}")
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        text = open(src).read()
+        a, b = text.index(GEMM_SOURCE_BEGIN), text.index(GEMM_SOURCE_END)
+        digest = hashlib.sha256(text[a:b].encode()).hexdigest()
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernels_hip_sha256") != digest:
+    if not rec or rec.get("gemm_source_sha256") != digest:
         return None
     return rec["bytes_per_launch"]
 
