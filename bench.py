@@ -222,23 +222,27 @@ def bench_copy(args, log):
     return 0
 
 
-# the GEMM kernels and their tile mapping, as hashed for the traffic record
-GEMM_SOURCE_BEGIN = "constexpr int TG = 8;"
-GEMM_SOURCE_END = "// --------------------------------------------------- triangular solves"
+# the FP32 GEMM kernel with its tile mapping and load helpers, as hashed for
+# the traffic record: [tile mapping .. FP64 kernel) + [FP32 kernel .. solves)
+GEMM_SOURCE_REGIONS = (("constexpr int TG = 8;", "// C (-)= A * B^T, FP64 MFMA"),
+                       ("// C (-)= A * B^T, FP32 MFMA", "// --------------------------------------------------- triangular solves"))
+
+
+def gemm_source_digest(text):
+    import hashlib
+    parts = [text[text.index(a):text.index(b)] for a, b in GEMM_SOURCE_REGIONS]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
 def traffic_of(kernel, workload):
     """HBM bytes per launch of kernel on workload measured with hardware
     counters (profiles/traffic.json), or None when the GEMM source (tile
-    mapping and kernels) changed since the counters were taken."""
-    import hashlib
+    mapping, load helpers, FP32 kernel) changed since the counters were taken."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path)).get(f"{kernel}@{workload}")
-        text = open(src).read()
-        a, b = text.index(GEMM_SOURCE_BEGIN), text.index(GEMM_SOURCE_END)
-        digest = hashlib.sha256(text[a:b].encode()).hexdigest()
+        digest = gemm_source_digest(open(src).read())
     except (OSError, ValueError):
         return None
     if not rec or rec.get("gemm_source_sha256") != digest:

@@ -568,12 +568,14 @@ __device__ inline double2u load2(const double* p, int valid) {
   return v;
 }
 
-// C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup, each of the
-// four waves owns a 32x32 quadrant (2x2 MFMA blocks); K chunks of 32 staged
+// C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup of eight
+// waves, each a 16x32 strip (1x2 MFMA blocks: more waves per tile hide the
+// LDS and MFMA latencies better than larger strips); K chunks of 32 staged
 // through LDS with the next chunk prefetched into registers.
-__global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
-                                                 double* ubuf, const double* inv) {
-  constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS;  // 8 per operand
+constexpr int BS64 = 512;  // threads of the FP64 GEMM (8 waves)
+__global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
+                                                   double* ubuf, const double* inv) {
+  constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS64;  // 4 per operand
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -586,22 +588,21 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
   const double* A = panel + d.a_off;
   const double* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 8 r
+  // eight waves: wave w owns rows 16 (w mod 4) .. +16 and columns 32 (w / 4) .. +32
+  const int wm = (wave & 3) * 16, wn = (wave >> 2) * 32;
+  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 16 r
   const int ii = (tid & 31) * 2, kb = tid >> 5;
   const double* Ap = A + (i0 + ii);
   const double* Bp = B + (j0 + ii);
   const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
-  doublex4 acc[2][2];
+  doublex4 acc[2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
+  for (int b = 0; b < 2; ++b) acc[b] = doublex4{0, 0, 0, 0};
   double2u ra[PER / 2], rb[PER / 2];
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < PER / 2; ++r) {
-      const int gk = k0 + kb + 8 * r;
+      const int gk = k0 + kb + 16 * r;
       ra[r] = load2(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load2(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
     }
@@ -610,42 +611,35 @@ __global__ void __launch_bounds__(BS) k_gemm_f64(DevPlan P, int64_t d0, int64_t 
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
     for (int r = 0; r < PER / 2; ++r) {
-      *(double2u*)&As[(kb + 8 * r) * LDS_LD + ii] = ra[r];
-      *(double2u*)&Bs[(kb + 8 * r) * LDS_LD + ii] = rb[r];
+      *(double2u*)&As[(kb + 16 * r) * LDS_LD + ii] = ra[r];
+      *(double2u*)&Bs[(kb + 16 * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
     if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      double a[2], b[2];
+      const double a = As[(kk + (lane >> 4)) * LDS_LD + wm + (lane & 15)];
+      double b[2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        a[q] = As[(kk + (lane >> 4)) * LDS_LD + wm + q * 16 + (lane & 15)];
-        b[q] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + q * 16 + (lane & 15)];
-      }
+      for (int q = 0; q < 2; ++q) b[q] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + q * 16 + (lane & 15)];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
+      for (int y = 0; y < 2; ++y) acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a, acc[y], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int y = 0; y < 2; ++y)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // operands swapped: lanes run along rows of C (contiguous stores)
-        const int i = i0 + wm + x * 16 + (lane & 15);
-        const int j = j0 + wn + y * 16 + 4 * r + (lane >> 4);
-        if (i < d.M && j < d.N && (!d.lower || i >= j)) {
-          double* cp = C + i + (int64_t)j * d.ldc;
-          if (d.mode == 0) *cp -= acc[x][y][r];
-          else *cp = acc[x][y][r];
-        }
+    for (int r = 0; r < 4; ++r) {
+      // operands swapped: lanes run along rows of C (contiguous stores)
+      const int i = i0 + wm + (lane & 15);
+      const int j = j0 + wn + y * 16 + 4 * r + (lane >> 4);
+      if (i < d.M && j < d.N && (!d.lower || i >= j)) {
+        double* cp = C + i + (int64_t)j * d.ldc;
+        if (d.mode == 0) *cp -= acc[y][r];
+        else *cp = acc[y][r];
       }
+    }
 }
 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
@@ -1421,7 +1415,7 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
     case OP_TRSM:
     case OP_UPDATE: {
       const unsigned g8 = (unsigned)((op.grid + 7) / 8 * 8);
-      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g8, BS, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
       else k_gemm_f32<<<g8, BS, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
       break;
     }
