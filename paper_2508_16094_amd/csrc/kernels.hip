@@ -643,11 +643,13 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
 }
 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
-// per workgroup, each wave a 64x64 quadrant (2x2 MFMA blocks); K is staged
-// through LDS in chunks of 32 with the next chunk prefetched into registers.
-__global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
-                                                 float* ubuf, const float* inv) {
-  constexpr int TM = 128, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS;  // 16 per operand
+// per workgroup of eight waves, each a 64x32 strip (2x1 MFMA blocks); K is
+// staged through LDS in chunks of 32 with the next chunk prefetched into
+// registers.
+constexpr int BS32 = 512;  // threads of the FP32 GEMM (8 waves)
+__global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
+                                                   float* ubuf, const float* inv) {
+  constexpr int TM = 128, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
   __shared__ float As[KC * LDS_LD];
   __shared__ float Bs[KC * LDS_LD];
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -660,25 +662,24 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
   const float* A = panel + d.a_off;
   const float* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  // eight waves: wave w owns rows 64 (w mod 2) .. +64 and columns 32 (w / 2) .. +32
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
   // this thread loads 4 consecutive rows (16-byte loads) at k offsets
-  // kb + 8 r; edge rows fall back to guarded scalar loads
+  // kb + 16 r; edge rows fall back to guarded scalar loads
   const int ii = (tid & 31) * 4, kb = tid >> 5;
   const float* Ap = A + (i0 + ii);
   const float* Bp = B + (j0 + ii);
   const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
-  floatx16 acc[2][2];
+  floatx16 acc[2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
   float4u ra[PER / 4], rb[PER / 4];
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < PER / 4; ++r) {
-      const int gk = k0 + kb + 8 * r;
+      const int gk = k0 + kb + 16 * r;
       ra[r] = load4(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load4(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
     }
@@ -687,42 +688,35 @@ __global__ void __launch_bounds__(BS) k_gemm_f32(DevPlan P, int64_t d0, int64_t 
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
     for (int r = 0; r < PER / 4; ++r) {
-      *(float4u*)&As[(kb + 8 * r) * LDS_LD + ii] = ra[r];
-      *(float4u*)&Bs[(kb + 8 * r) * LDS_LD + ii] = rb[r];
+      *(float4u*)&As[(kb + 16 * r) * LDS_LD + ii] = ra[r];
+      *(float4u*)&Bs[(kb + 16 * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
     if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
-      float a[2], b[2];
+      float a[2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        a[q] = As[(kk + (lane >> 5)) * LDS_LD + wm + q * 32 + (lane & 31)];
-        b[q] = Bs[(kk + (lane >> 5)) * LDS_LD + wn + q * 32 + (lane & 31)];
-      }
+      for (int q = 0; q < 2; ++q) a[q] = As[(kk + (lane >> 5)) * LDS_LD + wm + q * 32 + (lane & 31)];
+      const float b = Bs[(kk + (lane >> 5)) * LDS_LD + wn + (lane & 31)];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(b[y], a[x], acc[x][y], 0, 0, 0);
+      for (int x = 0; x < 2; ++x) acc[x] = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a[x], acc[x], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        // operands swapped: lanes run along rows of C (contiguous stores)
-        const int i = i0 + wm + x * 32 + (lane & 31);
-        const int j = j0 + wn + y * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (i < d.M && j < d.N && (!d.lower || i >= j)) {
-          float* cp = C + i + (int64_t)j * d.ldc;
-          if (d.mode == 0) *cp -= acc[x][y][r];
-          else *cp = acc[x][y][r];
-        }
+    for (int r = 0; r < 16; ++r) {
+      // operands swapped: lanes run along rows of C (contiguous stores)
+      const int i = i0 + wm + x * 32 + (lane & 31);
+      const int j = j0 + wn + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (i < d.M && j < d.N && (!d.lower || i >= j)) {
+        float* cp = C + i + (int64_t)j * d.ldc;
+        if (d.mode == 0) *cp -= acc[x][r];
+        else *cp = acc[x][r];
       }
+    }
 }
 
 // --------------------------------------------------- triangular solves
@@ -1416,7 +1410,7 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
     case OP_UPDATE: {
       const unsigned g8 = (unsigned)((op.grid + 7) / 8 * 8);
       if constexpr (sizeof(T) == 8) k_gemm_f64<<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
-      else k_gemm_f32<<<g8, BS, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      else k_gemm_f32<<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
       break;
     }
   }
