@@ -3,7 +3,7 @@
 // gradients and Adam state (interface and formulas in pdipm_mlp.h).
 //
 // Every product C = A B' runs through one tiled kernel: 128 x 128 output
-// tiles, four waves of 64 x 64 (2 x 2 blocks of the 32x32x16 BF16 MFMA), K
+// tiles, eight waves of 64 x 32 (2 x 1 blocks of the 32x32x16 BF16 MFMA), K
 // staged through LDS in chunks of 32 with operands loaded either along K or
 // along the row index (so the transposed products of the backward pass need
 // no transposed copies).  Long reductions are split over workgroups; the
@@ -24,6 +24,7 @@
 namespace {
 
 constexpr int BS = 256;
+constexpr int GBS = 512;                         // threads of the product kernel (8 waves)
 constexpr int TM = 128, KC = 32, LDK = KC + 8;  // LDS rows of 40 BF16 (80 bytes, 16-byte aligned)
 constexpr int RB = 512;                          // blocks of the loss reduction
 
@@ -52,8 +53,8 @@ __device__ inline void stage(const bf16* p, int64_t sr, int64_t sk, int r0, int 
   const int tid = threadIdx.x;
   if (sk == 1) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + q * BS;
+    for (int q = 0; q < (TM * KC / 8) / GBS; ++q) {
+      const int c = tid + q * GBS;
       const int row = c >> 2, kk = (c & 3) * 8;
       const int r = r0 + row, k = k0 + kk;
       const bf16* src = p + (int64_t)r * sr + k;
@@ -72,8 +73,8 @@ __device__ inline void stage(const bf16* p, int64_t sr, int64_t sk, int r0, int 
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + q * BS;
+    for (int q = 0; q < (TM * KC / 8) / GBS; ++q) {
+      const int c = tid + q * GBS;
       const int kk = c >> 4, rr = (c & 15) * 8;
       const int r = r0 + rr, k = k0 + kk;
       const bf16* src = p + (int64_t)k * sk + (int64_t)r * sr;
@@ -91,39 +92,36 @@ __device__ inline void stage(const bf16* p, int64_t sr, int64_t sk, int r0, int 
   }
 }
 
-__global__ void __launch_bounds__(BS) k_gemm_bf16(GemmArgs g) {
+__global__ void __launch_bounds__(GBS) k_gemm_bf16(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) bf16 As[TM * LDK];
   __shared__ __attribute__((aligned(16))) bf16 Bs[TM * LDK];
   const int tm = blockIdx.x / g.tiles_n, tn = blockIdx.x % g.tiles_n;
   const int m0 = tm * TM, n0 = tn * TM;
   const int kb = blockIdx.y * g.kper, ke = std::min(g.K, kb + g.kper);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  floatx16 acc[2][2];
+  // eight waves: wave w owns rows 64 (w mod 2) .. +64 and columns 32 (w / 2) .. +32
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
+  floatx16 acc[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
   for (int k0 = kb; k0 < ke; k0 += KC) {
     stage(g.a, g.sam, g.sak, m0, g.M, k0, ke, As);
     stage(g.b, g.sbn, g.sbk, n0, g.N, k0, ke, Bs);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 16) {
-      bf16x8 af[2], bfr[2];
+      bf16x8 af[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const uint4 va = *(const uint4*)(As + (wm + i * 32 + (lane & 31)) * LDK + ks + 8 * (lane >> 5));
         af[i] = __builtin_bit_cast(bf16x8, va);
-        const uint4 vb = *(const uint4*)(Bs + (wn + i * 32 + (lane & 31)) * LDK + ks + 8 * (lane >> 5));
-        bfr[i] = __builtin_bit_cast(bf16x8, vb);
       }
+      const uint4 vb = *(const uint4*)(Bs + (wn + (lane & 31)) * LDK + ks + 8 * (lane >> 5));
+      const bf16x8 bfr = __builtin_bit_cast(bf16x8, vb);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr, acc[i], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -131,13 +129,11 @@ __global__ void __launch_bounds__(BS) k_gemm_bf16(GemmArgs g) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int m = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        const int n = n0 + wn + j * 32 + (lane & 31);
-        if (m < g.M && n < g.N) out[(int64_t)m * g.N + n] = acc[i][j][e];
-      }
+    for (int e = 0; e < 16; ++e) {
+      const int m = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      const int n = n0 + wn + (lane & 31);
+      if (m < g.M && n < g.N) out[(int64_t)m * g.N + n] = acc[i][e];
+    }
 }
 
 enum { EP_HIDDEN = 0, EP_OUTPUT = 1, EP_GRAD = 2, EP_MASKED = 3 };
@@ -319,7 +315,7 @@ void product(mlp_handle* h, const bf16* a, int64_t sam, int64_t sak, const bf16*
   g.tiles_n = (N + TM - 1) / TM;
   g.out = h->at<float>(h->o.part);
   dim3 grid((unsigned)(((M + TM - 1) / TM) * g.tiles_n), (unsigned)zs);
-  k_gemm_bf16<<<grid, BS, 0, h->stream>>>(g);
+  k_gemm_bf16<<<grid, GBS, 0, h->stream>>>(g);
   const int64_t MN = (int64_t)M * N;
   k_epilogue<<<grid_of(MN), BS, 0, h->stream>>>(g.out, zs, MN, N, bias, mode, mask, ob, of);
 }
