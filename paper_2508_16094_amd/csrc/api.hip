@@ -686,6 +686,7 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
   }
   double delta_w_last = 0.0;
   bool stay64 = false;  // FP32 form: switched to FP64 factors for the rest of the solve
+  int ntri_prev = 0;    // triangular solves of the previous FP32 iteration
   int status = PDIPM_MAX_ITER;
   int it = 0;
   double Pm = 0, Dm = 0, Cm = 0, mu = 0, f = 0;
@@ -794,19 +795,25 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     if ((rc = read_back(h, red_out(h), lim, 2))) return rc;
     const double solve_ms = ms_since(ts0);
     R.ms_solve += solve_ms;
-    // Cost-based switch of the FP32 form: once refinement makes an FP32
-    // iteration dearer than an FP64 one would be (FP64 factor about 2.3x the
-    // FP32 factor time, as the MFMA rates of the two precisions differ;
-    // FP64 solves need no refinement and cost about two FP32 solves), FP64
-    // factors take over for the remaining iterations, where the condition
-    // number and with it the refinement work only grow.
+    // Cost-based switch of the FP32 form: once the next FP32 iteration is
+    // predicted to cost more than an FP64 one, FP64 factors take over for
+    // the remaining iterations, where the condition number and with it the
+    // refinement work only grow.  FP32 prediction: this iteration's factor
+    // time (shift retries included) plus its solves, their count grown by
+    // the ratio to the previous FP32 iteration (between 1 and 2).  FP64
+    // prediction: one factorisation at 2.3x one FP32 factorisation (the MFMA
+    // rates of the two precisions differ) plus two solves without
+    // refinement at about two FP32 solves each.
     if (fp32_iter && !stay64 && O.fp64_fallback && h->need64) {
       const int ntri = 2 + (R.ir_steps - ir_before);
       const double t_tri = solve_ms / ntri, t32 = R.ms_factor - factor_ms_before;
-      if (ntri * t_tri > 1.3 * t32 + 4.0 * t_tri) {
+      const double t1 = t32 / (1 + shifts);
+      const double grow = ntri_prev > 0 ? std::min(2.0, std::max(1.0, (double)ntri / ntri_prev)) : 1.0;
+      if (t32 + grow * ntri * t_tri > 2.3 * t1 + 4.0 * t_tri) {
         stay64 = true;
         R.fp64_refactors++;
       }
+      ntri_prev = ntri;
     }
     if (O.print_level > 1)
       fprintf(stderr, "    solve: ir %d omega %.2e shifts %d fp64 %d delta_w %.1e kmax %.2e sigma %.2e\n",

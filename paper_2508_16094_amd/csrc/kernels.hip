@@ -15,6 +15,7 @@ namespace pdipm {
 namespace {
 
 constexpr int BS = 256;
+constexpr int SBS = 512;  // threads of the blocked triangular-solve steps (8 waves)
 
 inline int64_t blocks_for(int64_t n, int bs = BS) {
   int64_t b = (n + bs - 1) / bs;
@@ -766,7 +767,7 @@ __device__ inline void block_inv_lower(const T* I, int nb, int bw, const double*
   __shared__ double hi_part[128];
   const int k = threadIdx.x & 127, half = threadIdx.x >> 7, hw = nb >> 1;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (k < bw) {
+  if (k < bw && half < 2) {
     const int j0 = half * hw, j1 = min(k + 1, j0 + hw);
     const T* col = I + k;
     int j = j0;
@@ -778,9 +779,9 @@ __device__ inline void block_inv_lower(const T* I, int nb, int bw, const double*
     }
     for (; j < j1; ++j) a0 += (double)col[(int64_t)j * nb] * t[j];
   }
-  if (half) hi_part[k] = (a0 + a1) + (a2 + a3);
+  if (half == 1) hi_part[k] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (!half && k < bw) ys[k] = ((a0 + a1) + (a2 + a3)) + hi_part[k];
+  if (half == 0 && k < bw) ys[k] = ((a0 + a1) + (a2 + a3)) + hi_part[k];
 }
 // Forward solve, large supernodes: collect the children's update vectors,
 // then y for the first column block.
@@ -827,15 +828,15 @@ template <> struct VecOf<double> { typedef double2 type; static constexpr int n 
 
 // Forward solve step of column block J: every item updates its rows with
 // y_J; the owner item (its rows start with block J+1) then forms y_{J+1}.
-// Lanes load VEC consecutive rows of a column with one vector load; the four
+// Lanes load VEC consecutive rows of a column with one vector load; the eight
 // waves split the block's columns and are summed through LDS in a fixed order.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
+__global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
                                                 double* xp, double* ys, double* uvec) {
-  constexpr int VEC = VecOf<T>::n, CPW = 32, RW = 64 * VEC;
+  constexpr int VEC = VecOf<T>::n, NW = SBS / 64, CPW = 128 / NW, RW = 64 * VEC;
   typedef typename VecOf<T>::type V;
   __shared__ double y[128], tb[128];
-  __shared__ double red[4 * RW];
+  __shared__ double red[NW * RW];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int32_t S = d.sn;
   const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
@@ -879,7 +880,9 @@ __global__ void __launch_bounds__(BS) k_fwd_step(DevPlan P, int64_t d0, const T*
     if (tid < RW) {
       const int i = rb + tid;
       if (i >= d.r0 && i < d.r1) {
-        const double sum = (red[tid] + red[RW + tid]) + (red[2 * RW + tid] + red[3 * RW + tid]);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum += red[q * RW + tid];
         if (i < w) {
           const double v = xp[f + i] - sum;
           xp[f + i] = v;
@@ -927,13 +930,13 @@ __global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T
 // Backward solve, large supernodes: partial products L(rows, J)' x(rows)
 // over a row range below column block J.  Each lane loads VEC consecutive
 // rows of a column with one vector load (coalesced along the column), each
-// wave owns 32 columns of the block and keeps one FP64 accumulator per
-// column; the 64 lanes are combined by recursive halving (32 exchanges in
-// all instead of 6 per column).
+// of the eight waves owns 16 columns of the block and keeps one FP64
+// accumulator per column; the 64 lanes are combined by recursive halving
+// (17 exchanges in all instead of 6 per column).
 template <typename T>
-__global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
+__global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
                                                 double* part) {
-  constexpr int CPW = 32, VEC = VecOf<T>::n;
+  constexpr int CPW = 16, VEC = VecOf<T>::n;   // eight waves of 16 columns
   typedef typename VecOf<T>::type V;
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int32_t S = d.sn;
@@ -979,15 +982,14 @@ __global__ void __launch_bounds__(BS) k_bwd_part(DevPlan P, int64_t d0, const T*
       }
     }
   }
-  halve_step<32>(acc, lane & 32, 32);
-  halve_step<16>(acc, lane & 16, 16);
-  halve_step<8>(acc, lane & 8, 8);
-  halve_step<4>(acc, lane & 4, 4);
-  halve_step<2>(acc, lane & 2, 2);
+  halve_step<16>(acc, lane & 32, 32);
+  halve_step<8>(acc, lane & 16, 16);
+  halve_step<4>(acc, lane & 8, 8);
+  halve_step<2>(acc, lane & 4, 4);
+  acc[0] += __shfl_xor(acc[0], 2, 64);
   acc[0] += __shfl_xor(acc[0], 1, 64);
-  const int c = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-                ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-  if ((lane & 1) == 0 && c < d.bw) part[d.part_off + c] = acc[0];
+  const int c = cb + ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+  if ((lane & 3) == 0 && c < d.bw) part[d.part_off + c] = acc[0];
 }
 
 // Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of partials).
@@ -1446,9 +1448,9 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
   switch (op.type) {
     case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec); break;
     case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec); break;
-    case OP_FWD_STEP: k_fwd_step<T><<<g, BS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
+    case OP_FWD_STEP: k_fwd_step<T><<<g, SBS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
     case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
-    case OP_BWD_PART: k_bwd_part<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, part); break;
+    case OP_BWD_PART: k_bwd_part<T><<<g, SBS, 0, s>>>(P, op.begin, panel, ys, part); break;
     case OP_BWD_DIAG: k_bwd_diag<T><<<g, BS, 0, s>>>(P, op.begin, inv, ys, part); break;
   }
 }
