@@ -757,41 +757,67 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
   else if ((int)threadIdx.x < h) uvec[P.suv[S] + threadIdx.x - w] = t[threadIdx.x];
 }
 
-// y = inv(L_JJ) t for a diagonal block (inverse lower triangular, ld nb);
-// t in LDS, result to ys.  Threads k < bw.
-template <typename T>
-__device__ inline void block_inv_lower(const T* I, int nb, int bw, const double* t, double* ys) {
-  // two threads per row k, each over half of the columns j <= k (coalesced
-  // along k for every j), four independent accumulators; the halves meet in
-  // LDS.  Must be reached by the whole workgroup.
-  __shared__ double hi_part[128];
-  const int k = threadIdx.x & 127, half = threadIdx.x >> 7, hw = nb >> 1;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (k < bw && half < 2) {
-    const int j0 = half * hw, j1 = min(k + 1, j0 + hw);
-    const T* col = I + k;
-    int j = j0;
-    for (; j + 3 < j1; j += 4) {
-      a0 += (double)col[(int64_t)j * nb] * t[j];
-      a1 += (double)col[(int64_t)(j + 1) * nb] * t[j + 1];
-      a2 += (double)col[(int64_t)(j + 2) * nb] * t[j + 2];
-      a3 += (double)col[(int64_t)(j + 3) * nb] * t[j + 3];
-    }
-    for (; j < j1; ++j) a0 += (double)col[(int64_t)j * nb] * t[j];
+// Inverse of a diagonal block (lower triangular, column-major, NB x NB
+// storage per block: NB = 128 in FP32, 64 in FP64) held in registers: wave w
+// keeps the columns j = w, w + NW, ... and every lane the rows lane (and
+// lane + 64).  The whole block is requested in one round of independent
+// loads, issued before the vector it multiplies is known, so a dependent
+// chain of solve steps pays one memory latency here instead of one per
+// column group.
+template <int NT, typename T>
+struct InvBlock {
+  static constexpr int NB = sizeof(T) == 4 ? 128 : 64, NW = NT / 64, JPW = NB / NW, RPL = NB / 64;
+  T v[JPW][RPL];
+  __device__ void load(const T* I) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < JPW; ++m)
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[m][r] = I[(lane + 64 * r) + (int64_t)(wave + m * NW) * NB];
   }
-  if (half == 1) hi_part[k] = (a0 + a1) + (a2 + a3);
-  __syncthreads();
-  if (half == 0 && k < bw) ys[k] = ((a0 + a1) + (a2 + a3)) + hi_part[k];
-}
+  // ys[k] = sum over j <= k of inv(k, j) t[j] for k < bw (t in LDS); the
+  // waves' partial sums meet in red (NW * NB doubles of LDS) in a fixed
+  // order.  Entries outside the triangle are never used.  Must be reached by
+  // the whole workgroup.
+  __device__ void lower_times(int bw, const double* t, double* red, double* ys) const {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double a[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) a[r] = 0.0;
+#pragma unroll
+    for (int m = 0; m < JPW; ++m) {
+      const int j = wave + m * NW;
+      const double tj = j < bw ? t[j] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int k = lane + 64 * r;
+        const double p = (double)v[m][r] * tj;
+        a[r] += (k >= j && k < bw && j < bw) ? p : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) red[wave * NB + lane + 64 * r] = a[r];
+    __syncthreads();
+    if (tid < bw) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) sum += red[q * NB + tid];
+      ys[tid] = sum;
+    }
+  }
+};
 // Forward solve, large supernodes: collect the children's update vectors,
 // then y for the first column block.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, const T* inv, double* xp, double* ys,
                                                   double* uvec) {
-  __shared__ double tb[128];
+  typedef InvBlock<BS, T> IB;
+  __shared__ double tb[IB::NB], red[IB::NW * IB::NB];
   const int32_t S = P.slarge[d0 + blockIdx.x];
   const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
   const int64_t uo = P.suv[S];
+  IB ib;
+  ib.load(inv + P.sinv[S]);
   for (int i = threadIdx.x; i < h - w; i += BS) uvec[uo + i] = 0.0;
   __syncthreads();
   for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
@@ -806,10 +832,10 @@ __global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, const 
     }
     __syncthreads();
   }
-  const int bw = w < P.nb ? w : P.nb;
+  const int bw = w < IB::NB ? w : IB::NB;
   if ((int)threadIdx.x < bw) tb[threadIdx.x] = xp[f + threadIdx.x];
   __syncthreads();
-  block_inv_lower(inv + P.sinv[S], P.nb, bw, tb, ys + f);
+  ib.lower_times(bw, tb, red, ys + f);
 }
 
 template <int C>
@@ -830,12 +856,17 @@ template <> struct VecOf<double> { typedef double2 type; static constexpr int n 
 // y_J; the owner item (its rows start with block J+1) then forms y_{J+1}.
 // Lanes load VEC consecutive rows of a column with one vector load; the eight
 // waves split the block's columns and are summed through LDS in a fixed order.
+// y_J comes straight from global memory into registers and the owner's
+// inverse block is requested at the start, so the panel, y and inverse loads
+// of a step are in flight together (the steps of a wide supernode form a
+// dependent chain whose length is set by these latencies).
 template <typename T>
 __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
                                                 double* xp, double* ys, double* uvec) {
+  typedef InvBlock<SBS, T> IB;
   constexpr int VEC = VecOf<T>::n, NW = SBS / 64, CPW = 128 / NW, RW = 64 * VEC;
   typedef typename VecOf<T>::type V;
-  __shared__ double y[128], tb[128];
+  __shared__ double tb[IB::NB], red_inv[IB::NW * IB::NB];
   __shared__ double red[NW * RW];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
   const int32_t S = d.sn;
@@ -843,12 +874,19 @@ __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T
   const int64_t uo = P.suv[S];
   const int bw = d.bw, c0 = d.c0, nc0 = c0 + bw;
   const T* L = panel + P.spanel[S] + (int64_t)c0 * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cb = wave * CPW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), cb = wave * CPW;
   const int ncol = bw - cb < CPW ? bw - cb : CPW;
-  if (tid < bw) y[tid] = ys[f + c0 + tid];
-  __syncthreads();
+  IB ib;
+  if (d.owner) ib.load(inv + P.sinv[S] + (int64_t)(nc0 / IB::NB) * IB::NB * IB::NB);
+  double y[CPW];
+#pragma unroll
+  for (int m = 0; m < CPW; ++m) y[m] = m < ncol ? ys[f + c0 + cb + m] : 0.0;
   for (int rb = d.r0 & ~(VEC - 1); rb < d.r1; rb += RW) {
     const int i0 = rb + lane * VEC;
+    // the row this thread finishes below, read now to overlap the panel loads
+    const int io = rb + tid;
+    const bool mine = tid < RW && io >= d.r0 && io < d.r1;
+    const double old = mine ? (io < w ? xp[f + io] : uvec[uo + io - w]) : 0.0;
     double a[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) a[e] = 0.0;
@@ -868,35 +906,31 @@ __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[e] = (i0 + e >= d.r0 && i0 + e < d.r1) ? p[e] : (T)0;
           }
-          const double yk = y[cb + m];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) a[e] += (double)v[e] * yk;
+          for (int e = 0; e < VEC; ++e) a[e] += (double)v[e] * y[m];
         }
       }
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[wave * RW + lane * VEC + e] = a[e];
     __syncthreads();
-    if (tid < RW) {
-      const int i = rb + tid;
-      if (i >= d.r0 && i < d.r1) {
-        double sum = 0.0;
+    if (mine) {
+      double sum = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) sum += red[q * RW + tid];
-        if (i < w) {
-          const double v = xp[f + i] - sum;
-          xp[f + i] = v;
-          if (d.owner && i - nc0 < 128) tb[i - nc0] = v;
-        } else {
-          uvec[uo + i - w] -= sum;
-        }
+      for (int q = 0; q < NW; ++q) sum += red[q * RW + tid];
+      const double v = old - sum;
+      if (io < w) {
+        xp[f + io] = v;
+        if (d.owner && io - nc0 < IB::NB) tb[io - nc0] = v;
+      } else {
+        uvec[uo + io - w] = v;
       }
     }
     __syncthreads();
   }
   if (d.owner) {
-    const int bw2 = w - nc0 < P.nb ? w - nc0 : P.nb;
-    block_inv_lower(inv + P.sinv[S] + (int64_t)(nc0 / P.nb) * P.nb * P.nb, P.nb, bw2, tb, ys + f + nc0);
+    const int bw2 = w - nc0 < IB::NB ? w - nc0 : IB::NB;
+    ib.lower_times(bw2, tb, red_inv, ys + f + nc0);
   }
 }
 
@@ -943,7 +977,7 @@ __global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T
   const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
   const T* L = panel + P.spanel[S] + (int64_t)d.c0 * ld;   // 16-byte aligned columns
   const int32_t* rows = P.sn_rows + P.srow[S];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cb = wave * CPW;
   double acc[CPW];
 #pragma unroll
@@ -993,52 +1027,75 @@ __global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T
 }
 
 // Backward solve, diagonal block: x_J = inv(L_JJ)' (y_J - sum of partials).
-// Two threads per column sum the partials (fixed order, four independent
-// accumulators each); column k of the inverse is contiguous, so lanes run
-// along it and each wave reduces its 32 columns by recursive halving.
+// All memory traffic is requested up front: each wave's 16 columns of the
+// inverse (column k contiguous, lanes along it), y_J, and the partials, of
+// which every thread sums one column's share with up to 16 loads in flight
+// (groups of threads per column, combined in a fixed order).  Each wave then
+// reduces its 16 columns by recursive halving.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
+__global__ void __launch_bounds__(SBS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
                                                 const double* part) {
-  __shared__ double z[128], zp[128];
+  constexpr int NB = sizeof(T) == 4 ? 128 : 64, CPW = 16, RPL = NB / 64;
+  constexpr int NG = SBS / NB, PU = 16;   // thread groups per column; partial loads per round
+  __shared__ double z[NB], zp[NG * NB];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
-  const int f = P.sfirst[d.sn], nb = P.nb, bw = d.bw;
-  const int tid = threadIdx.x, c = tid & 127, half = tid >> 7;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int f = P.sfirst[d.sn], bw = d.bw;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), cb = wave * CPW;
+  const T* I = inv + P.sinv[d.sn] + (int64_t)(d.c0 / NB) * NB * NB;
+  T v[CPW][RPL];
+  if (cb < NB) {
+#pragma unroll
+    for (int m = 0; m < CPW; ++m)
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[m][r] = I[(lane + 64 * r) + (int64_t)(cb + m) * NB];
+  }
+  const int c = tid % NB, g = tid / NB;
+  const double yv = (g == 0 && c < bw) ? ys[f + d.c0 + c] : 0.0;
+  double sp = 0.0;
   if (c < bw) {
     const double* pp = part + d.part_off + c;
-    int q = half;
-    for (; q + 6 < d.nparts; q += 8) {
-      s0 += pp[(int64_t)q * nb];
-      s1 += pp[(int64_t)(q + 2) * nb];
-      s2 += pp[(int64_t)(q + 4) * nb];
-      s3 += pp[(int64_t)(q + 6) * nb];
-    }
-    for (; q < d.nparts; q += 2) s0 += pp[(int64_t)q * nb];
-  }
-  if (half) zp[c] = (s0 + s1) + (s2 + s3);
-  __syncthreads();
-  if (!half) z[c] = c < bw ? ys[f + d.c0 + c] - (((s0 + s1) + (s2 + s3)) + zp[c]) : 0.0;
-  __syncthreads();
-  const T* I = inv + P.sinv[d.sn] + (int64_t)(d.c0 / nb) * nb * nb;
-  const int lane = tid & 63, wave = tid >> 6, cb = wave * 32;
-  const double z1 = z[lane], z2 = z[lane + 64];
-  double acc[32];
+    for (int q0 = g; q0 < d.nparts; q0 += NG * PU) {
+      double t[PU];
 #pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    const int k = cb + m;
-    const T v1 = (k < bw && lane >= k && lane < bw) ? I[lane + (int64_t)k * nb] : (T)0;
-    const T v2 = (k < bw && lane + 64 < bw) ? I[lane + 64 + (int64_t)k * nb] : (T)0;
-    acc[m] = (double)v1 * z1 + (double)v2 * z2;
+      for (int u = 0; u < PU; ++u) {
+        const int q = q0 + u * NG;
+        t[u] = q < d.nparts ? pp[(int64_t)q * NB] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) sp += t[u];
+    }
   }
-  halve_step<32>(acc, lane & 32, 32);
-  halve_step<16>(acc, lane & 16, 16);
-  halve_step<8>(acc, lane & 8, 8);
-  halve_step<4>(acc, lane & 4, 4);
-  halve_step<2>(acc, lane & 2, 2);
+  zp[g * NB + c] = sp;
+  __syncthreads();
+  if (g == 0) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) tot += zp[q * NB + c];
+    z[c] = c < bw ? yv - tot : 0.0;
+  }
+  __syncthreads();
+  double acc[CPW];
+#pragma unroll
+  for (int m = 0; m < CPW; ++m) {
+    acc[m] = 0.0;
+    if (cb < NB) {
+      const int k = cb + m;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        const double p = (double)v[m][r] * z[i];
+        acc[m] += (k < bw && i >= k && i < bw) ? p : 0.0;
+      }
+    }
+  }
+  halve_step<16>(acc, lane & 32, 32);
+  halve_step<8>(acc, lane & 16, 16);
+  halve_step<4>(acc, lane & 8, 8);
+  halve_step<2>(acc, lane & 4, 4);
+  acc[0] += __shfl_xor(acc[0], 2, 64);
   acc[0] += __shfl_xor(acc[0], 1, 64);
-  const int col = cb + ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-                  ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-  if ((lane & 1) == 0 && col < bw) ys[f + d.c0 + col] = acc[0];
+  const int col = cb + ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+  if ((lane & 3) == 0 && col < bw) ys[f + d.c0 + col] = acc[0];
 }
 
 // -------------------------------------------------------- IPM vectors
@@ -1451,7 +1508,7 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
     case OP_FWD_STEP: k_fwd_step<T><<<g, SBS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
     case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
     case OP_BWD_PART: k_bwd_part<T><<<g, SBS, 0, s>>>(P, op.begin, panel, ys, part); break;
-    case OP_BWD_DIAG: k_bwd_diag<T><<<g, BS, 0, s>>>(P, op.begin, inv, ys, part); break;
+    case OP_BWD_DIAG: k_bwd_diag<T><<<g, SBS, 0, s>>>(P, op.begin, inv, ys, part); break;
   }
 }
 template void launch_solve_op<double>(const Op&, const DevPlan&, const double*, const double*, double*, double*,
