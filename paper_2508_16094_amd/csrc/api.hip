@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -434,10 +435,35 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
   hipEventElapsedTime(&ms, h->ev0, h->ev1);
   if (prof) {
     double gms = 0;
-    for (int64_t i = 0; i < gl; ++i) {
+    // optional diagnostic: GEMM time and rate by launch class (panel solve,
+    // updates at K <= nb, updates at larger K) and by grid size
+    static const bool breakdown = std::getenv("PDIPM_GEMM_BREAKDOWN") != nullptr;
+    double cls_ms[3][3] = {}, cls_fl[3][3] = {};
+    int64_t cls_n[3][3] = {};
+    int64_t li = 0;
+    for (const Op& op : P.ops) {
+      if (op.type != OP_TRSM && op.type != OP_UPDATE) continue;
       float t = 0;
-      hipEventElapsedTime(&t, h->pev[2 * i], h->pev[2 * i + 1]);
+      hipEventElapsedTime(&t, h->pev[2 * li], h->pev[2 * li + 1]);
+      ++li;
       gms += t;
+      if (breakdown) {
+        const int c = op.type == OP_TRSM ? 0 : (P.gemm[op.begin].K <= P.nb ? 1 : 2);
+        const int b = op.grid < 512 ? 0 : (op.grid < 4096 ? 1 : 2);
+        double fl = 0;
+        for (int64_t q = op.begin; q < op.end; ++q) fl += gemm_desc_flops(P.gemm[q]);
+        cls_ms[c][b] += t; cls_fl[c][b] += fl; cls_n[c][b]++;
+      }
+    }
+    if (breakdown) {
+      static const char* cn[3] = {"panel-solve", "update K<=nb", "update K>nb"};
+      static const char* bn[3] = {"<512", "<4096", ">=4096"};
+      for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+          if (cls_n[c][b])
+            fprintf(stderr, "gemm%s %-13s tiles %-6s launches %6lld  %9.2f ms  %7.1f TFLOP/s\n",
+                    prec == PDIPM_FP64 ? "64" : "32", cn[c], bn[b], (long long)cls_n[c][b], cls_ms[c][b],
+                    cls_fl[c][b] / (cls_ms[c][b] * 1e9));
     }
     if (prec == PDIPM_FP32) {
       h->prof.gemm32_launches += gl; h->prof.gemm32_ms += gms; h->prof.gemm32_flops += P.gemm_flops;

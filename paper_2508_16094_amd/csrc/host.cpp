@@ -268,6 +268,15 @@ void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km)
   km->tp.clear();
 }
 
+double gemm_desc_flops(const GemmDesc& g) {
+  if (g.mode == 1) return (double)g.M * g.K * g.K;   // triangular solve
+  if (g.lower) {
+    const double n = std::min(g.M, g.N);
+    return 2.0 * g.K * ((double)g.M * g.N - n * (n - 1) / 2);
+  }
+  return 2.0 * g.K * (double)g.M * g.N;
+}
+
 void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   Plan& P = *pl;
   P = Plan();
@@ -398,11 +407,24 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       else tiles += (int64_t)g.tiles_m * g.tiles_n;
       P.gemm.push_back(g);
     };
-    // two-level blocking: inner blocks of nb columns (diagonal factor, panel
-    // solve, update of the rest of the outer block), then one rank-nbo update
-    // of everything to the right of the outer block
+    // two-level blocking: inner blocks of nb columns, each first updated by
+    // the earlier inner blocks of its outer block (left-looking: one update
+    // of rank c0 - o0 instead of one rank-nb update per earlier block, so the
+    // block's columns are read and written once), then diagonal factor and
+    // panel solve; after the outer block, one rank-nbo update of everything
+    // to its right
     for (int32_t o0 = 0; o0 < maxw; o0 += nbo) {
       for (int32_t c0 = o0; c0 < std::min(o0 + nbo, maxw); c0 += nb) {
+        if (c0 > o0) {
+          int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
+          for (int32_t k : large) {
+            if (P.sw[k] <= c0) continue;
+            const int32_t h = P.sh[k], ld = P.sld[k], bw = std::min(nb, P.sw[k] - c0);
+            add_gemm(P.spanel[k] + (int64_t)c0 * ld + c0, P.spanel[k] + (int64_t)o0 * ld + c0,
+                     P.spanel[k] + (int64_t)o0 * ld + c0, ld, ld, ld, h - c0, bw, c0 - o0, 0, 0, 0, 1, tiles);
+          }
+          if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
+        }
         int64_t pb = (int64_t)P.potrf.size();
         std::vector<int64_t> inv_of(large.size(), -1);
         for (size_t q = 0; q < large.size(); ++q) {
@@ -432,20 +454,6 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
           add_gemm(off, off, inv_of[q], P.sld[k], P.sld[k], nb, M, bw, bw, 0, 1, 1, 0, tiles);
         }
         if (tiles) P.ops.push_back({OP_TRSM, gb, (int64_t)P.gemm.size(), tiles});
-        // update of the remaining columns of the outer block
-        gb = (int64_t)P.gemm.size();
-        tiles = 0;
-        for (size_t q = 0; q < large.size(); ++q) {
-          int32_t k = large[q];
-          if (inv_of[q] < 0) continue;
-          int32_t h = P.sh[k], w = P.sw[k], ld = P.sld[k];
-          int32_t bw = std::min(nb, w - c0);
-          int32_t r0 = c0 + bw, o1 = std::min(o0 + nbo, w);
-          if (o1 - r0 <= 0) continue;
-          add_gemm(P.spanel[k] + (int64_t)r0 * ld + r0, P.spanel[k] + (int64_t)c0 * ld + r0,
-                   P.spanel[k] + (int64_t)c0 * ld + r0, ld, ld, ld, h - r0, o1 - r0, bw, 0, 0, 0, 1, tiles);
-        }
-        if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
       }
       // rank-(outer block) update of the trailing panel columns and of U
       int64_t gb = (int64_t)P.gemm.size(), tiles = 0;
@@ -475,14 +483,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
         P.gemm_bytes += (double)esize * ((double)g.M * g.K + (g.mode == 1 ? (double)g.K * g.K : (double)g.N * g.K) +
                                          (g.mode == 1 ? 1.0 : 2.0) * c);
       }
-      if (g.mode == 1) {
-        P.gemm_flops += (double)g.M * g.K * g.K;                 // triangular solve
-      } else if (g.lower) {
-        const double n = std::min(g.M, g.N);
-        P.gemm_flops += 2.0 * g.K * ((double)g.M * g.N - n * (n - 1) / 2);
-      } else {
-        P.gemm_flops += 2.0 * g.K * (double)g.M * g.N;
-      }
+      P.gemm_flops += gemm_desc_flops(g);
     }
   }
   // ---- triangular solve schedule (same levels; large fronts blocked by nb)

@@ -141,6 +141,9 @@ struct Blocking {
   int small_h = 64;
   int outer_blocks = 0;  // 0: the precision's default (8 FP64, 4 FP32)
 };
+// Useful flops of one GEMM descriptor (lower-masked blocks count only the
+// entries on or below the diagonal; the panel solve counts M K^2).
+double gemm_desc_flops(const GemmDesc& g);
 void build_plan(const Symbolic& s, int precision_bytes, Plan* plan, const Blocking& blk = Blocking());
 void map_k_to_panels(const Symbolic& s, const Plan& plan, KMap* km);
 
