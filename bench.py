@@ -234,10 +234,12 @@ def gemm_source_digest(text):
     return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
-def traffic_of(kernel, workload):
+def traffic_of(kernel, workload, alg_bytes_per_launch):
     """HBM bytes per launch of kernel on workload measured with hardware
     counters (profiles/traffic.json), or None when the GEMM source (tile
-    mapping, load helpers, FP32 kernel) changed since the counters were taken."""
+    mapping, load helpers, FP32 kernel) changed since the counters were taken,
+    or when the launch mix did (the algorithmic bytes per launch differ from
+    the recorded ones by more than 0.5%)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc", "kernels.hip")
     try:
@@ -246,6 +248,9 @@ def traffic_of(kernel, workload):
     except (OSError, ValueError):
         return None
     if not rec or rec.get("gemm_source_sha256") != digest:
+        return None
+    ref = rec.get("algorithmic_bytes_per_launch")
+    if not ref or abs(alg_bytes_per_launch - ref) > 0.005 * ref:
         return None
     return rec["bytes_per_launch"]
 
@@ -388,7 +393,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
                      "frac": gemm_tf / PEAK[pkey],
                      "traffic": traffic_of("k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
-                                           f"lp_block{args.nblocks}") if args.workload == "lp_block" else None,
+                                           f"lp_block{args.nblocks}",
+                                           prof["gemm" + key + "_bytes"] / max(1, launches))
+                     if args.workload == "lp_block" else None,
                      "kernel": "k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
                      "launches": launches,
                      "algorithmic_bytes_per_launch": prof["gemm" + key + "_bytes"] / max(1, launches),

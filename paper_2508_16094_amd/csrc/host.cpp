@@ -390,7 +390,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     if (large.empty()) continue;
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
-    const int tm = esize == 8 ? 64 : 128;  // gemm tile
+    const int tm = esize == 8 ? GEMM_TILE_F64 : GEMM_TILE_F32;
     auto add_gemm = [&](int64_t c_off, int64_t a_off, int64_t b_off, int32_t ldc, int32_t lda, int32_t ldb,
                         int32_t M, int32_t N, int32_t K, int32_t c_buf, int32_t b_buf, int32_t mode,
                         int32_t lower, int64_t& tiles) {

@@ -49,6 +49,13 @@ struct KMap {
 };
 
 // Launch descriptors (offsets are element offsets in the named buffers).
+// Square tile edge of the Schur-update / panel-solve GEMM kernels.  FP64
+// 128 x 128 tiles (KC 16) ran the rank-512 updates 3% faster than 64 x 64
+// but wasted half of every tile of the 64-column panel solves and inner
+// updates: no net gain, so FP64 keeps 64 x 64.
+constexpr int GEMM_TILE_F32 = 128;
+constexpr int GEMM_TILE_F64 = 64;
+
 struct GemmDesc {          // C (-)= A * B^T on an M x N block, K inner
   int64_t c_off, a_off, b_off;
   int32_t ldc, lda, ldb;

@@ -569,14 +569,17 @@ __device__ inline double2u load2(const double* p, int valid) {
   return v;
 }
 
-// C (-)= A * B^T, FP64 MFMA 16x16x4.  64x64 tile per workgroup of eight
-// waves, each a 16x32 strip (1x2 MFMA blocks: more waves per tile hide the
-// LDS and MFMA latencies better than larger strips); K chunks of 32 staged
-// through LDS with the next chunk prefetched into registers.
+// C (-)= A * B^T, FP64 MFMA 16x16x4.  TM x TM tile per workgroup of eight
+// waves, each a (16 BX) x (16 BY) strip of BX x BY MFMA blocks; K chunks of
+// 32 (16 for 128 x 128 tiles, to fit two workgroups per CU) staged through
+// LDS with the next chunk prefetched into registers.
 constexpr int BS64 = 512;  // threads of the FP64 GEMM (8 waves)
 __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
                                                    double* ubuf, const double* inv) {
-  constexpr int TM = 64, KC = 32, LDS_LD = TM + 2, PER = (TM * KC) / BS64;  // 4 per operand
+  constexpr int TM = GEMM_TILE_F64, BX = TM == 128 ? 4 : 1, BY = 2;
+  constexpr int WX = TM / (16 * BX);                       // waves along rows
+  static_assert(WX * (TM / (16 * BY)) == BS64 / 64, "eight waves per tile");
+  constexpr int KC = TM == 128 ? 16 : 32, LDS_LD = TM + 2, TPR = TM / 2, KS = BS64 / TPR, PER = KC / KS;
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -589,21 +592,22 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
   const double* A = panel + d.a_off;
   const double* B = (d.b_buf ? inv : panel) + d.b_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // eight waves: wave w owns rows 16 (w mod 4) .. +16 and columns 32 (w / 4) .. +32
-  const int wm = (wave & 3) * 16, wn = (wave >> 2) * 32;
-  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + 16 r
-  const int ii = (tid & 31) * 2, kb = tid >> 5;
+  const int wm = (wave % WX) * 16 * BX, wn = (wave / WX) * 16 * BY;
+  // this thread loads 2 consecutive rows (16-byte loads) at k offsets kb + KS r
+  const int ii = (tid % TPR) * 2, kb = tid / TPR;
   const double* Ap = A + (i0 + ii);
   const double* Bp = B + (j0 + ii);
   const int arows = d.M - (i0 + ii), brows = d.N - (j0 + ii);
-  doublex4 acc[2];
+  doublex4 acc[BX][BY];
 #pragma unroll
-  for (int b = 0; b < 2; ++b) acc[b] = doublex4{0, 0, 0, 0};
-  double2u ra[PER / 2], rb[PER / 2];
+  for (int x = 0; x < BX; ++x)
+#pragma unroll
+    for (int y = 0; y < BY; ++y) acc[x][y] = doublex4{0, 0, 0, 0};
+  double2u ra[PER], rb[PER];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < PER / 2; ++r) {
-      const int gk = k0 + kb + 16 * r;
+    for (int r = 0; r < PER; ++r) {
+      const int gk = k0 + kb + KS * r;
       ra[r] = load2(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load2(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
     }
@@ -611,36 +615,41 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
   load(0);
   for (int k0 = 0; k0 < d.K; k0 += KC) {
 #pragma unroll
-    for (int r = 0; r < PER / 2; ++r) {
-      *(double2u*)&As[(kb + 16 * r) * LDS_LD + ii] = ra[r];
-      *(double2u*)&Bs[(kb + 16 * r) * LDS_LD + ii] = rb[r];
+    for (int r = 0; r < PER; ++r) {
+      *(double2u*)&As[(kb + KS * r) * LDS_LD + ii] = ra[r];
+      *(double2u*)&Bs[(kb + KS * r) * LDS_LD + ii] = rb[r];
     }
     __syncthreads();
     if (k0 + KC < d.K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      const double a = As[(kk + (lane >> 4)) * LDS_LD + wm + (lane & 15)];
-      double b[2];
+      double a[BX], b[BY];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) b[q] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + q * 16 + (lane & 15)];
+      for (int x = 0; x < BX; ++x) a[x] = As[(kk + (lane >> 4)) * LDS_LD + wm + x * 16 + (lane & 15)];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a, acc[y], 0, 0, 0);
+      for (int y = 0; y < BY; ++y) b[y] = Bs[(kk + (lane >> 4)) * LDS_LD + wn + y * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < BX; ++x)
+#pragma unroll
+        for (int y = 0; y < BY; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int y = 0; y < 2; ++y)
+  for (int x = 0; x < BX; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      // operands swapped: lanes run along rows of C (contiguous stores)
-      const int i = i0 + wm + (lane & 15);
-      const int j = j0 + wn + y * 16 + 4 * r + (lane >> 4);
-      if (i < d.M && j < d.N && (!d.lower || i >= j)) {
-        double* cp = C + i + (int64_t)j * d.ldc;
-        if (d.mode == 0) *cp -= acc[y][r];
-        else *cp = acc[y][r];
+    for (int y = 0; y < BY; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // operands swapped: lanes run along rows of C (contiguous stores)
+        const int i = i0 + wm + x * 16 + (lane & 15);
+        const int j = j0 + wn + y * 16 + 4 * r + (lane >> 4);
+        if (i < d.M && j < d.N && (!d.lower || i >= j)) {
+          double* cp = C + i + (int64_t)j * d.ldc;
+          if (d.mode == 0) *cp -= acc[x][y][r];
+          else *cp = acc[x][y][r];
+        }
       }
-    }
 }
 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
@@ -650,7 +659,8 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
 constexpr int BS32 = 512;  // threads of the FP32 GEMM (8 waves)
 __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
                                                    float* ubuf, const float* inv) {
-  constexpr int TM = 128, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
+  constexpr int TM = GEMM_TILE_F32, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
+  static_assert(TM == 128, "the FP32 wave layout assumes 128 x 128 tiles");
   __shared__ float As[KC * LDS_LD];
   __shared__ float Bs[KC * LDS_LD];
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
