@@ -567,6 +567,11 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       P.bwd_ops.push_back({OP_BWD_DIAG, qb, (int64_t)P.sdesc.size(), (int64_t)P.sdesc.size() - qb});
     }
   }
+  for (SolveDesc& d : P.sdesc) {
+    const int32_t k = d.sn;
+    d.w = P.sw[k]; d.first = P.sfirst[k]; d.ld = P.sld[k];
+    d.panel_off = P.spanel[k]; d.uvec_off = P.suv[k]; d.inv_off = P.sinv[k]; d.row_off = P.srow[k];
+  }
 }
 
 void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {

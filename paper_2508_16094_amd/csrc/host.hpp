@@ -84,10 +84,17 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
 // [c0, c0 + bw) over rows [r0, r1) below the block.  Forward: the owner
 // item also forms y of the next block.  Backward: partial products go to
 // part[part_off ..]; a diagonal item sums its nparts partials and solves.
+// The supernode's own fields are copied in, so that a solve kernel reaches
+// its data after one dependent load (the descriptor) instead of two.
 struct SolveDesc {
   int32_t sn, c0, bw, r0, r1, owner;
   int64_t part_off;
-  int32_t nparts, pad;
+  int32_t nparts, w;       // w: supernode width
+  int64_t panel_off;       // panel offset of the supernode
+  int64_t uvec_off;        // its update-vector offset
+  int64_t inv_off;         // its diagonal-block inverses
+  int64_t row_off;         // its row list
+  int32_t first, ld;       // first column, panel leading dimension
 };
 
 enum OpType {

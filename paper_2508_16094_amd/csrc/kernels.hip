@@ -879,15 +879,14 @@ __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T
   __shared__ double tb[IB::NB], red_inv[IB::NW * IB::NB];
   __shared__ double red[NW * RW];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
-  const int32_t S = d.sn;
-  const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
-  const int64_t uo = P.suv[S];
+  const int w = d.w, f = d.first, ld = d.ld;
+  const int64_t uo = d.uvec_off;
   const int bw = d.bw, c0 = d.c0, nc0 = c0 + bw;
-  const T* L = panel + P.spanel[S] + (int64_t)c0 * ld;
+  const T* L = panel + d.panel_off + (int64_t)c0 * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), cb = wave * CPW;
   const int ncol = bw - cb < CPW ? bw - cb : CPW;
   IB ib;
-  if (d.owner) ib.load(inv + P.sinv[S] + (int64_t)(nc0 / IB::NB) * IB::NB * IB::NB);
+  if (d.owner) ib.load(inv + d.inv_off + (int64_t)(nc0 / IB::NB) * IB::NB * IB::NB);
   double y[CPW];
 #pragma unroll
   for (int m = 0; m < CPW; ++m) y[m] = m < ncol ? ys[f + c0 + cb + m] : 0.0;
@@ -983,10 +982,9 @@ __global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T
   constexpr int CPW = 16, VEC = VecOf<T>::n;   // eight waves of 16 columns
   typedef typename VecOf<T>::type V;
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
-  const int32_t S = d.sn;
-  const int w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
-  const T* L = panel + P.spanel[S] + (int64_t)d.c0 * ld;   // 16-byte aligned columns
-  const int32_t* rows = P.sn_rows + P.srow[S];
+  const int w = d.w, f = d.first, ld = d.ld;
+  const T* L = panel + d.panel_off + (int64_t)d.c0 * ld;   // 16-byte aligned columns
+  const int32_t* rows = P.sn_rows + d.row_off;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cb = wave * CPW;
   double acc[CPW];
@@ -1049,9 +1047,9 @@ __global__ void __launch_bounds__(SBS) k_bwd_diag(DevPlan P, int64_t d0, const T
   constexpr int NG = SBS / NB, PU = 16;   // thread groups per column; partial loads per round
   __shared__ double z[NB], zp[NG * NB];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
-  const int f = P.sfirst[d.sn], bw = d.bw;
+  const int f = d.first, bw = d.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), cb = wave * CPW;
-  const T* I = inv + P.sinv[d.sn] + (int64_t)(d.c0 / NB) * NB * NB;
+  const T* I = inv + d.inv_off + (int64_t)(d.c0 / NB) * NB * NB;
   T v[CPW][RPL];
   if (cb < NB) {
 #pragma unroll
