@@ -224,27 +224,35 @@ def bench_copy(args, log):
 
 # the FP32 GEMM kernel with its tile mapping and load helpers, as hashed for
 # the traffic record: [tile mapping .. FP64 kernel) + [FP32 kernel .. solves)
-GEMM_SOURCE_REGIONS = (("constexpr int TG = 8;", "// C (-)= A * B^T, FP64 MFMA"),
-                       ("// C (-)= A * B^T, FP32 MFMA", "// --------------------------------------------------- triangular solves"))
+GEMM_SOURCE_REGIONS = (("kernels.hip", "constexpr int TG = 8;", "// C (-)= A * B^T, FP64 MFMA"),
+                       ("kernels.hip", "// C (-)= A * B^T, FP32 MFMA",
+                        "// --------------------------------------------------- triangular solves"),
+                       ("host.cpp", "// columns of large fronts start", "P.srow[k] = s.sn_rowptr[k];"))
 
 
-def gemm_source_digest(text):
+def gemm_source_digest():
+    """sha256 over the source regions that decide the GEMM's memory traffic:
+    tile mapping and load helpers, the FP32 kernel, the panel layout."""
     import hashlib
-    parts = [text[text.index(a):text.index(b)] for a, b in GEMM_SOURCE_REGIONS]
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc")
+    parts = []
+    for fn, a, b in GEMM_SOURCE_REGIONS:
+        text = open(os.path.join(csrc, fn)).read()
+        parts.append(text[text.index(a):text.index(b)])
     return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
 def traffic_of(kernel, workload, alg_bytes_per_launch):
     """HBM bytes per launch of kernel on workload measured with hardware
     counters (profiles/traffic.json), or None when the GEMM source (tile
-    mapping, load helpers, FP32 kernel) changed since the counters were taken,
+    mapping, load helpers, FP32 kernel, panel layout) changed since the
+    counters were taken,
     or when the launch mix did (the algorithmic bytes per launch differ from
     the recorded ones by more than 0.5%)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path)).get(f"{kernel}@{workload}")
-        digest = gemm_source_digest(open(src).read())
+        digest = gemm_source_digest()
     except (OSError, ValueError):
         return None
     if not rec or rec.get("gemm_source_sha256") != digest:
