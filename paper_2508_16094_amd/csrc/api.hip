@@ -778,13 +778,15 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     auto ts0 = clk::now();
     kkt_solve_info si{};
     // refinement target: the stationarity error a solve leaves behind stays
-    // below 1% of the tolerance on the scaled dual infeasibility
+    // below 1% of the tolerance on the scaled dual infeasibility; the affine
+    // predictor, which only sets sigma and the second-order term of the
+    // corrector, stops at 10%
     const double target = 1e-2 * O.tol * (1.0 + S.maxgf);
     auto direction = [&](const double* tsv, const double* tlv, const double* tuv, double* dx, double* ds,
                          double* dl, double* dzl, double* dzu) -> int {
       launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
       bool conv = false;
-      int r2 = solve_refined(h, h->rhs, dx, &si, target, &conv);
+      int r2 = solve_refined(h, h->rhs, dx, &si, tsv ? target : 10.0 * target, &conv);
       if (r2) return r2;
       if (!conv && h->factor_prec == PDIPM_FP32 && h->need64) {
         // FP32 refinement cannot reach the target: FP64 factors from here on
