@@ -227,7 +227,7 @@ def bench_copy(args, log):
 GEMM_SOURCE_REGIONS = (("kernels.hip", "constexpr int TG = 8;", "// C (-)= A * B^T, FP64 MFMA"),
                        ("kernels.hip", "// C (-)= A * B^T, FP32 MFMA",
                         "// --------------------------------------------------- triangular solves"),
-                       ("host.cpp", "// columns of large fronts start", "P.srow[k] = s.sn_rowptr[k];"))
+                       ("host.cpp", "P.sld[k] =", "P.srow[k] = s.sn_rowptr[k];"))
 
 
 def gemm_source_digest():

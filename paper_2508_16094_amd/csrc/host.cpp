@@ -285,7 +285,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   // outer block: rank of the trailing update (a multiple of nb); by default
   // 512 columns in both precisions (FP64: eight 64-column blocks)
   const int nbo = P.nb * (blk.outer_blocks > 0 ? blk.outer_blocks : (esize == 8 ? 8 : 4));
-  P.small_h = blk.small_h > 0 && blk.small_h <= 64 ? blk.small_h : 64;
+  P.small_h = blk.small_h > 0 && blk.small_h <= SMALL_H_MAX ? blk.small_h : SMALL_H_MAX;
   const int64_t ns = s.nsuper();
   P.ns = ns;
   P.n = s.n;
@@ -296,10 +296,12 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     P.sfirst[k] = s.sn_start[k];
     P.sw[k] = s.sn_start[k + 1] - s.sn_start[k];
     P.sh[k] = (int32_t)(s.sn_rowptr[k + 1] - s.sn_rowptr[k]);
-    // columns of large fronts start on 128-byte boundaries (the GEMM tiles
-    // then touch no partial cache lines: +5% GEMM rate); small fronts keep
-    // 16-byte alignment
-    P.sld[k] = P.sh[k] > P.small_h ? (P.sh[k] + 31) & ~31 : (P.sh[k] + 3) & ~3;
+    // columns of fronts taller than any small-front limit start on 128-byte
+    // boundaries (the GEMM tiles then touch no partial cache lines: +5% GEMM
+    // rate), the others on 16-byte ones.  The rule must not depend on the
+    // blocking: the map of K entries to panel positions is built once and
+    // serves every blocking the autotuner tries.
+    P.sld[k] = P.sh[k] > SMALL_H_MAX ? (P.sh[k] + 31) & ~31 : (P.sh[k] + 3) & ~3;
     P.srow[k] = s.sn_rowptr[k];
     for (int32_t j = s.sn_start[k]; j < s.sn_start[k + 1]; ++j) col2sn[j] = (int32_t)k;
   }

@@ -49,6 +49,9 @@ struct KMap {
 };
 
 // Launch descriptors (offsets are element offsets in the named buffers).
+// Largest front height factored by the one-workgroup small-front kernel.
+constexpr int SMALL_H_MAX = 64;
+
 // Square tile edge of the Schur-update / panel-solve GEMM kernels.  FP64
 // 128 x 128 tiles (KC 16) ran the rank-512 updates 3% faster than 64 x 64
 // but wasted half of every tile of the 64-column panel solves and inner

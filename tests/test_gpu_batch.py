@@ -105,6 +105,22 @@ def test_batch_autotune_and_blockings():
     _check(ps, refs, results, b.solution())
 
 
+@pytest.mark.parametrize("precision", [L.PDIPM_FP64, L.PDIPM_FP32])
+def test_batch_every_blocking(precision):
+    """Every autotuner candidate solves the batch: the map of K entries to
+    panel positions is built once, so the panel layout must not depend on
+    the blocking (fronts of height 33-64 are small under one candidate and
+    blocked under another)."""
+    ps = _problems()
+    refs = _refs(ps)
+    b = L.BatchSolver(ps, precision=precision).bind()
+    for idx in range(len(b.blockings())):
+        b.set_blocking(idx)
+        results, info = b.solve()
+        assert info["blocking"] == idx
+        _check(ps, refs, results, b.solution())
+
+
 def test_batch_warm_start():
     ps = _problems()
     refs = _refs(ps)
