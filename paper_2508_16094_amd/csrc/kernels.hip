@@ -340,12 +340,23 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tr = tid >> 4, tc = tid & 15;
   T* g = panel + d.d_off;
-  for (int idx = tid; idx < NB * NB; idx += BS) {
-    const int i = idx % NB, j = idx / NB;
-    T v = (T)0;
-    if (i < bw && j < bw) { if (i >= j) v = g[i + (int64_t)j * d.ld]; }
-    else if (i == j) v = (T)1;
-    A[i + j * LDA] = v;
+  // load the block with CH independent loads in flight per thread (a plain
+  // strided loop waits for each load before the next)
+  constexpr int PER = NB * NB / BS, CH = PER < 32 ? PER : 32;
+  static_assert(PER % CH == 0, "block load chunks");
+#pragma unroll
+  for (int c0 = 0; c0 < PER; c0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int idx = tid + (c0 + u) * BS, i = idx % NB, j = idx / NB;
+      v[u] = (i < bw && j < bw && i >= j) ? g[i + (int64_t)j * d.ld] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int idx = tid + (c0 + u) * BS, i = idx % NB, j = idx / NB;
+      A[i + j * LDA] = (i < bw && j < bw) ? v[u] : (i == j ? (T)1 : (T)0);
+    }
   }
   if (tid < NB) xd[tid] = (T)1;
   __syncthreads();
