@@ -335,6 +335,7 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
   constexpr int PB = 16, NP = NB / PB, LDA = NB + 1, TS = NB / 16, S = NB / 64;
   __shared__ T A[NB * LDA];
   __shared__ T xd[NB];
+  __shared__ T rdiag[NB];   // 1 / L(k, k)
   const PotrfDesc d = P.potrf[d0 + blockIdx.x];
   const int bw = d.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -379,6 +380,7 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
           dk = (T)1;
         }
         const T piv = sqrt(dk), rp = (T)1 / piv;
+        if (lane == 0) rdiag[c0 + k] = rp;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int rel = lane + 64 * s;
@@ -435,15 +437,21 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
   for (int p = 0; p < NP; ++p) {
     const int c0 = p * PB, c1 = c0 + PB;
     if (tid < c1) {
+      // column j of L_pp X_p = B_p, column-oriented: once x_t is known it
+      // updates every later row at once (a dependent chain of PB steps
+      // instead of PB (PB - 1) / 2), the diagonal applied as 1 / L(i, i)
       const int j = tid;
       T x[PB];
 #pragma unroll
       for (int r = 0; r < PB; ++r) {
         const int i = c0 + r;
-        T sum = j < i ? A[j + i * LDA] : (j == i ? xd[i] : (T)0);
+        x[r] = j < i ? A[j + i * LDA] : (j == i ? xd[i] : (T)0);
+      }
 #pragma unroll
-        for (int t = 0; t < r; ++t) sum -= A[i + (c0 + t) * LDA] * x[t];
-        x[r] = sum / A[i + i * LDA];
+      for (int t = 0; t < PB; ++t) {
+        x[t] *= rdiag[c0 + t];
+#pragma unroll
+        for (int r = t + 1; r < PB; ++r) x[r] -= A[(c0 + r) + (c0 + t) * LDA] * x[t];
       }
 #pragma unroll
       for (int r = 0; r < PB; ++r) {
