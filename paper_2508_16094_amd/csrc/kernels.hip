@@ -330,32 +330,39 @@ __device__ inline double lane_bcast(double v, int src) {
 //            subtract L(below, p) X_p from the rows below.
 // X is kept transposed in the (zero) upper triangle of the same LDS array
 // and its diagonal in xd, so one NB x (NB + 1) array holds both factors.
-template <typename T, int NB>
-__global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
-  constexpr int PB = 16, NP = NB / PB, LDA = NB + 1, TS = NB / 16, S = NB / 64;
+// PT threads in a (PT / 16) x 16 grid of register tiles.  FP32 launches of
+// at most one block per CU take 8 waves (the chain of diagonal blocks of a
+// wide supernode is latency-bound: 135 instead of 190 us per block); larger
+// launches and FP64 take 4 waves (two workgroups per CU; 8 waves would not
+// fit the FP64 panel work in registers).
+template <typename T, int NB, int PT>
+__global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
+  constexpr int GR = PT / 16, GC = 16, PB = 16, NP = NB / PB, LDA = NB + 1, S = NB / 64;
+  constexpr int TR = NB / GR, TC = NB / GC;   // rows and columns of a thread's tile
+  static_assert(GR * GC == PT && TR * GR == NB && TC * GC == NB, "thread grid");
   __shared__ T A[NB * LDA];
   __shared__ T xd[NB];
   __shared__ T rdiag[NB];   // 1 / L(k, k)
   const PotrfDesc d = P.potrf[d0 + blockIdx.x];
   const int bw = d.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tr = tid >> 4, tc = tid & 15;
+  const int tr = tid / GC, tc = tid % GC;
   T* g = panel + d.d_off;
   // load the block with CH independent loads in flight per thread (a plain
   // strided loop waits for each load before the next)
-  constexpr int PER = NB * NB / BS, CH = PER < 32 ? PER : 32;
+  constexpr int PER = NB * NB / PT, CH = PER < 32 ? PER : 32;
   static_assert(PER % CH == 0, "block load chunks");
 #pragma unroll
   for (int c0 = 0; c0 < PER; c0 += CH) {
     T v[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int idx = tid + (c0 + u) * BS, i = idx % NB, j = idx / NB;
+      const int idx = tid + (c0 + u) * PT, i = idx % NB, j = idx / NB;
       v[u] = (i < bw && j < bw && i >= j) ? g[i + (int64_t)j * d.ld] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int idx = tid + (c0 + u) * BS, i = idx % NB, j = idx / NB;
+      const int idx = tid + (c0 + u) * PT, i = idx % NB, j = idx / NB;
       A[i + j * LDA] = (i < bw && j < bw) ? v[u] : (i == j ? (T)1 : (T)0);
     }
   }
@@ -405,29 +412,29 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
     }
     __syncthreads();
     // trailing update of rows and columns >= c1 (lower part)
-    if (c1 < NB && tr >= tc && tr * TS + TS > c1 && tc * TS + TS > c1) {
-      T acc[TS][TS];
+    if (c1 < NB && tr * TR + TR - 1 >= tc * TC && tr * TR + TR > c1 && tc * TC + TC > c1) {
+      T acc[TR][TC];
 #pragma unroll
-      for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < TR; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) acc[r][c] = (T)0;
+        for (int c = 0; c < TC; ++c) acc[r][c] = (T)0;
 #pragma unroll 4
       for (int t = 0; t < PB; ++t) {
-        T li[TS], lj[TS];
+        T li[TR], lj[TC];
 #pragma unroll
-        for (int r = 0; r < TS; ++r) li[r] = A[tr * TS + r + (c0 + t) * LDA];
+        for (int r = 0; r < TR; ++r) li[r] = A[tr * TR + r + (c0 + t) * LDA];
 #pragma unroll
-        for (int c = 0; c < TS; ++c) lj[c] = A[tc * TS + c + (c0 + t) * LDA];
+        for (int c = 0; c < TC; ++c) lj[c] = A[tc * TC + c + (c0 + t) * LDA];
 #pragma unroll
-        for (int r = 0; r < TS; ++r)
+        for (int r = 0; r < TR; ++r)
 #pragma unroll
-          for (int c = 0; c < TS; ++c) acc[r][c] += li[r] * lj[c];
+          for (int c = 0; c < TC; ++c) acc[r][c] += li[r] * lj[c];
       }
 #pragma unroll
-      for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < TR; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-          const int i = tr * TS + r, j = tc * TS + c;
+        for (int c = 0; c < TC; ++c) {
+          const int i = tr * TR + r, j = tc * TC + c;
           if (j >= c1 && i >= j) A[i + j * LDA] -= acc[r][c];
         }
     }
@@ -462,33 +469,33 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
     }
     __syncthreads();
     // rows below the panel: B(i, j) -= sum_t L(i, c0+t) X(c0+t, j), j < c1 <= i
-    if (c1 < NB && tr * TS + TS > c1 && tc * TS < c1) {
-      T acc[TS][TS];
+    if (c1 < NB && tr * TR + TR > c1 && tc * TC < c1) {
+      T acc[TR][TC];
 #pragma unroll
-      for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < TR; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) acc[r][c] = (T)0;
+        for (int c = 0; c < TC; ++c) acc[r][c] = (T)0;
 #pragma unroll 4
       for (int t = 0; t < PB; ++t) {
         const int q = c0 + t;
-        T li[TS], xj[TS];
+        T li[TR], xj[TC];
 #pragma unroll
-        for (int r = 0; r < TS; ++r) li[r] = A[tr * TS + r + q * LDA];
+        for (int r = 0; r < TR; ++r) li[r] = A[tr * TR + r + q * LDA];
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-          const int j = tc * TS + c;
+        for (int c = 0; c < TC; ++c) {
+          const int j = tc * TC + c;
           xj[c] = j < q ? A[j + q * LDA] : (j == q ? xd[q] : (T)0);
         }
 #pragma unroll
-        for (int r = 0; r < TS; ++r)
+        for (int r = 0; r < TR; ++r)
 #pragma unroll
-          for (int c = 0; c < TS; ++c) acc[r][c] += li[r] * xj[c];
+          for (int c = 0; c < TC; ++c) acc[r][c] += li[r] * xj[c];
       }
 #pragma unroll
-      for (int r = 0; r < TS; ++r)
+      for (int r = 0; r < TR; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-          const int i = tr * TS + r, j = tc * TS + c;
+        for (int c = 0; c < TC; ++c) {
+          const int i = tr * TR + r, j = tc * TC + c;
           if (i >= c1 && j < c1) A[j + i * LDA] -= acc[r][c];
         }
     }
@@ -496,7 +503,7 @@ __global__ void __launch_bounds__(BS) k_potrf(DevPlan P, int64_t d0, T* panel, T
   }
   // ---- write back L (lower, bw x bw) and X = inv(L) (nb x nb, zero padded)
   T* o = inv + d.inv_off;
-  for (int idx = tid; idx < NB * NB; idx += BS) {
+  for (int idx = tid; idx < NB * NB; idx += PT) {
     const int i = idx % NB, j = idx / NB;
     if (i < bw && j < bw && i >= j) g[i + (int64_t)j * d.ld] = A[i + j * LDA];
     T x = (T)0;
@@ -1491,8 +1498,9 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
     case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf); break;
     case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad); break;
     case OP_POTRF:
-      if constexpr (sizeof(T) == 8) k_potrf<T, 64><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
-      else k_potrf<T, 128><<<g, BS, 0, s>>>(P, op.begin, panel, inv, bad);
+      if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+      else if (op.grid <= 256) k_potrf<T, 128, 512><<<g, 512, 0, s>>>(P, op.begin, panel, inv, bad);
+      else k_potrf<T, 128, 256><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
       break;
     case OP_TRSM:
     case OP_UPDATE: {
