@@ -778,10 +778,12 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     auto ts0 = clk::now();
     kkt_solve_info si{};
     // refinement target: the stationarity error a solve leaves behind stays
-    // below 1% of the tolerance on the scaled dual infeasibility; the affine
+    // below 1% of the larger of the tolerance and the current scaled dual
+    // infeasibility (an inexact Newton step: far from the solution a direction
+    // needs only be accurate relative to the residual it removes); the affine
     // predictor, which only sets sigma and the second-order term of the
     // corrector, stops at 10%
-    const double target = 1e-2 * O.tol * (1.0 + S.maxgf);
+    const double target = 1e-2 * std::max(O.tol, Dm) * (1.0 + S.maxgf);
     auto direction = [&](const double* tsv, const double* tlv, const double* tuv, double* dx, double* ds,
                          double* dl, double* dzl, double* dzu) -> int {
       launch_rhs(P, v, tsv, tlv, tuv, h->rhs, h->stream);
