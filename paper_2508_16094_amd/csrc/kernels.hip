@@ -797,9 +797,9 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
 // storage per block: NB = 128 in FP32, 64 in FP64) held in registers: wave w
 // keeps the columns j = w, w + NW, ... and every lane the rows lane (and
 // lane + 64).  The whole block is requested in one round of independent
-// loads, issued before the vector it multiplies is known, so a dependent
-// chain of solve steps pays one memory latency here instead of one per
-// column group.
+// loads (the gather kernel issues it before the vector it multiplies is
+// known), so a dependent chain of solve steps pays one memory latency here
+// instead of one per column group.
 template <int NT, typename T>
 struct InvBlock {
   static constexpr int NB = sizeof(T) == 4 ? 128 : 64, NW = NT / 64, JPW = NB / NW, RPL = NB / 64;
