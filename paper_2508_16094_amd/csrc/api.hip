@@ -10,7 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "batch.hpp"
@@ -1176,13 +1178,26 @@ const char* ipm_status_string(int s) {
 
 const char* ipm_last_error(const ipm_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
+// Host-side phase timing on stderr when PDIPM_TIMING is set.
+static void create_lap(const char* what) {
+  static const bool on = std::getenv("PDIPM_TIMING") != nullptr;
+  static auto t0 = std::chrono::steady_clock::now();
+  if (!on) return;
+  const auto t1 = std::chrono::steady_clock::now();
+  fprintf(stderr, "[create] %s %.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+  t0 = t1;
+}
+
 static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** out) {
   try {
     h->need64 = h->opt.precision == PDIPM_FP64 || h->opt.fp64_fallback;
     h->need32 = h->opt.precision == PDIPM_FP32;
     analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym);
+    create_lap("symbolic analysis");
     finish_analysis(h);
+    create_lap("plans and K map");
     layout(h);
+    create_lap("workspace layout");
     hipGetDevice(&h->device);
   } catch (const std::exception& e) {
     g_create_error = e.what();
@@ -1204,11 +1219,30 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
   }
+  create_lap("start");
   std::string e = build_problem(prob, &h->hp);
   if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
+  create_lap("problem copy and patterns");
   try {
-    build_graph_from_problem(h->hp, &h->graph);
-    build_kmap_problem(h->hp, &h->km);
+    // the graph of K (for the ordering) and the K map (for assembly) both
+    // only read the problem: build them on two host threads
+    std::string kmap_error;
+    std::thread kmap_thread([&]() {
+      try {
+        build_kmap_problem(h->hp, &h->km);
+      } catch (const std::exception& ex) {
+        kmap_error = ex.what();
+      }
+    });
+    try {
+      build_graph_from_problem(h->hp, &h->graph);
+    } catch (...) {
+      kmap_thread.join();
+      throw;
+    }
+    kmap_thread.join();
+    if (!kmap_error.empty()) throw std::runtime_error(kmap_error);
+    create_lap("graph of K and K map");
   } catch (const std::exception& ex) {
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());

@@ -264,7 +264,10 @@ std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
 
 namespace {
 
-// Adjacency of the permuted graph: for position j, neighbours as positions.
+// Adjacency of the permuted graph: for position j, neighbours as positions,
+// in increasing order.  The graph is symmetric, so the lists come out sorted
+// without a sort: positions j are visited in increasing order and j is
+// appended to the list of every neighbour of perm[j].
 Graph permute_graph(const Graph& g, const std::vector<int32_t>& perm, const std::vector<int32_t>& pinv) {
   Graph h;
   h.n = g.n;
@@ -274,11 +277,10 @@ Graph permute_graph(const Graph& g, const std::vector<int32_t>& perm, const std:
     int32_t v = perm[j];
     h.ptr[j + 1] = h.ptr[j] + (g.ptr[v + 1] - g.ptr[v]);
   }
+  std::vector<int64_t> fill(h.ptr.begin(), h.ptr.end() - 1);
   for (int64_t j = 0; j < g.n; ++j) {
     int32_t v = perm[j];
-    int64_t o = h.ptr[j];
-    for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) h.adj[o++] = pinv[g.adj[e]];
-    std::sort(h.adj.begin() + h.ptr[j], h.adj.begin() + h.ptr[j + 1]);
+    for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) h.adj[fill[pinv[g.adj[e]]]++] = (int32_t)j;
   }
   return h;
 }
@@ -388,10 +390,11 @@ void analyze(const Graph& g, int leaf, int menu, Symbolic* out) {
   lap("nested dissection");
   std::vector<int32_t> pinv(n);
   for (int64_t k = 0; k < n; ++k) pinv[nd[k]] = (int32_t)k;
-  std::vector<int32_t> post;
+  std::vector<int32_t> post, etree0;
   {
     Graph h0 = permute_graph(g, nd, pinv);
-    post = postorder_of(etree_of(h0));
+    etree0 = etree_of(h0);
+    post = postorder_of(etree0);
   }
   s.perm.resize(n);
   for (int64_t k = 0; k < n; ++k) s.perm[k] = nd[post[k]];
@@ -399,7 +402,17 @@ void analyze(const Graph& g, int leaf, int menu, Symbolic* out) {
   for (int64_t k = 0; k < n; ++k) s.pinv[s.perm[k]] = (int32_t)k;
   lap("postorder");
   Graph h = permute_graph(g, s.perm, s.pinv);
-  s.etree = etree_of(h);
+  // a postorder is a topological order of the tree: the elimination tree
+  // of the reordered graph is the relabelled tree
+  {
+    std::vector<int32_t> at(n);
+    for (int64_t k = 0; k < n; ++k) at[post[k]] = (int32_t)k;
+    s.etree.resize(n);
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t p = etree0[post[k]];
+      s.etree[k] = p < 0 ? -1 : at[p];
+    }
+  }
   s.colcount = column_counts(h, s.etree);
   lap("etree and counts");
   s.nnz_L = 0;
