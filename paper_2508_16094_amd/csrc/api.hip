@@ -157,11 +157,29 @@ void finish_analysis(ipm_handle* h) {
     }
     build_plan(h->sym, 8, &h->plan64, h->bcand[0]);
     build_plan(h->sym, 4, &h->plan32, h->bcand[0]);
+    map_k_to_panels(h->sym, h->plan64, &h->km);
   } else {
-    build_plan(h->sym, 8, &h->plan64);
-    build_plan(h->sym, 4, &h->plan32);
+    // the FP32 plan on a second host thread while the FP64 plan and the map
+    // of K entries to panel positions (same layout in both precisions) are
+    // built here
+    std::string plan32_error;
+    std::thread plan32_thread([&]() {
+      try {
+        build_plan(h->sym, 4, &h->plan32);
+      } catch (const std::exception& ex) {
+        plan32_error = ex.what();
+      }
+    });
+    try {
+      build_plan(h->sym, 8, &h->plan64);
+      map_k_to_panels(h->sym, h->plan64, &h->km);
+    } catch (...) {
+      plan32_thread.join();
+      throw;
+    }
+    plan32_thread.join();
+    if (!plan32_error.empty()) throw std::runtime_error(plan32_error);
   }
-  map_k_to_panels(h->sym, h->plan64, &h->km);
   if (h->standalone) {
     // symmetric pattern of the stored lower K for products K v
     const int64_t n = h->km.n;

@@ -2,10 +2,12 @@
 #include "host.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
 #include <sstream>
 #include <stdexcept>
+#include <thread>
 #include <tuple>
 
 #include "pdipm.h"
@@ -585,16 +587,26 @@ void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {
   std::vector<int32_t> col2sn(s.n);
   for (int64_t k = 0; k < P.ns; ++k)
     for (int32_t j = s.sn_start[k]; j < s.sn_start[k + 1]; ++j) col2sn[j] = (int32_t)k;
-  for (int64_t e = 0; e < nk; ++e) {
-    int32_t a = s.pinv[km->krow[e]], b = s.pinv[km->kc[e]];
-    int32_t r = std::max(a, b), c = std::min(a, b);
-    int32_t k = col2sn[c];
-    const int32_t* rows = s.sn_rows.data() + s.sn_rowptr[k];
-    int64_t h = s.sn_rowptr[k + 1] - s.sn_rowptr[k];
-    const int32_t* it = std::lower_bound(rows, rows + h, r);
-    if (it == rows + h || *it != r) throw std::runtime_error("K entry outside the factor structure");
-    km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sld[k] + (it - rows);
-  }
+  // entries are independent: contiguous ranges on up to 8 host threads
+  std::atomic<bool> outside{false};
+  auto range = [&](int64_t e0, int64_t e1) {
+    for (int64_t e = e0; e < e1; ++e) {
+      int32_t a = s.pinv[km->krow[e]], b = s.pinv[km->kc[e]];
+      int32_t r = std::max(a, b), c = std::min(a, b);
+      int32_t k = col2sn[c];
+      const int32_t* rows = s.sn_rows.data() + s.sn_rowptr[k];
+      int64_t h = s.sn_rowptr[k + 1] - s.sn_rowptr[k];
+      const int32_t* it = std::lower_bound(rows, rows + h, r);
+      if (it == rows + h || *it != r) { outside = true; return; }
+      km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sld[k] + (it - rows);
+    }
+  };
+  const int64_t nt = nk < (1 << 20) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int64_t t = 1; t < nt; ++t) pool.emplace_back(range, nk * t / nt, nk * (t + 1) / nt);
+  range(0, nk / nt);
+  for (std::thread& th : pool) th.join();
+  if (outside) throw std::runtime_error("K entry outside the factor structure");
 }
 
 }  // namespace pdipm
