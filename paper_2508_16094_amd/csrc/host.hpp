@@ -48,7 +48,6 @@ struct KMap {
   std::vector<int64_t> pos;  // element offset of the entry in the panels
 };
 
-// Launch descriptors (offsets are element offsets in the named buffers).
 // Largest front height factored by the one-workgroup small-front kernel.
 constexpr int SMALL_H_MAX = 64;
 
@@ -59,6 +58,7 @@ constexpr int SMALL_H_MAX = 64;
 constexpr int GEMM_TILE_F32 = 128;
 constexpr int GEMM_TILE_F64 = 64;
 
+// Launch descriptors (offsets are element offsets in the named buffers).
 struct GemmDesc {          // C (-)= A * B^T on an M x N block, K inner
   int64_t c_off, a_off, b_off;
   int32_t ldc, lda, ldb;
