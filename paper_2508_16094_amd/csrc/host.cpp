@@ -218,44 +218,90 @@ void build_graph_from_lower(int64_t n, const int64_t* rp, const int32_t* ci, Gra
 void build_kmap_problem(const HostProblem& p, KMap* km) {
   const int64_t n = p.n;
   km->n = n;
+  // Columns are independent: contiguous column ranges, balanced by the J
+  // entries they visit, are mapped on up to 8 host threads into arrays of
+  // their own and concatenated in column order (the result does not depend
+  // on the number of threads).
+  struct Part {
+    std::vector<int32_t> kc, krow, kh, tk, ta, tb;
+    std::vector<int64_t> tend;    // triples of the part up to each entry
+    std::vector<int64_t> ncol;    // entries of each column of the range
+  };
+  std::vector<int64_t> work(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t w = 1 + (p.hp[i + 1] - p.hp[i]);
+    for (int64_t q = p.jtp[i]; q < p.jtp[i + 1]; ++q) w += p.jp[p.jtr[q] + 1] - p.jp[p.jtr[q]];
+    work[i + 1] = work[i] + w;
+  }
+  const int64_t nt = work[n] < (1 << 22) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  std::vector<int64_t> cut(nt + 1, n);
+  cut[0] = 0;
+  for (int64_t t = 1; t < nt; ++t)
+    cut[t] = std::lower_bound(work.begin(), work.end(), work[n] * t / nt) - work.begin();
+  for (int64_t t = 1; t <= nt; ++t) cut[t] = std::max(cut[t], cut[t - 1]);
+  std::vector<Part> parts(nt);
+  auto run = [&](int64_t t) {
+    Part& q = parts[t];
+    struct Item { int32_t j, k, a, b; };
+    std::vector<Item> items;
+    for (int64_t i = cut[t]; i < cut[t + 1]; ++i) {
+      items.clear();
+      for (int64_t r = p.jtp[i]; r < p.jtp[i + 1]; ++r) {
+        int32_t k = p.jtr[r], a = p.jte[r];
+        for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
+          int32_t j = p.jc[e];
+          if (j > i) break;
+          items.push_back({j, k, a, (int32_t)e});
+        }
+      }
+      std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+        return x.j != y.j ? x.j < y.j : x.k < y.k;
+      });
+      // merge with the H row (lower, sorted; includes the diagonal)
+      const size_t before = q.kc.size();
+      size_t u = 0;
+      int64_t eh = p.hp[i];
+      while (u < items.size() || eh < p.hp[i + 1]) {
+        int32_t jt = u < items.size() ? items[u].j : INT32_MAX;
+        int32_t jh = eh < p.hp[i + 1] ? p.hc[eh] : INT32_MAX;
+        int32_t j = std::min(jt, jh);
+        q.kc.push_back(j);
+        q.krow.push_back((int32_t)i);
+        q.kh.push_back(jh == j ? (int32_t)eh++ : -1);
+        while (u < items.size() && items[u].j == j) {
+          q.tk.push_back(items[u].k);
+          q.ta.push_back(items[u].a);
+          q.tb.push_back(items[u].b);
+          ++u;
+        }
+        q.tend.push_back((int64_t)q.tk.size());
+      }
+      q.ncol.push_back((int64_t)(q.kc.size() - before));
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int64_t t = 1; t < nt; ++t) pool.emplace_back(run, t);
+  run(0);
+  for (std::thread& th : pool) th.join();
+  int64_t ne = 0, ntr = 0;
+  for (const Part& q : parts) { ne += (int64_t)q.kc.size(); ntr += (int64_t)q.tk.size(); }
   km->kp.assign(n + 1, 0);
   km->kc.clear(); km->krow.clear(); km->kh.clear(); km->tk.clear(); km->ta.clear(); km->tb.clear();
+  km->kc.reserve(ne); km->krow.reserve(ne); km->kh.reserve(ne);
+  km->tk.reserve(ntr); km->ta.reserve(ntr); km->tb.reserve(ntr);
   km->tp.assign(1, 0);
-  struct Item { int32_t j, k, a, b; };
-  std::vector<Item> items;
-  std::vector<std::pair<int32_t, int32_t>> hrow;
-  for (int64_t i = 0; i < n; ++i) {
-    items.clear();
-    for (int64_t q = p.jtp[i]; q < p.jtp[i + 1]; ++q) {
-      int32_t k = p.jtr[q], a = p.jte[q];
-      for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
-        int32_t j = p.jc[e];
-        if (j > i) break;
-        items.push_back({j, k, a, (int32_t)e});
-      }
-    }
-    std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
-      return x.j != y.j ? x.j < y.j : x.k < y.k;
-    });
-    // merge with the H row (lower, sorted; includes the diagonal)
-    size_t t = 0;
-    int64_t eh = p.hp[i];
-    while (t < items.size() || eh < p.hp[i + 1]) {
-      int32_t jt = t < items.size() ? items[t].j : INT32_MAX;
-      int32_t jh = eh < p.hp[i + 1] ? p.hc[eh] : INT32_MAX;
-      int32_t j = std::min(jt, jh);
-      km->kc.push_back(j);
-      km->krow.push_back((int32_t)i);
-      km->kh.push_back(jh == j ? (int32_t)eh++ : -1);
-      while (t < items.size() && items[t].j == j) {
-        km->tk.push_back(items[t].k);
-        km->ta.push_back(items[t].a);
-        km->tb.push_back(items[t].b);
-        ++t;
-      }
-      km->tp.push_back((int64_t)km->tk.size());
-    }
-    km->kp[i + 1] = (int64_t)km->kc.size();
+  km->tp.reserve(ne + 1);
+  int64_t col = 0;
+  for (const Part& q : parts) {
+    const int64_t base = (int64_t)km->tk.size();
+    km->kc.insert(km->kc.end(), q.kc.begin(), q.kc.end());
+    km->krow.insert(km->krow.end(), q.krow.begin(), q.krow.end());
+    km->kh.insert(km->kh.end(), q.kh.begin(), q.kh.end());
+    km->tk.insert(km->tk.end(), q.tk.begin(), q.tk.end());
+    km->ta.insert(km->ta.end(), q.ta.begin(), q.ta.end());
+    km->tb.insert(km->tb.end(), q.tb.begin(), q.tb.end());
+    for (int64_t v : q.tend) km->tp.push_back(base + v);
+    for (int64_t c : q.ncol) { km->kp[col + 1] = km->kp[col] + c; ++col; }
   }
 }
 
