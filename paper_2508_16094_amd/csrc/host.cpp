@@ -176,26 +176,56 @@ std::string build_problem(const ipm_problem_desc* d, HostProblem* p) {
 void build_graph_from_problem(const HostProblem& p, Graph* g) {
   const int64_t n = p.n;
   g->n = n;
-  g->ptr.assign(n + 1, 0);
-  g->adj.clear();
-  std::vector<int32_t> mark(n, -1), row;
+  // Adjacency rows are independent: contiguous column ranges, balanced by
+  // the J entries they visit, on up to 8 host threads, concatenated in order.
+  std::vector<int64_t> work(n + 1, 0);
   for (int64_t j = 0; j < n; ++j) {
-    row.clear();
-    mark[j] = (int32_t)j;
-    for (int64_t q = p.jtp[j]; q < p.jtp[j + 1]; ++q) {
-      int32_t k = p.jtr[q];
-      for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
-        int32_t i = p.jc[e];
+    int64_t w = 1 + (p.hsp[j + 1] - p.hsp[j]);
+    for (int64_t q = p.jtp[j]; q < p.jtp[j + 1]; ++q) w += p.jp[p.jtr[q] + 1] - p.jp[p.jtr[q]];
+    work[j + 1] = work[j] + w;
+  }
+  const int64_t nt = work[n] < (1 << 22) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  std::vector<int64_t> cut(nt + 1, n);
+  cut[0] = 0;
+  for (int64_t t = 1; t < nt; ++t)
+    cut[t] = std::lower_bound(work.begin(), work.end(), work[n] * t / nt) - work.begin();
+  for (int64_t t = 1; t <= nt; ++t) cut[t] = std::max(cut[t], cut[t - 1]);
+  std::vector<std::vector<int32_t>> adj(nt);
+  std::vector<std::vector<int64_t>> len(nt);
+  auto run = [&](int64_t t) {
+    std::vector<int32_t> mark(n, -1), row;
+    for (int64_t j = cut[t]; j < cut[t + 1]; ++j) {
+      row.clear();
+      mark[j] = (int32_t)j;
+      for (int64_t q = p.jtp[j]; q < p.jtp[j + 1]; ++q) {
+        int32_t k = p.jtr[q];
+        for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
+          int32_t i = p.jc[e];
+          if (mark[i] != j) { mark[i] = (int32_t)j; row.push_back(i); }
+        }
+      }
+      for (int64_t q = p.hsp[j]; q < p.hsp[j + 1]; ++q) {
+        int32_t i = p.hsc[q];
         if (mark[i] != j) { mark[i] = (int32_t)j; row.push_back(i); }
       }
+      std::sort(row.begin(), row.end());
+      adj[t].insert(adj[t].end(), row.begin(), row.end());
+      len[t].push_back((int64_t)row.size());
     }
-    for (int64_t q = p.hsp[j]; q < p.hsp[j + 1]; ++q) {
-      int32_t i = p.hsc[q];
-      if (mark[i] != j) { mark[i] = (int32_t)j; row.push_back(i); }
-    }
-    std::sort(row.begin(), row.end());
-    g->adj.insert(g->adj.end(), row.begin(), row.end());
-    g->ptr[j + 1] = (int64_t)g->adj.size();
+  };
+  std::vector<std::thread> pool;
+  for (int64_t t = 1; t < nt; ++t) pool.emplace_back(run, t);
+  run(0);
+  for (std::thread& th : pool) th.join();
+  g->ptr.assign(n + 1, 0);
+  g->adj.clear();
+  int64_t total = 0;
+  for (const auto& a : adj) total += (int64_t)a.size();
+  g->adj.reserve(total);
+  int64_t col = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    g->adj.insert(g->adj.end(), adj[t].begin(), adj[t].end());
+    for (int64_t c : len[t]) { g->ptr[col + 1] = g->ptr[col] + c; ++col; }
   }
 }
 
