@@ -184,7 +184,7 @@ void build_graph_from_problem(const HostProblem& p, Graph* g) {
     for (int64_t q = p.jtp[j]; q < p.jtp[j + 1]; ++q) w += p.jp[p.jtr[q] + 1] - p.jp[p.jtr[q]];
     work[j + 1] = work[j] + w;
   }
-  const int64_t nt = work[n] < (1 << 22) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  const int64_t nt = host_threads(work[n], 1 << 22);
   std::vector<int64_t> cut(nt + 1, n);
   cut[0] = 0;
   for (int64_t t = 1; t < nt; ++t)
@@ -263,7 +263,7 @@ void build_kmap_problem(const HostProblem& p, KMap* km) {
     for (int64_t q = p.jtp[i]; q < p.jtp[i + 1]; ++q) w += p.jp[p.jtr[q] + 1] - p.jp[p.jtr[q]];
     work[i + 1] = work[i] + w;
   }
-  const int64_t nt = work[n] < (1 << 22) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  const int64_t nt = host_threads(work[n], 1 << 22);
   std::vector<int64_t> cut(nt + 1, n);
   cut[0] = 0;
   for (int64_t t = 1; t < nt; ++t)
@@ -677,7 +677,7 @@ void map_k_to_panels(const Symbolic& s, const Plan& P, KMap* km) {
       km->pos[e] = P.spanel[k] + (int64_t)(c - P.sfirst[k]) * P.sld[k] + (it - rows);
     }
   };
-  const int64_t nt = nk < (1 << 20) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  const int64_t nt = host_threads(nk, 1 << 20);
   std::vector<std::thread> pool;
   for (int64_t t = 1; t < nt; ++t) pool.emplace_back(range, nk * t / nt, nk * (t + 1) / nt);
   range(0, nk / nt);

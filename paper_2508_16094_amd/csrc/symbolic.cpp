@@ -12,6 +12,15 @@
 
 namespace pdipm {
 
+int64_t host_threads(int64_t work, int64_t work_min) {
+  if (const char* e = std::getenv("PDIPM_HOST_THREADS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1) return std::min<long>(v, 64);
+  }
+  if (work < work_min) return 1;
+  return std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+}
+
 AmalgamationRule amalgamation_rule(int menu) {
   switch (menu) {
     case 1: return {128, 16, 1, 20};
@@ -278,7 +287,7 @@ Graph permute_graph(const Graph& g, const std::vector<int32_t>& perm, const std:
     h.ptr[j + 1] = h.ptr[j] + (g.ptr[v + 1] - g.ptr[v]);
   }
   const int64_t nnz = h.ptr[g.n];
-  const int64_t nt = nnz < (1 << 22) ? 1 : std::min<int64_t>(8, std::max(1u, std::thread::hardware_concurrency()));
+  const int64_t nt = host_threads(nnz, 1 << 22);
   auto run = [&](int64_t t) {
     const int64_t j0 = std::lower_bound(h.ptr.begin(), h.ptr.end(), nnz * t / nt) - h.ptr.begin();
     const int64_t j1 = t + 1 == nt ? g.n : std::lower_bound(h.ptr.begin(), h.ptr.end(), nnz * (t + 1) / nt) - h.ptr.begin();

@@ -40,6 +40,10 @@ struct Symbolic {
 };
 
 // Nested dissection order (before postordering).
+// Host threads for a parallel setup loop of the given work: the value of
+// PDIPM_HOST_THREADS when set (1 to 64, at any size; the results never
+// depend on it), else up to 8 once the work reaches work_min.
+int64_t host_threads(int64_t work, int64_t work_min);
 std::vector<int32_t> nested_dissection(const Graph& g, int leaf);
 // Full analysis: order, postorder, etree, column counts, supernodes.
 void analyze(const Graph& g, int leaf, int menu, Symbolic* out);

@@ -116,3 +116,32 @@ def test_batch_rejects_nonlinear_instances():
     assert e.value.code == L.PDIPM_ERR_INVALID_ARG
     with pytest.raises(L.PdipmError):
         L.BatchSolver([])
+
+
+@pytest.mark.parametrize("threads", [2, 5, 8])
+def test_host_setup_does_not_depend_on_thread_count(threads, monkeypatch):
+    """The graph of K, the K map, the graph permutations and the panel map
+    run on several host threads over contiguous ranges; forcing the thread
+    count (PDIPM_HOST_THREADS, applied at any size) changes none of the
+    exported symbolic arrays, the K pattern or the statistics (triples and
+    update bytes included)."""
+    probs = [w.lp_block(nblocks=6, block_rows=300, block_cols=600, link_cols_per_block=30),
+             w.nlp_grid(40, 33), w.qp_instance(500, 3)]
+
+    def run(p, t):
+        monkeypatch.setenv("PDIPM_HOST_THREADS", str(t))
+        s = L.IpmSolver(p)
+        return s.symbolic(), s.k_pattern(), s.stats()
+
+    for p in probs:
+        sym1, (rp1, ci1), st1 = run(p, 1)
+        symt, (rpt, cit), stt = run(p, threads)
+        for k in sym1:
+            assert np.array_equal(sym1[k], symt[k]), (p.name, k)
+        assert np.array_equal(rp1, rpt) and np.array_equal(ci1, cit), p.name
+        assert st1 == stt, p.name
+    ps = [w.qp_instance(n, 80 + i) for i, n in enumerate([60, 140, 90])]
+    monkeypatch.setenv("PDIPM_HOST_THREADS", "1")
+    b1 = L.BatchSolver(ps).stats()
+    monkeypatch.setenv("PDIPM_HOST_THREADS", str(threads))
+    assert L.BatchSolver(ps).stats() == b1
