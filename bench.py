@@ -22,6 +22,7 @@ import os
 import sys
 import time
 
+T_START = time.time()
 PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA TFLOP/s
 
 
@@ -263,39 +264,77 @@ def traffic_of(kernel, workload, alg_bytes_per_launch):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(args, flops_full, iters_full):
-    """The oracle (plain FP64 CPU IPM) on a bounded slice of the workload:
-    its time per IPM iteration per factorisation flop, scaled to the full
-    workload's sum_j (c_j^2 - 1) and iteration count."""
-    import numpy as np
-    from oracle import ipm as oipm
-    from oracle import symbolic as osym
+def host_cpu():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def sample_problem(workload):
+    """The bounded sample the oracle solves for the CPU baseline: a smaller
+    instance of the benchmarked workload's own generator."""
     from paper_2508_16094_amd import workloads as w
-    if args.workload == "lp_block":
-        p = w.lp_block(nblocks=1, block_rows=1500, block_cols=3000, n_link_rows=0)
-        sample = "oracle IPM, 5 iterations on a 1500x3000 block of the block-angular LP generator"
-    elif args.workload == "nlp_grid":
-        p = w.nlp_grid(60, 60)
-        sample = "oracle IPM, 5 iterations on the 60x60 grid instance of the same generator"
-    else:
-        p = w.lp_small()
-        sample = "oracle IPM, 5 iterations on the same instance"
-    t0 = time.time()
-    r = oipm.solve(p, tol=1e-6, max_iter=5, dense_max=0)
-    dt = time.time() - t0
-    # factorisation work of the sample from the oracle's own symbolic analysis
+    if workload == "lp_block":
+        return (w.lp_block(nblocks=1, block_rows=1000, block_cols=2000, n_link_rows=0),
+                "one 1000 x 2000 block of the block-angular LP generator (no linking rows)")
+    if workload == "nlp_grid":
+        return w.nlp_grid(60, 60), "the 60 x 60 grid instance of the same generator"
+    return w.lp_small(), "the same instance"
+
+
+def cpu_baseline_sample(args, cap_s=40.0):
+    """The oracle (plain FP64 CPU IPM, one thread) solving a bounded sample
+    of the workload to the same tolerance, timed (at most about cap_s)."""
+    import numpy as np
     import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
+    from oracle import ipm as oipm
     from oracle import model
+    from oracle import symbolic as osym
+    p, what = sample_problem(args.workload)
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        r = oipm.solve(p, tol=1e-6, dense_max=0, max_wall_time=cap_s)
+        dt = time.time() - t0
+    # factorisation work of the sample from the oracle's own symbolic analysis
     J = model.jacobian(p, np.zeros(p.n)).tocsr()
     H = sp.tril(model.hessian(p, np.zeros(p.n), np.ones(p.m))).tocsr()
     adj = osym.kkt_pattern(p.n, J.indptr, J.indices, H.indptr, H.indices)
     f_sample = float(osym.analyze(adj, p.n)["flops"])
-    it = max(1, r["iterations"])
-    sec_per_flop_iter = dt / (it * f_sample)
-    t_full = sec_per_flop_iter * flops_full * iters_full
-    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}: {dt:.1f} s for {it} iterations, sum c_j^2 = {f_sample:.3g}; "
-                      f"scaled by flops ({flops_full:.3g}) and iterations ({iters_full})"}
+    return {"what": what, "seconds": dt, "iterations": max(1, r["iterations"]), "flops": f_sample,
+            "status": oipm.STATUS_NAMES.get(r["status"], str(r["status"]))}
+
+
+def cpu_baseline_scale(smp, flops_full, iters_full):
+    """Scale the sample's time per iteration per factorisation flop to the
+    full workload's sum_j (c_j^2 - 1) and iteration count (an estimate: the
+    full instance would take the oracle hours)."""
+    t_full = smp["seconds"] / (smp["iterations"] * smp["flops"]) * flops_full * iters_full
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle", "estimate": True,
+            "sample": f"oracle IPM solve of {smp['what']}: {smp['status']} after {smp['iterations']} "
+                      f"iterations in {smp['seconds']:.1f} s (sum c_j^2 = {smp['flops']:.3g}); scaled to the "
+                      f"benchmarked instance by factorisation flops ({flops_full:.3g}) and iterations "
+                      f"({iters_full})",
+            "host": host_cpu()}
+
+
+def plan_steps(done, elapsed, t_step, reserve, budget):
+    """Whether another timed step fits: the first always runs; later ones
+    only while the elapsed time plus one more step (the slowest seen) plus
+    the time reserved for what follows stays within the wall budget."""
+    return done == 0 or (t_step is not None and elapsed + t_step + reserve <= budget)
 
 
 def main():
@@ -306,6 +345,11 @@ def main():
     ap.add_argument("--workload", default="lp_block")
     ap.add_argument("--nblocks", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--time-budget", type=float, default=450.0,
+                    help="wall seconds from process start within which the JSON line is printed; "
+                         "timed steps and warmups stop early to keep it")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip the FP64 solve on the same handle (reported next to the FP32 form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--count", type=int, default=4096, help="qp_batch: number of instances")
@@ -323,18 +367,27 @@ def main():
         print(f"--gpus {args.gpus}: the solver runs one instance on one GPU; multi-GPU sharding "
               "(etree subtrees per GPU) is not implemented, run with --gpus 1", file=sys.stderr)
         return 2
-    import torch
-    from paper_2508_16094_amd import lib as L
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    if args.workload == "copy":
-        return bench_copy(args, log)
-    if args.workload == "qp_batch":
-        return bench_batch(args, log)
-    if args.workload == "warm":
-        return bench_warm(args, log)
+    def since_start():
+        return time.time() - T_START
+
+    if args.workload in ("copy", "qp_batch", "warm"):
+        import torch  # noqa: F401
+        return {"copy": bench_copy, "qp_batch": bench_batch, "warm": bench_warm}[args.workload](args, log)
+
+    # 1. the CPU baseline first, bounded, so that it never pushes the JSON
+    #    line past the budget; it needs the plan's flops and the iteration
+    #    count, so it is timed now and scaled once those are known
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        cpu = cpu_baseline_sample(args)
+        log(f"[bench] cpu baseline sample in {time.time() - t:.1f}s")
+    import torch
+    from paper_2508_16094_amd import lib as L
 
     t = time.time()
     p, name = make_problem(args)
@@ -342,30 +395,48 @@ def main():
     prec = L.PDIPM_FP32 if args.precision == "fp32" else L.PDIPM_FP64
     t = time.time()
     # FP32 form: FP64 factors take over for the rest of a solve once FP32
-    # refinement cannot reach the accuracy the iteration needs
+    # refinement cannot reach the accuracy the iteration needs; the FP64
+    # space also serves the FP64 comparison solve on the same handle
     s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0)
     st = s.stats()
-    log(f"[bench] analysed in {time.time() - t:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
+    t_setup = time.time() - t
+    log(f"[bench] analysed in {t_setup:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
         f"supernodes={st['n_super']} levels={st['n_levels']} workspace={s.workspace_bytes() / 1e9:.1f} GB")
     s.bind()
     torch.cuda.synchronize()
-    for i in range(args.warmup):
+    # 2. warmup: at most one solve (each is a complete solve); its time sizes
+    #    the timed loop
+    t_step = None
+    warm_done = 0
+    for i in range(min(args.warmup, 1)):
+        t = time.time()
         r = s.solve()
+        torch.cuda.synchronize()
+        t_step = time.time() - t
+        warm_done += 1
         log(f"[bench] warmup {i}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s")
+    compare = prec == L.PDIPM_FP32 and not args.no_fp64_compare
+    # time kept for the FP64 solve (FP64 factors cost about twice FP32 ones)
+    reserve = lambda: (2.0 * t_step if compare and t_step else 0.0)  # noqa: E731
     s.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.time()
     results = []
-    for i in range(args.steps):
+    while len(results) < max(1, args.steps) and plan_steps(len(results), since_start(), t_step, reserve(),
+                                                         args.time_budget):
+        t = time.time()
         r = s.solve()
+        torch.cuda.synchronize()
+        t_step = time.time() - t if t_step is None else max(t_step, time.time() - t)
         results.append(r)
-        log(f"[bench] step {i}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s "
+        log(f"[bench] step {len(results) - 1}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s "
             f"f {r['f']:.10e} P {r['P']:.1e} D {r['D']:.1e} C {r['C']:.1e}")
     torch.cuda.synchronize()
     elapsed = time.time() - t0
     prof = s.profile()
     last = results[-1]
-    iters = sum(r["iterations"] for r in results)
+    steps = len(results)
+
     def rate(flops, ms):
         return flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     # dominant kernel: the Schur-update GEMM of the form's own precision
@@ -373,16 +444,20 @@ def main():
     pkey = "fp" + key
     gemm_tf = rate(prof["gemm" + key + "_flops"], prof["gemm" + key + "_ms"])
     launches = prof["gemm" + key + "_launches"]
+    nfac_key = prof["factorizations" + key]
+    method_tf = rate(st["flops"] * nfac_key, prof["gemm" + key + "_ms"])
     factor_tf = rate(prof["factor_flops"], prof["factor_ms"])
     nfac = prof["factorizations32"] + prof["factorizations64"]
     out = {
         "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
-        "value": args.steps / elapsed,
+        "value": steps / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": steps,
+        "warmup": warm_done,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -393,10 +468,11 @@ def main():
         "status": last["status"], "iterations": last["iterations"], "f": last["f"],
         "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],
         "P": last["P"], "D": last["D"], "C": last["C"],
+        "setup_s": t_setup,
         "factor_tflops": factor_tf,
         "factorizations": {"fp32": prof["factorizations32"], "fp64": prof["factorizations64"]},
         "factor_ms_per_iter": prof["factor_ms"] / max(1, nfac),
-        "solve_gbps": prof["solve_bytes"] / (last["ms_solve"] * 1e-3 * len(results)) / 1e9
+        "solve_gbps": prof["solve_bytes"] / (sum(r["ms_solve"] for r in results) * 1e-3) / 1e9
         if last["ms_solve"] > 0 else None,
         "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
                      "frac": gemm_tf / PEAK[pkey],
@@ -408,12 +484,31 @@ def main():
                      "launches": launches,
                      "algorithmic_bytes_per_launch": prof["gemm" + key + "_bytes"] / max(1, launches),
                      "avg_launch_us": 1e3 * prof["gemm" + key + "_ms"] / max(1, launches),
+                     "method_rate": {"achieved": method_tf, "frac": method_tf / PEAK[pkey],
+                                     "definition": "sum_j (c_j^2 - 1) per factorisation x factorisations in "
+                                                   "this precision / summed time of its GEMM launches"},
                      "fp64_fallback_gemm_tflops": rate(prof["gemm64_flops"], prof["gemm64_ms"])},
     }
-    if not args.no_cpu_baseline:
-        t = time.time()
-        out["cpu_baseline"] = cpu_baseline(args, st["flops"], last["iterations"])
-        log(f"[bench] cpu baseline in {time.time() - t:.1f}s")
+    # 3. the plain FP64 GPU path on the same handle and instance
+    if compare:
+        if since_start() + 2.0 * t_step <= args.time_budget + 60.0:
+            s.set_profiling(False)
+            s.set_precision(L.PDIPM_FP64)
+            t = time.time()
+            r64 = s.solve()
+            torch.cuda.synchronize()
+            dt = time.time() - t
+            s.set_precision(prec)
+            log(f"[bench] fp64 path: status {r64['status']} it {r64['iterations']} {dt:.2f}s f {r64['f']:.10e}")
+            out["fp64_path"] = {"solves_per_s": 1.0 / dt, "s_per_solve": dt, "status": r64["status"],
+                                "iterations": r64["iterations"], "f": r64["f"], "P": r64["P"], "D": r64["D"],
+                                "C": r64["C"], "fp32_form_speedup": (steps / elapsed) * dt,
+                                "rel_f_diff_vs_fp32_form": abs(r64["f"] - last["f"]) / max(1.0, abs(r64["f"]))}
+        else:
+            out["fp64_path"] = {"skipped": "time budget"}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu_baseline_scale(cpu, st["flops"], last["iterations"])
+    out["wall_s"] = since_start()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -118,7 +118,9 @@ typedef struct kkt_solve_info {
   int32_t ir_steps;      /* refinement corrections applied */
   double residual;       /* backward error ||rhs - K x||_inf /
                             (max_i K_ii ||x||_inf + ||rhs||_inf) */
-  int32_t fallback;      /* 0 none, 1 FP64 refactor */
+  int32_t fallback;      /* 0 none; 1: the FP32 factor's refinement missed the
+                            target and kkt_solve refactored K in FP64 and
+                            solved again (the handle keeps the FP64 factor) */
   double ms;
 } kkt_solve_info;
 
@@ -172,7 +174,11 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
 int kkt_create_csr(int64_t n, const int64_t* h_rowptr, const int32_t* h_colind,
                    const ipm_options* opts, ipm_handle** out);
 
-/* Symbolic statistics (host only; the analysis itself runs at create). */
+/* Symbolic statistics (host only; the analysis itself runs at create):
+ * fill-reducing ordering, elimination tree, column counts and supernodes,
+ * computed once and reused by every factorisation (Section 2: the ordering
+ * is serial and amortised over the iterations).  out is a caller struct;
+ * errors: INVALID_ARG for NULL arguments. */
 int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* out);
 
 /* Export the symbolic analysis (host arrays sized from kkt_analyze):
@@ -197,9 +203,12 @@ int ipm_set_stream(ipm_handle* h, void* stream);
 int kkt_set_values(ipm_handle* h, const double* d_kval);
 
 /* Assemble K for the point (x, lambda) with the given Sigma_s [m] and
- * Sigma_x [n] (device vectors): evaluates J and H on their patterns and sums
- * H + diag(Sigma_x + delta_p) + J' diag(Sigma_s) J into the supernodal
- * panels in the given precision. */
+ * Sigma_x [n] (device vectors, read on the handle's stream): evaluates J and
+ * H on their patterns and sums H + diag(Sigma_x + delta_p) + J' diag(Sigma_s) J
+ * (Section 3, eq. kkt_primal, with the bound term Sigma_x) into the
+ * supernodal panels in the given precision (FP32: scaled to unit diagonal).
+ * Errors: NOT_ANALYZED without a workspace, INVALID_ARG on a standalone
+ * handle, NOT_PD when a diagonal entry of K is not positive. */
 int kkt_assemble(ipm_handle* h, const double* d_x, const double* d_lam,
                  const double* d_sig_s, const double* d_sig_x, int precision);
 
@@ -215,9 +224,15 @@ int kkt_factor(ipm_handle* h, int precision, kkt_factor_info* info);
  * total length nnz_L_stored. */
 int kkt_get_factor(ipm_handle* h, double* h_lval);
 
-/* Solve K x = rhs with the current factor (device FP64 vectors, original
- * numbering).  With an FP32 factor, FP64 iterative refinement against the
- * assembled (or set) K runs up to ir_max steps. */
+/* Solve K x = rhs with the current factor (Section 2: L y = P'rhs, then
+ * L'z = y, x = P z).  rhs and x are device FP64 vectors of length n in the
+ * original numbering (may not alias); the handle's stream orders them.
+ * FP64 iterative refinement against the assembled (or set) K runs up to
+ * ir_max steps towards the backward error ir_tol; with an FP32 factor it
+ * continues with conjugate gradients preconditioned by the factor, and when
+ * that still misses the target and the handle has FP64 space, K is
+ * refactored in FP64 (info->fallback = 1).  Errors: NOT_ANALYZED without a
+ * valid factor, NUMERICAL on a non-finite residual. */
 int kkt_solve(ipm_handle* h, const double* d_rhs, double* d_x, kkt_solve_info* info);
 
 /* Evaluate the model at (x, lambda) on the device: f (host scalar),
@@ -233,10 +248,22 @@ int ipm_pattern_sizes(ipm_handle* h, int64_t* nnz_j, int64_t* nnz_h);
 int ipm_get_patterns(ipm_handle* h, int64_t* j_rowptr, int32_t* j_colind,
                      int64_t* h_rowptr, int32_t* h_colind);
 
-/* Run the interior-point method to tolerance.  start NULL = cold start
- * (x from the bounds, s = max(g, 1), lambda = 1, z = 1); a start is pushed
- * into the interior first. */
+/* Run the interior-point method to tolerance: the Newton iteration on the
+ * barrier KKT conditions (Section 3, eq. kkt), each step from the primal
+ * condensed system (Section 3, eq. kkt_primal) factored without pivoting,
+ * inertia correction by delta_w I on a non-positive pivot (Section 3,
+ * Regularization).  start NULL = cold start (x from the bounds,
+ * s = max(g, 1), lambda = 1, z = 1); a start (host or device arrays per
+ * start->memspace) is pushed into the interior first.  res (caller struct,
+ * may be NULL) receives status, iterations, f, P, D, C, mu and phase times.
+ * Returns the status (>= 0: best iterate kept) or an error code. */
 int ipm_solve(ipm_handle* h, const ipm_start* start, ipm_result* res);
+
+/* Precision of the next ipm_solve on this handle: PDIPM_FP64, or
+ * PDIPM_FP32 (FP32 factor, FP64 refinement).  The workspace must hold that
+ * precision's factor: FP64 needs precision FP64 or fp64_fallback at create,
+ * FP32 needs precision FP32 at create; otherwise INVALID_ARG. */
+int ipm_set_precision(ipm_handle* h, int precision);
 
 /* Copy the final iterate to caller buffers (memspace PDIPM_HOST/DEVICE);
  * NULL pointers are skipped. */

@@ -687,6 +687,27 @@ int check_ready(ipm_handle* h) {
 // ------------------------------------------------------------ IPM loop
 struct Scalars { double maxrp, maxg, maxrd, maxgf, comp, f, nonfinite; };
 
+// Modelled device time (seconds) of one factorisation and of one refinement
+// step (triangular-solve pair, matrix-free K v, residual norms) of the
+// current plans in each precision.  The FP32 form decides from these counts
+// when FP64 factors take over, so the decision, and with it the whole
+// iterate sequence, is the same on every run.  Model constants for gfx950:
+// about 6 us of launch and dependency latency per kernel, sustained MFMA
+// rates of 100 (FP32) and 50 (FP64) TFLOP/s on the Schur updates, and
+// 3 TB/s for the streaming triangular solves and sparse products.
+struct CostModel { double fac32, fac64, step32, step64; };
+
+CostModel cost_model(const ipm_handle* h) {
+  constexpr double lat = 6e-6, r32 = 100e12, r64 = 50e12, bw = 3e12;
+  const double F = h->sym.flops, nl = (double)h->sym.nnz_L, n = (double)h->sym.n;
+  const double kv_bytes = 8.0 * (3.0 * (double)h->hp.jc.size() + 2.0 * (double)h->hp.hc.size()) + 96.0 * n;
+  auto fac = [&](const Plan& P, double r) { return lat * (double)P.ops.size() + F / r; };
+  auto step = [&](const Plan& P, double w) {
+    return lat * (double)(P.fwd_ops.size() + P.bwd_ops.size() + 8) + (2.0 * nl * w + 32.0 * n + kv_bytes) / bw;
+  };
+  return CostModel{fac(h->plan32, r32), fac(h->plan64, r64), step(h->plan32, 4.0), step(h->plan64, 8.0)};
+}
+
 int evaluate_point(ipm_handle* h, IpmVecs& v, bool hess) {
   const DevProblem& P = h->dp;
   if (h->hp.kind == KIND_NLP) launch_jac_eval(P, v.x, v.jv, h->stream);
@@ -731,6 +752,7 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     launch_init_point(P, v, h->stream);
   }
   double delta_w_last = 0.0;
+  const CostModel cm = cost_model(h);
   bool stay64 = false;  // FP32 form: switched to FP64 factors for the rest of the solve
   int ntri_prev = 0;    // triangular solves of the previous FP32 iteration
   int status = PDIPM_MAX_ITER;
@@ -764,7 +786,6 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     int fprec = stay64 ? PDIPM_FP64 : prec;
     double delta_w = 0.0;
     auto ta = clk::now();
-    const double factor_ms_before = R.ms_factor;
     const int ir_before = R.ir_steps;
     const bool fp32_iter = !stay64 && prec == PDIPM_FP32;
     assemble_values(h, O.delta_p);
@@ -848,18 +869,15 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     // Cost-based switch of the FP32 form: once the next FP32 iteration is
     // predicted to cost more than an FP64 one, FP64 factors take over for
     // the remaining iterations, where the condition number and with it the
-    // refinement work only grow.  FP32 prediction: this iteration's factor
-    // time (shift retries included) plus its solves, their count grown by
-    // the ratio to the previous FP32 iteration (between 1 and 2).  FP64
-    // prediction: one factorisation at 2.3x one FP32 factorisation (the MFMA
-    // rates of the two precisions differ) plus two solves without
-    // refinement at about two FP32 solves each.
+    // refinement work only grow.  FP32 prediction: this iteration's
+    // factorisations (shift retries included) plus its solves, their count
+    // grown by the ratio to the previous FP32 iteration (between 1 and 2).
+    // FP64 prediction: one factorisation plus two solves.  Both from the
+    // cost model (counts, not clocks).
     if (fp32_iter && !stay64 && O.fp64_fallback && h->need64) {
       const int ntri = 2 + (R.ir_steps - ir_before);
-      const double t_tri = solve_ms / ntri, t32 = R.ms_factor - factor_ms_before;
-      const double t1 = t32 / (1 + shifts);
       const double grow = ntri_prev > 0 ? std::min(2.0, std::max(1.0, (double)ntri / ntri_prev)) : 1.0;
-      if (t32 + grow * ntri * t_tri > 2.3 * t1 + 4.0 * t_tri) {
+      if ((1 + shifts) * cm.fac32 + grow * ntri * cm.step32 > cm.fac64 + 2.0 * cm.step64) {
         stay64 = true;
         R.fp64_refactors++;
       }
@@ -1451,7 +1469,18 @@ int kkt_solve(ipm_handle* h, const double* rhs, double* x, kkt_solve_info* info)
   if (!h->factored) return fail(h, PDIPM_ERR_NOT_ANALYZED, "no valid factor");
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   kkt_solve_info si{};
-  rc = solve_refined(h, rhs, x, &si, 0.0, nullptr);
+  bool conv = false;
+  rc = solve_refined(h, rhs, x, &si, 0.0, &conv);
+  if (rc == PDIPM_OK && !conv && h->factor_prec == PDIPM_FP32 && h->need64) {
+    // FP32 refinement missed the backward-error target: refactor in FP64
+    // and solve again (the handle keeps the FP64 factor afterwards)
+    const int steps32 = si.ir_steps;
+    kkt_factor_info f64{};
+    rc = factor_k(h, PDIPM_FP64, &f64, nullptr, nullptr);
+    if (rc == PDIPM_OK) rc = solve_refined(h, rhs, x, &si, 0.0, &conv);
+    si.ir_steps += steps32;
+    si.fallback = 1;
+  }
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0;
@@ -1518,6 +1547,16 @@ int ipm_get_patterns(ipm_handle* h, int64_t* jrp, int32_t* jci, int64_t* hrp, in
   if (jci) memcpy(jci, h->hp.jc.data(), bytes_of(h->hp.jc));
   if (hrp) memcpy(hrp, h->hp.hp.data(), bytes_of(h->hp.hp));
   if (hci) memcpy(hci, h->hp.hc.data(), bytes_of(h->hp.hc));
+  return PDIPM_OK;
+}
+
+int ipm_set_precision(ipm_handle* h, int precision) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (precision != PDIPM_FP64 && precision != PDIPM_FP32)
+    return fail(h, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+  if ((precision == PDIPM_FP64 && !h->need64) || (precision == PDIPM_FP32 && !h->need32))
+    return fail(h, PDIPM_ERR_INVALID_ARG, "the handle was not created with space for this precision");
+  h->opt.precision = precision;
   return PDIPM_OK;
 }
 

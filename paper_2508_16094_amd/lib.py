@@ -102,6 +102,7 @@ _SIGS = {
     "ipm_pattern_sizes": (ctypes.c_int, [_p, _p, _p]),
     "ipm_get_patterns": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "ipm_solve": (ctypes.c_int, [_p, _p, _p]),
+    "ipm_set_precision": (ctypes.c_int, [_p, ctypes.c_int]),
     "ipm_get_solution": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, ctypes.c_int]),
     "ipm_set_profiling": (ctypes.c_int, [_p, ctypes.c_int]),
     "ipm_get_profile": (ctypes.c_int, [_p, _p]),
@@ -309,7 +310,7 @@ class _Handle:
             out = torch.empty_like(rhs)
         info = kkt_solve_info()
         self._check(lib().kkt_solve(self.h, _dptr(rhs), _dptr(out), ctypes.byref(info)), "kkt_solve")
-        return out, dict(ir_steps=info.ir_steps, residual=info.residual, ms=info.ms)
+        return out, dict(ir_steps=info.ir_steps, residual=info.residual, fallback=info.fallback, ms=info.ms)
 
     def factor_values(self):
         s = self.stats()
@@ -378,6 +379,9 @@ class IpmSolver(_Handle):
         out = np.empty(self.stats()["nnz_K"], np.float64)
         self._check(lib().kkt_get_values(self.h, _ptr(out)), "kkt_get_values")
         return out
+
+    def set_precision(self, precision):
+        self._check(lib().ipm_set_precision(self.h, int(precision)), "ipm_set_precision")
 
     def solve(self, start=None):
         res = ipm_result()

@@ -51,3 +51,50 @@ def test_traffic_record_is_consistent():
         assert abs(r["fetch_scale"] - 2.0) < 0.01 and abs(r["write_scale"] - 1.0) < 0.01
         # traffic can exceed the algorithmic bytes (re-reads) but not fall far below them
         assert r["bytes_per_launch"] >= 0.9 * r["algorithmic_bytes_per_launch"]
+
+
+def _simulate(bm, requested, t_solve, t_before, budget, compare=True):
+    """Wall time of the bench's step loop with solves of t_solve seconds
+    after t_before seconds of set-up and one warmup solve."""
+    now = t_before + t_solve          # set-up, then the (single) warmup
+    t_step, done = t_solve, 0
+    reserve = 2.0 * t_step if compare else 0.0
+    while done < max(1, requested) and bm.plan_steps(done, now, t_step, reserve, budget):
+        now += t_solve
+        done += 1
+    if compare:
+        now += 2.0 * t_solve          # the FP64 solve
+    return done, now
+
+
+def test_driver_command_fits_its_time_limit():
+    """--steps 20 --warmup 5 with a 25 s solve (the 2M-column LP) and about
+    60 s of start-up (torch import, generation, analysis, CPU baseline):
+    the JSON line comes well before 600 s and the steps are reduced."""
+    bm = _bench()
+    done, wall = _simulate(bm, 20, 25.0, 60.0, 450.0)
+    assert 1 <= done < 20
+    assert wall <= 500.0
+    # a slower solve still runs one timed step and stays bounded
+    done, wall = _simulate(bm, 20, 150.0, 60.0, 450.0)
+    assert done == 1 and wall <= 60 + 150 * 4
+    # small workloads run every requested step
+    done, _ = _simulate(bm, 20, 0.02, 10.0, 450.0)
+    assert done == 20
+
+
+def test_first_step_always_runs_and_budget_is_respected():
+    bm = _bench()
+    assert bm.plan_steps(0, 1e9, 10.0, 0.0, 100.0)
+    assert bm.plan_steps(1, 50.0, 10.0, 20.0, 100.0)
+    assert not bm.plan_steps(1, 75.0, 10.0, 20.0, 100.0)
+
+
+def test_cpu_baseline_scaling_and_host_record():
+    bm = _bench()
+    smp = {"what": "x", "seconds": 10.0, "iterations": 10, "flops": 1e9, "status": "optimal"}
+    r = bm.cpu_baseline_scale(smp, 1e12, 20)
+    # 1 s per iteration at 1e9 flops -> 1000 s per iteration at 1e12, 20 iterations
+    assert abs(1.0 / r["value"] - 20000.0) < 1e-6
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["estimate"] is True
+    assert r["host"]["nproc"] >= 1 and isinstance(r["host"]["model"], str)

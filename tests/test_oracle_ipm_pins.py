@@ -180,3 +180,49 @@ def test_warm_start_from_solution_converges_fast():
     assert warm["status"] == ipm.OK
     assert abs(warm["f"] - cold["f"]) <= 1e-6 * (1 + abs(cold["f"]))
     assert warm["iterations"] <= cold["iterations"]
+
+
+def _push_case(m_rows=True):
+    """3 variables: x0 in [0, 10], x1 in [0, 1], x2 <= 100 (no lower bound);
+    rows g1 = x0 + x1 - 0.5, g2 = -x2 + 90 (none when m_rows is False)."""
+    xl = np.array([0.0, 0.0, -np.inf])
+    xu = np.array([10.0, 1.0, 100.0])
+    if m_rows:
+        A = w.csr_from_coo(2, 3, [0, 0, 1], [0, 1, 2], [1.0, 1.0, -1.0])
+        b = np.array([0.5, -90.0])
+    else:
+        A, b = None, np.zeros(0)
+    return w.Problem(n=3, m=2 if m_rows else 0, c=np.zeros(3), b=b, A=A, xl=xl, xu=xu)
+
+
+def test_push_start_hand_computed():
+    """Bound push of a predicted point, values worked out by hand:
+    x0 = -5 -> 0 + min(1e-2 max(1, 0), 1e-2 * 10) = 0.01;
+    x1 = 0.9999 -> 1 - min(1e-2 max(1, 1), 1e-2 * 1) = 0.99;
+    x2 = 150 -> 100 - 1e-2 max(1, 100) = 99 (no lower bound, width infinite);
+    g = (0.01 + 0.99 - 0.5, -99 + 90) = (0.5, -9);
+    s = max(g, 1e-2 max(1, |g|)) = (0.5, 0.09); lambda = max((1e-3, 2e-3), 1e-2) = (0.01, 0.01);
+    mu_w = max(1e-4, s'lambda / m) = (0.005 + 0.0009) / 2 = 0.00295;
+    z_l = mu_w / (x - l) = (0.295, 0.00295 / 0.99, 0); z_u = mu_w / (u - x) = (0.00295 / 9.99, 0.295, 0.00295)."""
+    p = _push_case()
+    xl, xu = model.bounds(p)
+    x, s, lam, zl, zu = ipm.push_start(p, np.array([-5.0, 0.9999, 150.0]), np.array([1e-3, 2e-3]), xl, xu)
+    mu_w = 0.00295
+    np.testing.assert_allclose(x, [0.01, 0.99, 99.0], rtol=1e-14)
+    np.testing.assert_allclose(s, [0.5, 0.09], rtol=1e-12)
+    np.testing.assert_allclose(lam, [0.01, 0.01], rtol=1e-15)
+    np.testing.assert_allclose(zl, [0.295, mu_w / 0.99, 0.0], rtol=1e-12)
+    np.testing.assert_allclose(zu, [mu_w / 9.99, 0.295, mu_w], rtol=1e-12)
+
+
+def test_push_start_floor_without_rows():
+    """With no rows s'lambda / max(1, m) = 0, so mu_w is its floor 1e-4:
+    interior x = (5, 0.5, 3) stays, z_l = (1e-4/5, 1e-4/0.5, 0),
+    z_u = (1e-4/5, 1e-4/0.5, 1e-4/97)."""
+    p = _push_case(m_rows=False)
+    xl, xu = model.bounds(p)
+    x, s, lam, zl, zu = ipm.push_start(p, np.array([5.0, 0.5, 3.0]), np.zeros(0), xl, xu)
+    np.testing.assert_allclose(x, [5.0, 0.5, 3.0], rtol=0)
+    assert s.size == 0 and lam.size == 0
+    np.testing.assert_allclose(zl, [2e-5, 2e-4, 0.0], rtol=1e-14)
+    np.testing.assert_allclose(zu, [2e-5, 2e-4, 1e-4 / 97.0], rtol=1e-14)

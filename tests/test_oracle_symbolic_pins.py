@@ -151,3 +151,51 @@ def test_p6_disconnected_components_in_order():
     adj = _adj_from_edges(9, [(3, 0), (0, 6), (4, 1), (4, 2), (4, 5), (4, 7), (4, 8)])
     nd = symbolic.nested_dissection(adj, 9)
     assert nd == [3, 0, 6, 1, 2, 5, 7, 4, 8]
+
+
+def _two_supernode_columns(k9):
+    """Lower structures of a hand-built factor pattern on 20 columns: a chain
+    0..9 whose last column reaches rows 10..10+k9-1, under a dense 10 x 10
+    root block 10..19.  Column j < 10 has rows j+1..9 and 10..10+k9-1."""
+    cols = []
+    for j in range(10):
+        cols.append(np.array(list(range(j + 1, 10)) + list(range(10, 10 + k9)), dtype=np.int64))
+    for j in range(10, 20):
+        cols.append(np.arange(j + 1, 20, dtype=np.int64))
+    return cols
+
+
+def test_p6_amalgamation_merges_by_zero_fraction_at_width_20():
+    """Hand-derived: child c = columns 0..9 with c_j = 19 - j (its last
+    column reaches rows 10..18), parent s = dense root 10..19 with
+    c_j = 20 - j.  c_9 = 10 != c_10 + 1 = 11, so the fundamental supernodes
+    are [0, 10) and [10, 20).  Merging gives w = 20, h = 20, a trapezoid of
+    w h - w (w - 1) / 2 = 400 - 190 = 210 entries, of which
+    sum(19..10) + sum(10..1) = 145 + 55 = 200 are true: 10 zeros, and
+    10 * 10 <= 1 * 210, so the default rule (zero fraction 1/10, w = 20 > 8)
+    merges them into one supernode."""
+    structs, parent = symbolic.symbolic_factor(_two_supernode_columns(9))
+    cc = np.array([len(s) + 1 for s in structs])
+    assert cc.tolist() == [19 - j for j in range(10)] + [20 - j for j in range(10, 20)]
+    assert parent.tolist() == list(range(1, 20)) + [-1]
+    fund = symbolic.fundamental_supernodes(parent, cc)
+    assert fund == [0, 10]
+    assert symbolic.amalgamate(fund, parent, cc) == [0, 20]
+    # a width cap of 16 forbids the merge (menu entries: max_w, small_w, num, den)
+    assert symbolic.amalgamate(fund, parent, cc, (16, 8, 1, 10)) == [0, 10, 20]
+    # a stricter zero fraction (1/25: 10 * 25 = 250 > 210) rejects it
+    assert symbolic.amalgamate(fund, parent, cc, (1 << 30, 8, 1, 25)) == [0, 10, 20]
+
+
+def test_p6_amalgamation_rejects_too_many_zeros():
+    """Hand-derived: the child's last column reaches row 10 only, so
+    c_j = 11 - j for j < 10 (true entries 11 + ... + 2 = 65) and the merged
+    trapezoid of 210 entries holds 210 - 65 - 55 = 90 zeros: 90 * 10 > 210,
+    no merge; with w <= small_w (a menu with small_w = 20) it always merges."""
+    structs, parent = symbolic.symbolic_factor(_two_supernode_columns(1))
+    cc = np.array([len(s) + 1 for s in structs])
+    assert cc.tolist() == [11 - j for j in range(10)] + [20 - j for j in range(10, 20)]
+    fund = symbolic.fundamental_supernodes(parent, cc)
+    assert fund == [0, 10]
+    assert symbolic.amalgamate(fund, parent, cc) == [0, 10, 20]
+    assert symbolic.amalgamate(fund, parent, cc, (1 << 30, 20, 1, 10)) == [0, 20]
