@@ -41,16 +41,16 @@ STATUS_NAMES = {OK: "optimal", MAX_ITER: "max_iter", TIME_LIMIT: "time_limit",
 
 
 class Factorizer:
-    """Dense (small n) or sparse (fixed symbolic structure) Cholesky."""
+    """Dense (small order) or sparse (fixed symbolic structure) Cholesky of
+    the condensed matrix; pattern() gives the adjacency lists of its
+    structure, used for the symbolic analysis of the sparse path."""
 
-    def __init__(self, problem, J, H, dense_max=1500):
-        self.n = problem.n
+    def __init__(self, order, pattern, dense_max=1500):
+        self.n = order
         self.dense = self.n <= dense_max
         self.count = 0
         if not self.dense:
-            Jp = J.tocsr(); Hl = sp.tril(H).tocsr()
-            adj = symbolic.kkt_pattern(self.n, Jp.indptr, Jp.indices, Hl.indptr, Hl.indices)
-            self.sym = symbolic.analyze(adj, self.n)
+            self.sym = symbolic.analyze(pattern(), self.n)
 
     def factor(self, K):
         self.count += 1
@@ -103,9 +103,17 @@ def _max_step(v, dv):
 
 def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
           max_wall_time=900.0, start=None, dense_max=1500, log=None,
-          force_inertia=False):
+          force_inertia=False, form="primal"):
     """Returns a dict: status, iterations, f, P, D, C, x, s, lam, zl, zu,
-    history (per-iteration mu, alphas, invariants) and factorizations."""
+    history (per-iteration mu, alphas, invariants) and factorizations.
+
+    form "primal" solves each Newton step through the primal condensed
+    system (eq. kkt_primal), "dual" through the dual condensed system
+    (eq. kkt_dual, the normal equations; needs a diagonal Hessian).  The
+    inertia correction of step 5 applies to the primal form; in the dual
+    form a factorisation failure ends the solve with status NUMERICAL."""
+    if form not in ("primal", "dual"):
+        raise ValueError(form)
     t0 = time.time()
     n, m = problem.n, problem.m
     xl, xu = model.bounds(problem)
@@ -147,37 +155,60 @@ def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
             status = TIME_LIMIT
             break
         if fac is None:
-            fac = Factorizer(problem, J, H, dense_max)
+            Jc = J.tocsr()
+            if form == "dual":
+                fac = Factorizer(m, lambda: symbolic.dual_pattern(m, n, Jc.indptr, Jc.indices), dense_max)
+            else:
+                Hl = sp.tril(H).tocsr()
+                fac = Factorizer(n, lambda: symbolic.kkt_pattern(n, Jc.indptr, Jc.indices, Hl.indptr,
+                                                                 Hl.indices), dense_max)
         sig_s, sig_x = kkt.sigmas(x, s, lam, zl, zu, xl, xu, il, iu, delta_d)
-        K = kkt.condensed_matrix(H, J, sig_s, sig_x, delta_p)
-        # step 5: factorisation with inertia correction on failure
         delta_w = 0.0
-        try:
-            if force_inertia:
-                raise chol.NotPositiveDefinite(0)
-            fac.factor(K)
-        except chol.NotPositiveDefinite:
-            delta_w = 1e-4 if delta_w_last == 0.0 else max(1e-20, delta_w_last / 3.0)
-            first = delta_w_last == 0.0
-            while True:
-                try:
-                    fac.factor(K + delta_w * sp.eye(n))
-                    delta_w_last = delta_w
-                    break
-                except chol.NotPositiveDefinite:
-                    delta_w *= 100.0 if first else 8.0
-                    if delta_w > 1e40:
-                        status = NUMERICAL
-                        break
-            if status == NUMERICAL:
+        if form == "dual":
+            # eq. kkt_dual: factor M, d_lambda from M, then d_x
+            dD = kkt.dual_scaling(H, sig_x, delta_p)
+            try:
+                fac.factor(kkt.dual_matrix(J, dD, s, lam, delta_d))
+            except chol.NotPositiveDefinite:
+                status = NUMERICAL
                 break
 
-        def direction(t_s, t_l, t_u):
-            rhs = kkt.condensed_rhs(J, r_d, g, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u)
-            dx = fac.solve(rhs)
-            ds, dlam, dzl, dzu = kkt.recover(J, dx, g, r_p, lam, sig_s, x, zl, zu, xl, xu, il, iu,
-                                             t_s, t_l, t_u, delta_d)
-            return dx, ds, dlam, dzl, dzu
+            def direction(t_s, t_l, t_u):
+                rt = kkt.reduced_dual_residual(r_d, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+                dlam = fac.solve(kkt.dual_rhs(J, dD, rt, g, lam, t_s))
+                dx = kkt.dual_dx(J, dD, dlam, rt)
+                ds = J @ dx + r_p + delta_d * dlam
+                dzl, dzu = kkt.bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+                return dx, ds, dlam, dzl, dzu
+        else:
+            # eq. kkt_primal; step 5: inertia correction on failure
+            K = kkt.condensed_matrix(H, J, sig_s, sig_x, delta_p)
+            try:
+                if force_inertia:
+                    raise chol.NotPositiveDefinite(0)
+                fac.factor(K)
+            except chol.NotPositiveDefinite:
+                delta_w = 1e-4 if delta_w_last == 0.0 else max(1e-20, delta_w_last / 3.0)
+                first = delta_w_last == 0.0
+                while True:
+                    try:
+                        fac.factor(K + delta_w * sp.eye(n))
+                        delta_w_last = delta_w
+                        break
+                    except chol.NotPositiveDefinite:
+                        delta_w *= 100.0 if first else 8.0
+                        if delta_w > 1e40:
+                            status = NUMERICAL
+                            break
+                if status == NUMERICAL:
+                    break
+
+            def direction(t_s, t_l, t_u):
+                rhs = kkt.condensed_rhs(J, r_d, g, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u)
+                dx = fac.solve(rhs)
+                ds, dlam, dzl, dzu = kkt.recover(J, dx, g, r_p, lam, sig_s, x, zl, zu, xl, xu, il, iu,
+                                                 t_s, t_l, t_u, delta_d)
+                return dx, ds, dlam, dzl, dzu
 
         def step_limits(dx, ds, dlam, dzl, dzu):
             ap = min(_max_step(s, ds), _max_step((x - xl)[il], dx[il]),

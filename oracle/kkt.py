@@ -18,6 +18,18 @@ targets (t_s, t_l, t_u) the elimination gives
   d_zl    = t_l/(x-l) - z_l - (z_l/(x-l)) d_x
   d_zu    = t_u/(u-x) - z_u + (z_u/(u-x)) d_x
 Bound terms only exist on finite bounds (masks il, iu).
+
+Dual condensed system (eq. kkt_dual, the normal equations): when the (1,1)
+block H + Sigma_x + delta_p I is diagonal (LP, QP with diagonal Q), it is
+inverted, D = (H + Sigma_x + delta_p I)^-1, and the augmented system in
+(d_x, d_lambda)
+    (H + Sigma_x + delta_p I) d_x - J' d_lambda = -r~_d
+    J d_x + (delta_d I + S/Lambda) d_lambda     = t_s/lambda - g
+gives
+  M        = delta_d I + S/Lambda + J D J'              (m x m, SPD)
+  M d_lam  = t_s/lambda - g + J D r~_d
+  d_x      = D (J' d_lam - r~_d)
+  d_s      = J d_x + r_p + delta_d d_lam,  d_z as above.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -43,12 +55,55 @@ def condensed_rhs(J, r_d, g, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_
     return -rt - J.T @ (sig_s * (g - t_s / lam))
 
 
-def recover(J, dx, g, r_p, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u, delta_d):
-    Jdx = J @ dx
-    dlam = sig_s * (t_s / lam - g - Jdx)
-    ds = Jdx + r_p + delta_d * dlam
+def bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u):
     dzl = np.zeros_like(x)
     dzu = np.zeros_like(x)
     dzl[il] = t_l[il] / (x[il] - xl[il]) - zl[il] - zl[il] / (x[il] - xl[il]) * dx[il]
     dzu[iu] = t_u[iu] / (xu[iu] - x[iu]) - zu[iu] + zu[iu] / (xu[iu] - x[iu]) * dx[iu]
+    return dzl, dzu
+
+
+def recover(J, dx, g, r_p, lam, sig_s, x, zl, zu, xl, xu, il, iu, t_s, t_l, t_u, delta_d):
+    Jdx = J @ dx
+    dlam = sig_s * (t_s / lam - g - Jdx)
+    ds = Jdx + r_p + delta_d * dlam
+    dzl, dzu = bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u)
     return ds, dlam, dzl, dzu
+
+
+class NotDiagonal(ValueError):
+    """The dual condensed system needs a diagonal (1,1) block."""
+
+
+def dual_scaling(H, sig_x, delta_p):
+    """D = (H + Sigma_x + delta_p I)^-1 for a diagonal H (NotDiagonal
+    otherwise).  Entries that are not positive are returned as they are
+    (1 / value): M is then not positive definite and its factorisation
+    reports it."""
+    Hc = H.tocsr()
+    if (Hc - sp.diags(Hc.diagonal())).count_nonzero():
+        raise NotDiagonal("the dual condensed system needs a diagonal Hessian")
+    return 1.0 / (Hc.diagonal() + sig_x + delta_p)
+
+
+def dual_matrix(J, d, s, lam, delta_d):
+    """M = delta_d I + S/Lambda + J D J' (eq. kkt_dual)."""
+    return (sp.diags(delta_d + s / lam) + J @ sp.diags(d) @ J.T).tocsr()
+
+
+def reduced_dual_residual(r_d, x, zl, zu, xl, xu, il, iu, t_l, t_u):
+    """r~_d: r_d with the bound complementarity targets folded in."""
+    rt = r_d.copy()
+    rt[il] += -t_l[il] / (x[il] - xl[il]) + zl[il]
+    rt[iu] += t_u[iu] / (xu[iu] - x[iu]) - zu[iu]
+    return rt
+
+
+def dual_rhs(J, d, rt, g, lam, t_s):
+    """Right-hand side of M d_lambda: t_s/lambda - g + J D r~_d."""
+    return t_s / lam - g + J @ (d * rt)
+
+
+def dual_dx(J, d, dlam, rt):
+    """d_x = D (J' d_lambda - r~_d)."""
+    return d * (J.T @ dlam - rt)

@@ -67,6 +67,14 @@ def kkt_pattern(n, J_rowptr, J_colind, H_rowptr=None, H_colind=None):
     return adjacency_from_sym(S.tocsr(), n)
 
 
+def dual_pattern(m, n, J_rowptr, J_colind):
+    """Adjacency lists (no self loops) of the structure of the dual
+    condensed matrix M = diag + J D J' (m x m), from J's CSR pattern."""
+    nnzj = int(J_rowptr[-1])
+    Jb = sp.csr_matrix((np.ones(nnzj), np.asarray(J_colind), np.asarray(J_rowptr)), shape=(m, n))
+    return adjacency_from_sym((Jb @ Jb.T).tocsr(), m)
+
+
 def pattern_from_lower_csr(n, rowptr, colind):
     nnz = int(rowptr[-1])
     L = sp.csr_matrix((np.ones(nnz), np.asarray(colind), np.asarray(rowptr)), shape=(n, n))

@@ -33,12 +33,13 @@ def _vertex_enumeration_lp(p):
     return best
 
 
+@pytest.mark.parametrize("form", ["primal", "dual"])
 @pytest.mark.parametrize("seed", range(6))
-def test_p1_tiny_lp_vertex_enumeration(seed):
+def test_p1_tiny_lp_vertex_enumeration(seed, form):
     n, m = 4 + seed % 3, 3 + seed % 4
     p = w.random_lp(n, m, min(3, m), 777 + seed)
     f_star = _vertex_enumeration_lp(p)
-    r = ipm.solve(p, tol=1e-10)
+    r = ipm.solve(p, tol=1e-10, form=form)
     assert r["status"] == ipm.OK
     assert abs(r["f"] - f_star) <= 1e-7 * max(1.0, abs(f_star))
 
@@ -82,8 +83,9 @@ def test_p2_separable_box_qp_closed_form(seed):
     assert np.max(np.abs(r["x"] - x_star)) <= 1e-6
 
 
+@pytest.mark.parametrize("form", ["primal", "dual"])
 @pytest.mark.parametrize("seed", range(4))
-def test_p2_one_constraint_qp_bisection(seed):
+def test_p2_one_constraint_qp_bisection(seed, form):
     p, q = _box_qp(15, 200 + seed, True)
     a = p.A.val
     beta = p.b[0]
@@ -102,7 +104,7 @@ def test_p2_one_constraint_qp_bisection(seed):
             hi = mid
     nu = 0.5 * (lo + hi)
     x_star = x_of(nu)
-    r = ipm.solve(p, tol=1e-10)
+    r = ipm.solve(p, tol=1e-10, form=form)
     assert r["status"] == ipm.OK
     assert np.max(np.abs(r["x"] - x_star)) <= 1e-6
     assert abs(r["lam"][0] - nu) <= 1e-5 * max(1.0, nu)
@@ -226,3 +228,20 @@ def test_push_start_floor_without_rows():
     assert s.size == 0 and lam.size == 0
     np.testing.assert_allclose(zl, [2e-5, 2e-4, 0.0], rtol=1e-14)
     np.testing.assert_allclose(zu, [2e-5, 2e-4, 1e-4 / 97.0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("maker", [lambda: w.lp_small(2), lambda: w.qp_instance(300, 5),
+                                   lambda: w.lp_block(nblocks=3, block_rows=150, block_cols=300,
+                                                      link_cols_per_block=10)])
+def test_dual_form_invariants_and_same_optimum(maker):
+    """P7 for the dual form: interior iterates, fraction to the boundary and
+    the LP/QP dual objective; its optimum is the primal form's."""
+    p = maker()
+    r = ipm.solve(p, tol=1e-9, form="dual", dense_max=0)
+    ref = ipm.solve(p, tol=1e-9)
+    assert r["status"] == ipm.OK and ref["status"] == ipm.OK
+    assert abs(r["f"] - ref["f"]) <= 1e-7 * max(1.0, abs(ref["f"]))
+    for h in r["history"]:
+        assert h["min_s"] > 0 and h["min_lam"] > 0 and h["min_z"] > 0
+    chk = checker.check(p, r["x"], r["s"], r["lam"], r["zl"], r["zu"])
+    assert max(chk["P"], chk["D"], chk["C"]) <= 1e-9

@@ -162,3 +162,77 @@ def test_p8_grid_jacobian_exact_form():
     x = np.random.default_rng(1).uniform(-1, 1, p.n)
     J = model.jacobian(p, x).tocoo()
     assert np.allclose(J.data, -2.0 * x[J.col] / 5.0, rtol=0, atol=1e-15)
+
+
+def _dual_step(p, x, s, lam, zl, zu, t_s, t_l, t_u, dp, dd):
+    """Step through the dual condensed system (eq. kkt_dual), solved densely."""
+    xl, xu = model.bounds(p)
+    il, iu = np.isfinite(xl), np.isfinite(xu)
+    J = model.jacobian(p, x); H = model.hessian(p, x, lam)
+    gf = model.gradient(p, x); g = model.constraints(p, x)
+    r_d = gf - J.T @ lam - zl + zu
+    _, sig_x = kkt.sigmas(x, s, lam, zl, zu, xl, xu, il, iu, dd)
+    d = kkt.dual_scaling(H, sig_x, dp)
+    M = kkt.dual_matrix(J, d, s, lam, dd)
+    rt = kkt.reduced_dual_residual(r_d, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+    dlam = np.linalg.solve(M.toarray(), kkt.dual_rhs(J, d, rt, g, lam, t_s))
+    dx = kkt.dual_dx(J, d, dlam, rt)
+    ds = J @ dx + (g - s) + dd * dlam
+    dzl, dzu = kkt.bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+    return dx, ds, dlam, dzl, dzu
+
+
+def _random_point(p, rng):
+    xl, xu = model.bounds(p)
+    n, m = p.n, p.m
+    lo = np.where(np.isfinite(xl), xl, -5.0); hi = np.where(np.isfinite(xu), xu, 5.0)
+    x = lo + rng.uniform(0.2, 0.8, n) * (hi - lo)
+    s = rng.uniform(0.5, 2.0, m); lam = rng.uniform(0.5, 2.0, m)
+    zl = np.where(np.isfinite(xl), rng.uniform(0.5, 2, n), 0.0)
+    zu = np.where(np.isfinite(xu), rng.uniform(0.5, 2, n), 0.0)
+    t_s = rng.uniform(0, 0.3, m)
+    t_l = np.where(np.isfinite(xl), rng.uniform(0, 0.3, n), 0.0)
+    t_u = np.where(np.isfinite(xu), rng.uniform(0, 0.3, n), 0.0)
+    return x, s, lam, zl, zu, t_s, t_l, t_u
+
+
+@pytest.mark.parametrize("which", ["lp", "qp", "halfbounds", "more_rows"])
+def test_p5_dual_condensed_equals_full_kkt(which):
+    """eq. kkt_dual: the normal-equations step equals the Newton step of the
+    full regularised system (dense partial-pivot LU) component by component."""
+    rng = np.random.default_rng(8)
+    if which == "lp":
+        p = w.random_lp(12, 7, 3, 11)
+    elif which == "qp":
+        p = w.qp_instance(14, 3)
+    elif which == "more_rows":
+        p = w.random_lp(8, 13, 4, 19)
+    else:
+        p = w.random_lp(10, 6, 3, 12)
+        p.xl = np.where(np.arange(10) % 3 == 0, -np.inf, 0.0)
+        p.xu = np.where(np.arange(10) % 3 == 1, np.inf, 10.0)
+    pt = _random_point(p, rng)
+    for dp, dd in [(1e-8, 1e-8), (0.3, 0.2)]:
+        a = _full_kkt_step(p, *pt, dp, dd)
+        b = _dual_step(p, *pt, dp, dd)
+        for u, v in zip(a, b):
+            assert np.max(np.abs(u - v)) <= 1e-9 * max(1.0, np.max(np.abs(u)))
+
+
+def test_dual_condensed_needs_a_diagonal_hessian():
+    p = w.nlp_grid(4, 4)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.1, 0.5, p.n)
+    with pytest.raises(kkt.NotDiagonal):
+        kkt.dual_scaling(model.hessian(p, x, np.ones(p.m)), np.zeros(p.n), 1e-8)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_dual_pattern_is_the_structure_of_j_jt(seed):
+    p = w.random_lp(30, 18, 3, seed)
+    J = model.jacobian(p, np.ones(p.n)).tocsr()
+    adj = symbolic.dual_pattern(p.m, p.n, J.indptr, J.indices)
+    B = (J.toarray() != 0).astype(int)
+    S = (B @ B.T) > 0
+    for v in range(p.m):
+        assert adj[v] == [u for u in range(p.m) if S[v, u] and u != v]
