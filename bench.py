@@ -345,6 +345,9 @@ def main():
     ap.add_argument("--workload", default="lp_block")
     ap.add_argument("--nblocks", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--form", default="primal", choices=["primal", "dual"],
+                    help="KKT system factored each iteration: the primal condensed K (n x n) or the dual "
+                         "condensed normal-equations matrix M (m x m; LP and diagonal QP)")
     ap.add_argument("--time-budget", type=float, default=450.0,
                     help="wall seconds from process start within which the JSON line is printed; "
                          "timed steps and warmups stop early to keep it")
@@ -397,7 +400,8 @@ def main():
     # FP32 form: FP64 factors take over for the rest of a solve once FP32
     # refinement cannot reach the accuracy the iteration needs; the FP64
     # space also serves the FP64 comparison solve on the same handle
-    s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0)
+    form = L.PDIPM_KKT_DUAL if args.form == "dual" else L.PDIPM_KKT_PRIMAL
+    s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0, kkt_form=form)
     st = s.stats()
     t_setup = time.time() - t
     log(f"[bench] analysed in {t_setup:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
@@ -464,6 +468,8 @@ def main():
         "dtype": "f32" if prec == L.PDIPM_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": name, "form": "fp32 factor + fp64 refinement" if prec == L.PDIPM_FP32 else "fp64",
+                   "kkt_system": "primal condensed K (n x n)" if args.form == "primal"
+                   else "dual condensed M (m x m, normal equations)",
                    "tol": 1e-6, "parallelism": "single GPU"},
         "status": last["status"], "iterations": last["iterations"], "f": last["f"],
         "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],

@@ -56,6 +56,9 @@ extern "C" {
 #define PDIPM_HOST 0
 #define PDIPM_DEVICE 1
 
+#define PDIPM_KKT_PRIMAL 0        /* primal condensed K (Section 3, eq. kkt_primal) */
+#define PDIPM_KKT_DUAL 1          /* dual condensed M (Section 3, eq. kkt_dual) */
+
 typedef struct pdipm_csr {
   int64_t nrows, ncols;
   const int64_t* rowptr; /* [nrows+1]; NULL = empty matrix */
@@ -68,7 +71,10 @@ typedef struct ipm_problem_desc {
   const double* c;  /* [n], required */
   const double* b;  /* [m], required when m > 0 */
   pdipm_csr A;      /* m x n, may be empty */
-  pdipm_csr W;      /* m x n, entries >= 0 (keeps g concave), may be empty */
+  pdipm_csr W;      /* m x n, may be empty.  W >= 0 keeps g concave (a
+                       convex problem); negative entries make the problem
+                       nonconvex, and the primal condensed form then relies
+                       on inertia correction (Section 3, Regularization) */
   pdipm_csr Q;      /* n x n lower triangle, may be empty */
   const double* q4; /* [n] or NULL */
   const double* xl; /* [n] or NULL (= -inf); -INFINITY allowed */
@@ -92,6 +98,18 @@ typedef struct ipm_options {
                             the accuracy an iteration needs (default 1) */
   int32_t use_graphs;    /* batched solve: 1 replays captured HIP graphs
                             (default), 0 launches the same kernels eagerly */
+  int32_t kkt_form;      /* PDIPM_KKT_PRIMAL (default): factor the primal
+                            condensed K (n x n).  PDIPM_KKT_DUAL: factor the
+                            dual condensed (normal-equations) matrix
+                            M = diag(1/Sigma_s) + J D J',
+                            D = (H + Sigma_x + delta_p)^-1 (m x m; Section 3,
+                            eq. kkt_dual), and solve K d = r as
+                            d = D (r - J' M^-1 J D r), refined against K in
+                            FP64.  Needs a diagonal Hessian (Q diagonal or
+                            empty) and m >= 1; a non-positive pivot ends
+                            ipm_solve with PDIPM_ERR_NUMERICAL (no inertia
+                            correction).  The symbolic, pattern, value and
+                            factor calls then describe M. */
 } ipm_options;
 
 typedef struct kkt_symbolic_stats {

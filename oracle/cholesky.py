@@ -33,6 +33,9 @@ def lib():
         L.oracle_sparse_cholesky.argtypes = [i64, p, p, p]
         L.oracle_sparse_cholesky.restype = ctypes.c_int
         L.oracle_sparse_solve.argtypes = [i64, p, p, p, p]
+        L.oracle_sparse_ldlt.argtypes = [i64, p, p, p, p]
+        L.oracle_sparse_ldlt.restype = ctypes.c_int
+        L.oracle_sparse_ldlt_solve.argtypes = [i64, p, p, p, p, p]
         _lib = L
     return _lib
 
@@ -56,6 +59,12 @@ def dense_solve(L, b):
     x = np.array(b, dtype=np.float64, copy=True)
     lib().oracle_dense_solve(L.shape[0], _ptr(L), _ptr(x))
     return x
+
+
+class SingularPivot(ArithmeticError):
+    def __init__(self, col):
+        super().__init__(f"zero or non-finite pivot at column {col}")
+        self.col = col
 
 
 class NotPositiveDefinite(ArithmeticError):
@@ -99,6 +108,38 @@ class SparseFactor:
             raise NotPositiveDefinite(st - 1)
         self.Lx = Lx
         return self
+
+    def _place(self, K):
+        """K's lower entries (permuted) placed into L's structure."""
+        n = self.n
+        Kp = sp.csc_matrix(K)[self.perm, :][:, self.perm]
+        Kl = sp.tril(Kp).tocsc()
+        Kl.sort_indices()
+        Lx = np.zeros(len(self.Li))
+        for j in range(n):
+            rows = self.Li[self.Lp[j]:self.Lp[j + 1]]
+            pos_j = self.Lp[j] + np.searchsorted(rows, Kl.indices[Kl.indptr[j]:Kl.indptr[j + 1]])
+            Lx[pos_j] = Kl.data[Kl.indptr[j]:Kl.indptr[j + 1]]
+        return Lx
+
+    def factor_ldlt(self, K):
+        """P'KP = L D L' with unit lower L and D of either sign (no
+        pivoting); self.D holds D.  Raises SingularPivot."""
+        Lx = self._place(K)
+        D = np.zeros(self.n)
+        st = lib().oracle_sparse_ldlt(self.n, _ptr(self.Lp), _ptr(self.Li), _ptr(Lx), _ptr(D))
+        if st:
+            raise SingularPivot(st - 1)
+        self.Lx, self.D = Lx, D
+        return self
+
+    def solve_ldlt(self, b):
+        x = np.array(np.asarray(b, dtype=np.float64)[self.perm], copy=True)
+        lib().oracle_sparse_ldlt_solve(self.n, _ptr(self.Lp), _ptr(self.Li), _ptr(self.Lx), _ptr(self.D),
+                                       _ptr(x))
+        out = np.empty(self.n)
+        out[self.perm] = x
+        return out
 
     def solve(self, b):
         x = np.array(np.asarray(b, dtype=np.float64)[self.perm], copy=True)

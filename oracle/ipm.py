@@ -109,10 +109,13 @@ def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
 
     form "primal" solves each Newton step through the primal condensed
     system (eq. kkt_primal), "dual" through the dual condensed system
-    (eq. kkt_dual, the normal equations; needs a diagonal Hessian).  The
-    inertia correction of step 5 applies to the primal form; in the dual
-    form a factorisation failure ends the solve with status NUMERICAL."""
-    if form not in ("primal", "dual"):
+    (eq. kkt_dual, the normal equations; needs a diagonal Hessian),
+    "augmented" through the SQD augmented system (eq. augmentedKKT) with a
+    signed LDL' factorisation.  The inertia correction of step 5 applies to
+    the primal form; in the other forms a factorisation failure (or, in the
+    augmented form, a pivot whose sign is not its block's) ends the solve
+    with status NUMERICAL."""
+    if form not in ("primal", "dual", "augmented"):
         raise ValueError(form)
     t0 = time.time()
     n, m = problem.n, problem.m
@@ -156,7 +159,14 @@ def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
             break
         if fac is None:
             Jc = J.tocsr()
-            if form == "dual":
+            if form == "augmented":
+                Hl = sp.tril(H).tocsr()
+                aug_sym = symbolic.analyze(symbolic.augmented_pattern(n, m, Jc.indptr, Jc.indices, Hl.indptr,
+                                                                      Hl.indices), n + m)
+                fac = chol.SparseFactor(aug_sym["perm"], aug_sym["structs"])
+                fac.count = 0
+                block_sign = np.concatenate([np.ones(n), -np.ones(m)])[aug_sym["perm"]]
+            elif form == "dual":
                 fac = Factorizer(m, lambda: symbolic.dual_pattern(m, n, Jc.indptr, Jc.indices), dense_max)
             else:
                 Hl = sp.tril(H).tocsr()
@@ -164,7 +174,25 @@ def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
                                                                  Hl.indices), dense_max)
         sig_s, sig_x = kkt.sigmas(x, s, lam, zl, zu, xl, xu, il, iu, delta_d)
         delta_w = 0.0
-        if form == "dual":
+        if form == "augmented":
+            # eq. augmentedKKT: signed LDL' of the SQD matrix
+            fac.count += 1
+            try:
+                fac.factor_ldlt(kkt.augmented_matrix(H, J, s, lam, sig_x, delta_p, delta_d))
+            except chol.SingularPivot:
+                status = NUMERICAL
+                break
+            if np.any(np.sign(fac.D) != block_sign):
+                status = NUMERICAL
+                break
+
+            def direction(t_s, t_l, t_u):
+                rt = kkt.reduced_dual_residual(r_d, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+                dx, dlam = kkt.augmented_split(fac.solve_ldlt(kkt.augmented_rhs(rt, g, lam, t_s)), n)
+                ds = J @ dx + r_p + delta_d * dlam
+                dzl, dzu = kkt.bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+                return dx, ds, dlam, dzl, dzu
+        elif form == "dual":
             # eq. kkt_dual: factor M, d_lambda from M, then d_x
             dD = kkt.dual_scaling(H, sig_x, delta_p)
             try:

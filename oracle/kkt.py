@@ -30,6 +30,14 @@ gives
   M d_lam  = t_s/lambda - g + J D r~_d
   d_x      = D (J' d_lam - r~_d)
   d_s      = J d_x + r_p + delta_d d_lam,  d_z as above.
+
+Augmented system (eq. augmentedKKT) with the bound term folded into the
+(1,1) block, in the unknowns (d_x, -d_lambda):
+  [ H + Sigma_x + delta_p I    J'                   ] [ d_x      ]   [ -r~_d          ]
+  [ J                          -(delta_d I + S/Lam) ] [ -d_lam   ] = [ t_s/lambda - g ]
+For convex problems the matrix is symmetric quasi-definite (SQD): it has
+P'AP = L D L' for every permutation P, with D positive on the x block and
+negative on the lambda block (Section 2, strong factorisability).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -107,3 +115,21 @@ def dual_rhs(J, d, rt, g, lam, t_s):
 def dual_dx(J, d, dlam, rt):
     """d_x = D (J' d_lambda - r~_d)."""
     return d * (J.T @ dlam - rt)
+
+
+def augmented_matrix(H, J, s, lam, sig_x, delta_p, delta_d):
+    """The SQD matrix of eq. augmentedKKT (x block first, then lambda)."""
+    n, m = H.shape[0], J.shape[0]
+    A11 = (H + sp.diags(sig_x + delta_p)).tocsr()
+    A22 = sp.diags(-(delta_d + s / lam))
+    return sp.bmat([[A11, J.T], [J, A22]], format="csr")
+
+
+def augmented_rhs(rt, g, lam, t_s):
+    """[-r~_d; t_s/lambda - g]."""
+    return np.concatenate([-rt, t_s / lam - g])
+
+
+def augmented_split(v, n):
+    """(d_x, d_lambda) from the solution (d_x, -d_lambda)."""
+    return v[:n], -v[n:]

@@ -75,6 +75,17 @@ def dual_pattern(m, n, J_rowptr, J_colind):
     return adjacency_from_sym((Jb @ Jb.T).tocsr(), m)
 
 
+def augmented_pattern(n, m, J_rowptr, J_colind, H_rowptr, H_colind):
+    """Adjacency lists (no self loops) of the structure of the augmented
+    matrix [H J'; J diag] (x block 0..n-1, lambda block n..n+m-1)."""
+    nnzj = int(J_rowptr[-1])
+    Jb = sp.csr_matrix((np.ones(nnzj), np.asarray(J_colind), np.asarray(J_rowptr)), shape=(m, n))
+    nnzh = int(H_rowptr[-1])
+    Hb = sp.csr_matrix((np.ones(nnzh), np.asarray(H_colind), np.asarray(H_rowptr)), shape=(n, n))
+    S = sp.bmat([[Hb + Hb.T, Jb.T], [Jb, None]], format="csr")
+    return adjacency_from_sym(S, n + m)
+
+
 def pattern_from_lower_csr(n, rowptr, colind):
     nnz = int(rowptr[-1])
     L = sp.csr_matrix((np.ones(nnz), np.asarray(colind), np.asarray(rowptr)), shape=(n, n))

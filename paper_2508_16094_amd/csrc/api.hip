@@ -59,6 +59,7 @@ struct ipm_handle {
   hipStream_t stream = 0;
   ipm_options opt{};
   bool standalone = false;
+  bool dual = false;            // steps through the dual condensed system M
   HostProblem hp;
   Graph graph;
   Symbolic sym;
@@ -80,7 +81,7 @@ struct ipm_handle {
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
     size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
-    size_t vec[49];
+    size_t vec[53];
   } o{};
   DevProblem dp{};
   DevPlan dpl64{}, dpl32{};
@@ -103,6 +104,7 @@ struct ipm_handle {
   IpmVecs v{}, tv{};
   double *dxa, *dsa, *dla, *dzla, *dzua, *dx, *ds, *dl, *dzl, *dzu, *ts, *tl, *tu, *rhs, *ir_r, *ir_c,
       *ir_kx, *xhat, *lamhat, *cg_p;
+  double *dual_d = nullptr, *dual_e = nullptr, *dual_tn = nullptr, *dual_tm = nullptr;
   // factor state
   int assembled_prec = -1, factor_prec = -1;
   bool values_set = false, factored = false;
@@ -262,10 +264,11 @@ void layout(ipm_handle* h) {
   o.uvec = r.take((size_t)std::max<int64_t>(1, P.uv_elems) * 8);
   o.ysol = r.take(n * 8);
   o.part = r.take((size_t)std::max(h->need64 ? c64.part : 1, h->need32 ? c32.part : 1) * 8);
-  // vectors: 0..47 (n or m sized)
-  const int64_t nv = std::max<int64_t>(n, 1), mv = std::max<int64_t>(m, 1);
+  // vectors: 0..52 (n or m sized; n of the problem, which for the dual
+  // condensed system differs from the order of the factored matrix)
+  const int64_t nv = std::max<int64_t>(h->standalone ? n : p.n, 1), mv = std::max<int64_t>(m, 1);
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
-  const int64_t sizes[49] = {
+  const int64_t sizes[] = {
       nv, mv, mv, nv, nv,          // 0 x, 1 s, 2 lam, 3 zl, 4 zu
       nv, nv, mv, jn, hn,          // 5 gf, 6 qx, 7 g, 8 jv, 9 hv
       nv, mv, mv, nv,              // 10 rd, 11 rp, 12 sig_s, 13 sig_x
@@ -276,8 +279,10 @@ void layout(ipm_handle* h) {
       nv, mv, mv, nv, nv,          // 34..38 dx, ds, dlam, dzl, dzu
       mv, nv, nv, nv,              // 39 ts, 40 tl, 41 tu, 42 rhs
       nv, nv, nv, nv, mv,          // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
-      nv};                         // 48 cg direction
-  for (int i = 0; i < 49; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+      nv,                          // 48 cg direction
+      nv, mv, nv, mv};             // 49 D, 50 E, 51..52 dual solve temporaries
+  static_assert(sizeof(sizes) / sizeof(sizes[0]) == sizeof(o.vec) / sizeof(o.vec[0]), "vector table");
+  for (int i = 0; i < 53; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
   if (h->bcount > 0) {
     auto& b = h->bo;
     b.xoff = r.take(bytes_of(h->bxoff)); b.roff = r.take(bytes_of(h->broff));
@@ -392,8 +397,8 @@ int bind_workspace(ipm_handle* h) {
   h->dscale = at<double>(h, o.dscale);
   h->ysol = at<double>(h, o.ysol);
   h->part = at<double>(h, o.part);
-  double* V[49];
-  for (int i = 0; i < 49; ++i) V[i] = at<double>(h, o.vec[i]);
+  double* V[53];
+  for (int i = 0; i < 53; ++i) V[i] = at<double>(h, o.vec[i]);
   IpmVecs& v = h->v;
   v.x = V[0]; v.s = V[1]; v.lam = V[2]; v.zl = V[3]; v.zu = V[4]; v.gf = V[5]; v.qx = V[6]; v.g = V[7];
   v.jv = V[8]; v.hv = V[9]; v.rd = V[10]; v.rp = V[11]; v.sig_s = V[12]; v.sig_x = V[13];
@@ -407,6 +412,7 @@ int bind_workspace(ipm_handle* h) {
   h->ts = V[39]; h->tl = V[40]; h->tu = V[41]; h->rhs = V[42];
   h->ir_r = V[43]; h->ir_c = V[44]; h->ir_kx = V[45]; h->xhat = V[46]; h->lamhat = V[47];
   h->cg_p = V[48];
+  h->dual_d = V[49]; h->dual_e = V[50]; h->dual_tn = V[51]; h->dual_tm = V[52];
   h->ws_ready = true;
   h->assembled_prec = h->factor_prec = -1;
   h->factored = h->values_set = false;
@@ -435,7 +441,8 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
     h->pev.resize(2 * P.gemm_launches);
     for (size_t i = old; i < h->pev.size(); ++i) HIPCHK(h, hipEventCreate(&h->pev[i]));
   }
-  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  const bool timing = h->ev0 != nullptr;   // no events on a handle never given a workspace
+  if (timing) HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   int64_t gl = 0;
   for (const Op& op : P.ops) {
     const bool timed = prof && (op.type == OP_TRSM || op.type == OP_UPDATE);
@@ -446,13 +453,13 @@ int factor_now(ipm_handle* h, int prec, kkt_factor_info* info) {
       launch_factor_op<float>(op, D, (float*)h->panel, (float*)h->ubuf, (float*)h->inv, h->bad, h->stream);
     if (timed) { HIPCHK(h, hipEventRecord(h->pev[2 * gl + 1], h->stream)); ++gl; }
   }
-  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  if (timing) HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   HIPCHK(h, hipGetLastError());
   int badcol = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(&badcol, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0;
-  hipEventElapsedTime(&ms, h->ev0, h->ev1);
+  if (timing) hipEventElapsedTime(&ms, h->ev0, h->ev1);
   if (prof) {
     double gms = 0;
     // optional diagnostic: GEMM time and rate by launch class (panel solve,
@@ -531,6 +538,20 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
   launch_permute_out(D, h->ysol, d, out, h->stream);
 }
 
+// Solve K x = rhs with the current factor.  Primal condensed form: the
+// factor is of K.  Dual condensed form (Section 3, eq. kkt_dual): the factor
+// is of M = diag(E) + J D J', and K^-1 = D - D J' M^-1 J D, so
+// x = D (rhs - J' M^-1 J D rhs).
+void ksolve(ipm_handle* h, const double* rhs, double* out) {
+  if (!h->dual) { trisolve(h, rhs, out); return; }
+  const DevProblem& P = h->dp;
+  launch_mul_vec(P.n, h->dual_d, rhs, h->dual_tn, h->stream);
+  launch_j_mul(P, h->v.jv, h->dual_tn, h->dual_tm, h->stream);
+  trisolve(h, h->dual_tm, h->dual_tm);
+  launch_jt_mul(P, h->v.jv, h->dual_tm, h->dual_tn, h->stream);
+  launch_dual_finish(P.n, h->dual_d, rhs, h->dual_tn, out, h->stream);
+}
+
 void kmul(ipm_handle* h, const double* x, double* out) {
   if (h->standalone)
     launch_k_mul_stored(h->sym.n, nullptr, nullptr, at<int64_t>(h, h->o.ksp), at<int32_t>(h, h->o.ksc),
@@ -548,8 +569,8 @@ void kmul(ipm_handle* h, const double* x, double* out) {
 // when the residual stagnates.
 int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info* info, double target,
                   bool* converged) {
-  const int64_t n = h->sym.n;
-  trisolve(h, rhs, out);
+  const int64_t n = h->hp.n;   // order of K
+  ksolve(h, rhs, out);
   int steps = 0;
   double omega = 0, rnorm = 0, nb = 0, nx = 0;
   const bool fp32 = h->factor_prec == PDIPM_FP32;
@@ -564,7 +585,7 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
     rnorm = nr[0]; nb = nr[1]; nx = nr[2];
     if (!std::isfinite(rnorm) || rnorm <= goal() || it >= h->opt.ir_max || !(rnorm < 0.5 * prev)) break;
     prev = rnorm;
-    trisolve(h, h->ir_r, h->ir_c);
+    ksolve(h, h->ir_r, h->ir_c);
     launch_add(n, out, h->ir_c, h->stream);
     ++steps;
   }
@@ -572,7 +593,7 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
   if (fp32 && std::isfinite(rnorm) && rnorm > goal()) {
     // PCG from the refined point; ir_r holds its residual
     double* r = h->ir_r; double* z = h->ir_c; double* q = h->ir_kx; double* p = h->cg_p;
-    trisolve(h, r, z);
+    ksolve(h, r, z);
     launch_copy(n, p, z, h->stream);
     launch_dot(n, r, z, h->partials, h->stream);
     double rho;
@@ -595,7 +616,7 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
       if (rnorm <= goal() || !std::isfinite(rnorm)) { ++cg; break; }
       if (rnorm < 0.9 * best) { best = rnorm; since_best = 0; }
       else if (++since_best >= 8) { ++cg; break; }   // stagnation
-      trisolve(h, r, z);
+      ksolve(h, r, z);
       launch_dot(n, r, z, h->partials, h->stream);
       double rho2;
       if ((rc = read_back(h, red_out(h), &rho2, 1))) return rc;
@@ -614,8 +635,16 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
 }
 
 // K values (FP64, K pattern order) for the point held in the vectors.
+// Dual condensed form: the values of M = diag(1 / Sigma_s) + J D J' with
+// D = (H + Sigma_x + delta_p)^-1 (the assembly map of M has no Hessian term;
+// its triples scale by D and its diagonal adds E = 1 / Sigma_s).
 void assemble_values(ipm_handle* h, double delta_p) {
-  launch_assemble<double>(h->dk, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, nullptr, h->kval, h->stream);
+  if (h->dual) {
+    launch_dual_prep(h->dp, h->v.hv, h->v.sig_x, h->v.sig_s, delta_p, h->dual_d, h->dual_e, h->stream);
+    launch_assemble<double>(h->dk, h->v.hv, h->v.jv, h->dual_d, h->dual_e, 0.0, nullptr, h->kval, h->stream);
+  } else {
+    launch_assemble<double>(h->dk, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, nullptr, h->kval, h->stream);
+  }
   h->cur_delta_p = delta_p;
 }
 
@@ -631,6 +660,14 @@ int load_panels(ipm_handle* h, int prec, double shift) {
   int rc = read_back(h, red_out(h), dd, 3);
   if (rc) return rc;
   h->kmax = dd[0] > 0 ? dd[0] : 1.0;
+  if (h->dual && dd[1] == 0) {
+    // the backward error refers to K, whose largest diagonal entry is
+    // formed from D, Sigma_s and J
+    launch_kdiag_max(h->dp, h->v.jv, h->v.sig_s, h->dual_d, h->partials, h->stream);
+    double km;
+    if ((rc = read_back(h, red_out(h), &km, 1))) return rc;
+    h->kmax = km > 0 && std::isfinite(km) ? km : 1.0;
+  }
   if (dd[1] > 0) {
     h->factored = false;
     h->bad_diag_col = h->sym.pinv[(int64_t)dd[2]];
@@ -652,8 +689,12 @@ int load_panels(ipm_handle* h, int prec, double shift) {
 
 // Factor K in the requested precision.  FP32: on a non-positive pivot the
 // scaled factor is retried with diagonal shifts 1e-7, 1e-6, ... 1e-3 (the
-// shifted factor only preconditions refinement against the true K).
-int factor_k(ipm_handle* h, int prec, kkt_factor_info* fi, double* ms_acc, int* shifts) {
+// shifted factor only preconditions refinement against the true K) unless
+// allow_shift is false (a problem that may be nonconvex: the failed pivot
+// may reveal an indefinite K, which the FP64 factor decides and the
+// inertia correction treats).
+int factor_k(ipm_handle* h, int prec, kkt_factor_info* fi, double* ms_acc, int* shifts,
+             bool allow_shift = true) {
   double shift = 0.0;
   for (int attempt = 0;; ++attempt) {
     int rc = load_panels(h, prec, shift);
@@ -666,7 +707,7 @@ int factor_k(ipm_handle* h, int prec, kkt_factor_info* fi, double* ms_acc, int* 
     if (rc) return rc;
     rc = factor_now(h, prec, fi);
     if (ms_acc) *ms_acc += fi->ms;
-    if (rc != PDIPM_ERR_NOT_PD || prec == PDIPM_FP64) return rc;
+    if (rc != PDIPM_ERR_NOT_PD || prec == PDIPM_FP64 || !allow_shift) return rc;
     if (attempt >= 5) return rc;
     shift = shift == 0.0 ? 1e-7 : shift * 10.0;
     if (shifts) ++*shifts;
@@ -793,12 +834,18 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
     R.ms_assemble += ms_since(ta);
     kkt_factor_info fi{};
     int shifts = 0;
-    rc = factor_k(h, fprec, &fi, &R.ms_factor, &shifts);
+    rc = factor_k(h, fprec, &fi, &R.ms_factor, &shifts, h->hp.convex);
     if (rc == PDIPM_ERR_NOT_PD && fprec == PDIPM_FP32 && h->need64) {
       fprec = PDIPM_FP64;
       stay64 = true;
       R.fp64_refactors++;
       rc = factor_k(h, fprec, &fi, &R.ms_factor, nullptr);
+    }
+    if (rc == PDIPM_ERR_NOT_PD && h->dual) {
+      // the dual condensed form needs H + Sigma_x + delta_p > 0; the
+      // inertia correction belongs to the primal condensed form
+      status = PDIPM_ERR_NUMERICAL;
+      break;
     }
     if (rc == PDIPM_ERR_NOT_PD) {
       delta_w = delta_w_last == 0.0 ? 1e-4 : std::max(1e-20, delta_w_last / 3.0);
@@ -974,12 +1021,12 @@ void batch_factor(ipm_handle* h, int prec) {
 // Solve with a fixed number of FP64 refinement steps, then flag the running
 // instances whose residual misses their target.
 void batch_solve_fixed(ipm_handle* h, const double* rhs, double* out, int steps) {
-  const int64_t n = h->sym.n;
-  trisolve(h, rhs, out);
+  const int64_t n = h->hp.n;
+  ksolve(h, rhs, out);
   for (int k = 0; k < steps; ++k) {
     kmul(h, out, h->ir_kx);
     launch_residual_norms(n, rhs, h->ir_kx, out, h->ir_r, h->partials, h->stream);
-    trisolve(h, h->ir_r, h->ir_c);
+    ksolve(h, h->ir_r, h->ir_c);
     launch_add(n, out, h->ir_c, h->stream);
   }
   kmul(h, out, h->ir_kx);
@@ -1194,6 +1241,7 @@ void ipm_default_options(ipm_options* o) {
   o->print_level = 0;
   o->fp64_fallback = 1;
   o->use_graphs = 1;
+  o->kkt_form = PDIPM_KKT_PRIMAL;
 }
 
 const char* ipm_status_string(int s) {
@@ -1255,10 +1303,33 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
   }
+  if (h->opt.kkt_form != PDIPM_KKT_PRIMAL && h->opt.kkt_form != PDIPM_KKT_DUAL) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_form must be PDIPM_KKT_PRIMAL or PDIPM_KKT_DUAL");
+  }
   create_lap("start");
   std::string e = build_problem(prob, &h->hp);
   if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
   create_lap("problem copy and patterns");
+  if (h->opt.kkt_form == PDIPM_KKT_DUAL) {
+    if ((int64_t)h->hp.hc.size() != h->hp.n) {
+      delete h;
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, "the dual condensed form needs a diagonal Hessian (Q diagonal or empty)");
+    }
+    if (h->hp.m == 0) {
+      delete h;
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, "the dual condensed form needs at least one constraint row");
+    }
+    h->dual = true;
+    try {
+      build_dual_structures(h->hp, &h->graph, &h->km);
+    } catch (const std::exception& ex) {
+      delete h;
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());
+    }
+    create_lap("graph of M and M map");
+    return finish_create(h, opts, out);
+  }
   try {
     // the graph of K (for the ordering) and the K map (for assembly) both
     // only read the problem: build them on two host threads
@@ -1633,6 +1704,10 @@ int ipm_batch_create(int32_t count, const ipm_problem_desc* probs, const ipm_opt
   if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32) {
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+  }
+  if (h->opt.kkt_form != PDIPM_KKT_PRIMAL) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "batches use the primal condensed form (kkt_form 0)");
   }
   h->bcount = count;
   h->bxoff.assign(count + 1, 0);

@@ -79,10 +79,27 @@ std::string build_problem(const ipm_problem_desc* d, HostProblem* p) {
   }
   if (!p->has_q4) p->q4.clear();
   p->has_w = d->W.rowptr && d->W.rowptr[m] > 0;
+  // convexity that can be certified cheaply: W >= 0 (g concave) and Q
+  // symmetric diagonally dominant with a non-negative diagonal (PSD by
+  // Gershgorin); otherwise the Hessian may be indefinite and the primal
+  // condensed K needs inertia correction
+  p->convex = true;
   if (p->has_w)
     for (int64_t e2 = 0; e2 < d->W.rowptr[m]; ++e2)
-      if (d->W.val[e2] < 0) return "W must be non-negative";
+      if (d->W.val[e2] < 0) p->convex = false;
   bool has_q = d->Q.rowptr && d->Q.rowptr[n] > 0;
+  if (has_q) {
+    std::vector<double> diag(n, 0.0), off(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e2 = d->Q.rowptr[i]; e2 < d->Q.rowptr[i + 1]; ++e2) {
+        const int32_t j = d->Q.colind[e2];
+        const double v = d->Q.val[e2];
+        if (j == i) diag[i] += v;
+        else { off[i] += std::fabs(v); off[j] += std::fabs(v); }
+      }
+    for (int64_t i = 0; i < n; ++i)
+      if (diag[i] < off[i]) p->convex = false;
+  }
   p->kind = (p->has_w || p->has_q4) ? KIND_NLP : (has_q ? KIND_QP : KIND_LP);
   // J union pattern
   p->jp.assign(m + 1, 0);
@@ -333,6 +350,36 @@ void build_kmap_problem(const HostProblem& p, KMap* km) {
     for (int64_t v : q.tend) km->tp.push_back(base + v);
     for (int64_t c : q.ncol) { km->kp[col + 1] = km->kp[col] + c; ++col; }
   }
+}
+
+void build_dual_structures(const HostProblem& p, Graph* g, KMap* km) {
+  // A structural view of the problem whose constraint matrix is J' (its rows
+  // are the columns of J) and whose Hessian is diagonal: the primal builders
+  // then give the pattern of diag + (J')' D (J') = diag + J D J', the dual
+  // condensed matrix, and its assembly triples, with entry indices in J'
+  // order that are mapped back to J's CSR order below.
+  HostProblem t;
+  t.n = p.m;
+  t.m = p.n;
+  t.jp = p.jtp;
+  t.jc = p.jtr;
+  t.jtp = p.jp;
+  t.jtr = p.jc;
+  const int64_t nnz = (int64_t)p.jc.size();
+  t.jte.resize(nnz);
+  for (int64_t q = 0; q < nnz; ++q) t.jte[p.jte[q]] = (int32_t)q;
+  t.hp.resize(p.m + 1);
+  t.hc.resize(p.m);
+  t.hsp.resize(p.m + 1);
+  t.hsc.resize(p.m);
+  t.hss.resize(p.m);
+  for (int64_t k = 0; k <= p.m; ++k) t.hp[k] = t.hsp[k] = k;
+  for (int64_t k = 0; k < p.m; ++k) t.hc[k] = t.hsc[k] = t.hss[k] = (int32_t)k;
+  build_graph_from_problem(t, g);
+  build_kmap_problem(t, km);
+  for (int32_t& h : km->kh) h = -1;                 // M has no Hessian term
+  for (int32_t& a : km->ta) a = p.jte[a];
+  for (int32_t& b : km->tb) b = p.jte[b];
 }
 
 void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km) {

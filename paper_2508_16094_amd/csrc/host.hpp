@@ -18,6 +18,7 @@ struct HostProblem {
   int kind = KIND_LP;
   std::vector<double> c, b, q4, xl, xu;  // q4 empty when absent; bounds +-inf
   bool has_q4 = false, has_w = false;
+  bool convex = true;    // certified convex: W >= 0 and Q diagonally dominant
   // J = A - 2 W diag(x) on the union pattern of A and W (m x n, CSR)
   std::vector<int64_t> jp;
   std::vector<int32_t> jc;
@@ -151,6 +152,10 @@ void build_graph_from_problem(const HostProblem& p, Graph* g);
 void build_graph_from_lower(int64_t n, const int64_t* rp, const int32_t* ci, Graph* g);
 void build_kmap_problem(const HostProblem& p, KMap* km);
 void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km);
+// Graph and assembly map of the dual condensed matrix M = diag + J D J'
+// (m x m; Section 3, eq. kkt_dual): M(e) = [row == col] E_row
+// + sum_t D[tk[t]] J[ta[t]] J[tb[t]], tk a column of J, ta/tb J entries.
+void build_dual_structures(const HostProblem& p, Graph* g, KMap* km);
 // Blocking of the numeric plan: fronts of height <= small_h (at most 64) use
 // the one-workgroup LDS kernel; larger fronts take rank-(outer_blocks * nb)
 // trailing updates.

@@ -213,6 +213,46 @@ __global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc
   out[i] = acc;
 }
 
+// ------------------------------------------- dual condensed system
+// D = (H + Sigma_x + delta_p I)^-1 for a diagonal H and E = Sigma_s^-1
+// (= delta_d + s / lambda): the diagonal scalings of M = diag(E) + J D J'.
+__global__ void k_dual_prep(int64_t n, int64_t m, const double* hv, const int64_t* hdiag,
+                            const double* sig_x, const double* sig_s, double delta_p, double* dd,
+                            double* de) {
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) dd[i] = 1.0 / (hv[hdiag[i]] + sig_x[i] + delta_p);
+  if (i < m) de[i] = 1.0 / sig_s[i];
+}
+
+// out = a o b, and out = d o (r - w): the two diagonal steps of a K solve
+// through M (x = D r - D J' M^-1 J D r).
+__global__ void k_mul_vec(int64_t n, const double* a, const double* b, double* out) {
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+__global__ void k_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out) {
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n) out[i] = d[i] * (r[i] - w[i]);
+}
+
+// max_i K_ii with K_ii = 1/D_i + sum_k Sigma_s[k] J_ki^2 (the norm estimate
+// of K used by the backward error when K itself is never formed)
+__global__ void k_kdiag_max(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
+                            const double* jv, const double* sig_s, const double* dd, double* partials) {
+  RedSpec spec{1, {RED_MAX}};
+  double a[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    double k = 1.0 / dd[i];
+    for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) {
+      const double j = jv[jte[q]];
+      k += sig_s[jtr[q]] * j * j;
+    }
+    a[0] = fmax(a[0], k);
+  }
+  block_reduce_store<1>(a, spec, partials);
+}
+
 // ------------------------------------------------------- factorisation
 // Small fronts (h <= 64): the whole front in LDS; children's update
 // matrices are added in child order, then w columns are eliminated and the
@@ -1678,6 +1718,25 @@ void launch_cg_step(int64_t n, double alpha, const double* p, const double* q, d
 }
 void launch_xpby(int64_t n, const double* z, double beta, double* p, hipStream_t s) {
   k_xpby<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, z, beta, p);
+}
+void launch_dual_prep(const DevProblem& P, const double* hv, const double* sig_x, const double* sig_s,
+                      double delta_p, double* dd, double* de, hipStream_t s) {
+  const int64_t len = P.n > P.m ? P.n : P.m;
+  k_dual_prep<<<(unsigned)blocks_for(len), BS, 0, s>>>(P.n, P.m, hv, P.hdiag, sig_x, sig_s, delta_p, dd, de);
+}
+void launch_mul_vec(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  if (n > 0) k_mul_vec<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, a, b, out);
+}
+void launch_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out,
+                        hipStream_t s) {
+  if (n > 0) k_dual_finish<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, r, w, out);
+}
+void launch_kdiag_max(const DevProblem& P, const double* jv, const double* sig_s, const double* dd,
+                      double* partials, hipStream_t s) {
+  int g = red_grid(P.n);
+  k_kdiag_max<<<g, BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, sig_s, dd, partials);
+  RedSpec spec{1, {RED_MAX}};
+  launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_add(int64_t n, double* x, const double* c, hipStream_t s) {
   k_add<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, x, c);

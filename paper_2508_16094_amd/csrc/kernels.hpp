@@ -59,6 +59,18 @@ void launch_assemble(const DevKMap& K, const double* hv, const double* jv, const
 template <typename T>
 void launch_set_values(const DevKMap& K, const double* kval, T* panel, hipStream_t s);
 
+// dual condensed system M = diag(E) + J D J' (Section 3, eq. kkt_dual):
+// D = (H + Sigma_x + delta_p)^-1 (H diagonal), E = 1 / Sigma_s
+void launch_dual_prep(const DevProblem& P, const double* hv, const double* sig_x, const double* sig_s,
+                      double delta_p, double* dd, double* de, hipStream_t s);
+void launch_mul_vec(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+// out = d o (r - w)
+void launch_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out,
+                        hipStream_t s);
+// max_i (1/D_i + sum_k Sigma_s[k] J_ki^2) into the reduction output
+void launch_kdiag_max(const DevProblem& P, const double* jv, const double* sig_s, const double* dd,
+                      double* partials, hipStream_t s);
+
 // numeric factorisation
 template <typename T>
 void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv, int* bad, hipStream_t s);

@@ -18,6 +18,7 @@ PDIPM_ERR_INVALID_ARG, PDIPM_ERR_OUT_OF_MEMORY, PDIPM_ERR_NOT_PD = -1, -2, -3
 PDIPM_ERR_NUMERICAL, PDIPM_ERR_DEVICE, PDIPM_ERR_NOT_ANALYZED = -4, -5, -6
 PDIPM_FP64, PDIPM_FP32 = 0, 1
 PDIPM_HOST, PDIPM_DEVICE = 0, 1
+PDIPM_KKT_PRIMAL, PDIPM_KKT_DUAL = 0, 1
 
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -38,7 +39,7 @@ class ipm_options(ctypes.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("max_wall_time", _f64), ("delta_p", _f64),
                 ("delta_d", _f64), ("precision", _i32), ("ir_max", _i32), ("ir_tol", _f64),
                 ("nd_leaf", _i32), ("amalg_menu", _i32), ("print_level", _i32),
-                ("fp64_fallback", _i32), ("use_graphs", _i32)]
+                ("fp64_fallback", _i32), ("use_graphs", _i32), ("kkt_form", _i32)]
 
 
 class kkt_symbolic_stats(ctypes.Structure):
@@ -383,17 +384,21 @@ class IpmSolver(_Handle):
     def set_precision(self, precision):
         self._check(lib().ipm_set_precision(self.h, int(precision)), "ipm_set_precision")
 
+    def _start(self, start):
+        if start is None:
+            return None
+        xs, ls = start
+        st = ipm_start()
+        if hasattr(xs, "data_ptr"):
+            st.x, st.lam, st.memspace = _dptr(xs), _dptr(ls), PDIPM_DEVICE
+        else:
+            self._start_keep = (np.ascontiguousarray(xs, np.float64), np.ascontiguousarray(ls, np.float64))
+            st.x, st.lam, st.memspace = _ptr(self._start_keep[0]), _ptr(self._start_keep[1]), PDIPM_HOST
+        return st
+
     def solve(self, start=None):
         res = ipm_result()
-        st = None
-        if start is not None:
-            xs, ls = start
-            st = ipm_start()
-            if hasattr(xs, "data_ptr"):
-                st.x, st.lam, st.memspace = _dptr(xs), _dptr(ls), PDIPM_DEVICE
-            else:
-                self._start_keep = (np.ascontiguousarray(xs, np.float64), np.ascontiguousarray(ls, np.float64))
-                st.x, st.lam, st.memspace = _ptr(self._start_keep[0]), _ptr(self._start_keep[1]), PDIPM_HOST
+        st = self._start(start)
         rc = lib().ipm_solve(self.h, ctypes.byref(st) if st is not None else None, ctypes.byref(res))
         self._check(rc, "ipm_solve")
         return {k: getattr(res, k) for k, _ in res._fields_}

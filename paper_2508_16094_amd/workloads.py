@@ -227,6 +227,24 @@ def nlp_grid(nx: int = 700, ny: int = 700, instance: int = 0) -> Problem:
                    Q=grid_laplacian_lower(nx, ny), name=f"nlp_grid[{nx}x{ny}]")
 
 
+def nlp_grid_nonconvex(nx: int = 40, ny: int = 36, instance: int = 0, neg_frac: float = 0.5,
+                       weight: float = 0.2, c_scale: float = 4.0) -> Problem:
+    """nlp_grid with mixed-sign stencil weights: each W entry is -weight
+    with probability neg_frac, +weight otherwise.  Negative entries make g
+    convex in those terms, the feasible set nonconvex and the Lagrangian
+    Hessian L + diag(3 x^2) + 2 diag(W' lambda) indefinite where W' lambda
+    is negative enough (a nonconvex NLP of the COPS grid shape).  The linear
+    term is scaled by c_scale so that some constraints are active at the
+    solution (with c ~ N(0,1) alone they are not)."""
+    p = nlp_grid(nx, ny, instance)
+    p.c = p.c * c_scale
+    rng = np.random.default_rng(seed_for(3, 500 + instance))
+    sign = np.where(rng.random(p.W.nnz) < neg_frac, -1.0, 1.0)
+    p.W = CSR(p.W.nrows, p.W.ncols, p.W.rowptr, p.W.colind, sign * weight)
+    p.name = f"nlp_grid_nonconvex[{nx}x{ny}]"
+    return p
+
+
 def qp_batch_sizes(count: int = 4096, nmin: int = 50, nmax: int = 2000,
                    seed: Optional[int] = None) -> np.ndarray:
     rng = np.random.default_rng(seed_for(4, 99999) if seed is None else seed)

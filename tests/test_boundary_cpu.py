@@ -145,3 +145,42 @@ def test_host_setup_does_not_depend_on_thread_count(threads, monkeypatch):
     b1 = L.BatchSolver(ps).stats()
     monkeypatch.setenv("PDIPM_HOST_THREADS", str(threads))
     assert L.BatchSolver(ps).stats() == b1
+
+
+@pytest.mark.parametrize("name", ["lp_small", "qp", "lp_block", "lp_block_wide_link"])
+def test_dual_form_symbolic_bit_exact(name):
+    """Dual condensed form: the library orders and analyses M = diag + J D J'
+    (m x m) exactly as the oracle does on the structure of J J'."""
+    p = {"lp_small": lambda: w.lp_small(1),
+         "qp": lambda: w.qp_instance(800, 12),
+         "lp_block": lambda: w.lp_block(nblocks=6, block_rows=300, block_cols=600, link_cols_per_block=30),
+         "lp_block_wide_link": lambda: w.lp_block(nblocks=8, block_rows=120, block_cols=240,
+                                                  link_cols_per_block=40)}[name]()
+    s = L.IpmSolver(p, kkt_form=L.PDIPM_KKT_DUAL)
+    got = s.symbolic()
+    (jrp, jci), _ = s.patterns()
+    ref = osym.analyze(osym.dual_pattern(p.m, p.n, jrp, jci), p.m)
+    for k in ["perm", "etree", "colcount", "sn_start", "sn_rowptr", "sn_rows"]:
+        assert np.array_equal(got[k], ref[k]), k
+    st = s.stats()
+    assert st["n"] == p.m and st["nnz_L"] == ref["nnz_L"] and st["flops"] == ref["flops"]
+    # the pattern of M is the lower structure of J J' with its diagonal
+    rp, ci = s.k_pattern()
+    Jb = sp.csr_matrix((np.ones(len(jci)), jci, jrp), shape=(p.m, p.n))
+    S = sp.tril((Jb @ Jb.T + sp.eye(p.m)).tocsr()).tocsr()
+    S.sort_indices()
+    assert np.array_equal(rp, S.indptr) and np.array_equal(ci, S.indices)
+
+
+def test_dual_form_rejects_what_it_cannot_solve():
+    with pytest.raises(L.PdipmError) as e:
+        L.IpmSolver(w.nlp_grid(10, 10), kkt_form=L.PDIPM_KKT_DUAL)   # Laplacian Hessian
+    assert e.value.code == L.PDIPM_ERR_INVALID_ARG
+    p = w.qp_instance(60, 2)
+    p.m, p.A, p.b = 0, None, np.zeros(0)
+    with pytest.raises(L.PdipmError):
+        L.IpmSolver(p, kkt_form=L.PDIPM_KKT_DUAL)
+    with pytest.raises(L.PdipmError):
+        L.BatchSolver([w.qp_instance(60, 2)], kkt_form=L.PDIPM_KKT_DUAL)
+    with pytest.raises(L.PdipmError):
+        L.IpmSolver(w.lp_small(), kkt_form=2)

@@ -245,3 +245,29 @@ def test_dual_form_invariants_and_same_optimum(maker):
         assert h["min_s"] > 0 and h["min_lam"] > 0 and h["min_z"] > 0
     chk = checker.check(p, r["x"], r["s"], r["lam"], r["zl"], r["zu"])
     assert max(chk["P"], chk["D"], chk["C"]) <= 1e-9
+
+
+def test_nonconvex_grid_reaches_a_local_minimiser():
+    """Nonconvex grid NLP (mixed-sign stencil weights): the oracle needs the
+    inertia correction, ends at a KKT point with active constraints, and
+    that point satisfies the second-order condition of a local minimiser:
+    the Lagrangian Hessian on the null space of the active constraints'
+    gradients is positive definite (strict complementarity holds: every
+    active multiplier is bounded away from zero)."""
+    import scipy.linalg
+    p = w.nlp_grid_nonconvex(20, 20, 0, 0.5, 0.2, 5.0)
+    r = ipm.solve(p, tol=1e-10)
+    assert r["status"] == ipm.OK
+    assert sum(1 for h in r["history"] if h["delta_w"] > 0) > 0
+    chk = checker.check(p, r["x"], r["s"], r["lam"], r["zl"], r["zu"])
+    assert max(chk["P"], chk["D"], chk["C"]) <= 1e-9
+    active = r["lam"] > 1e-6
+    assert active.sum() > 0 and np.min(r["lam"][active]) > 1e-3
+    JA = model.jacobian(p, r["x"]).toarray()[active]
+    Z = scipy.linalg.null_space(JA)
+    Hr = Z.T @ model.hessian(p, r["x"], r["lam"]).toarray() @ Z
+    assert np.min(np.linalg.eigvalsh(0.5 * (Hr + Hr.T))) > 1e-6
+    # and the Hessian itself is indefinite somewhere on the path (at the
+    # start x = 0, lambda = 1), which is why the correction was needed
+    H0 = model.hessian(p, np.zeros(p.n), np.ones(p.m)).toarray()
+    assert np.min(np.linalg.eigvalsh(H0)) < 0
