@@ -33,7 +33,7 @@ def _vertex_enumeration_lp(p):
     return best
 
 
-@pytest.mark.parametrize("form", ["primal", "dual"])
+@pytest.mark.parametrize("form", ["primal", "dual", "augmented"])
 @pytest.mark.parametrize("seed", range(6))
 def test_p1_tiny_lp_vertex_enumeration(seed, form):
     n, m = 4 + seed % 3, 3 + seed % 4
@@ -83,7 +83,7 @@ def test_p2_separable_box_qp_closed_form(seed):
     assert np.max(np.abs(r["x"] - x_star)) <= 1e-6
 
 
-@pytest.mark.parametrize("form", ["primal", "dual"])
+@pytest.mark.parametrize("form", ["primal", "dual", "augmented"])
 @pytest.mark.parametrize("seed", range(4))
 def test_p2_one_constraint_qp_bisection(seed, form):
     p, q = _box_qp(15, 200 + seed, True)
@@ -271,3 +271,26 @@ def test_nonconvex_grid_reaches_a_local_minimiser():
     # start x = 0, lambda = 1), which is why the correction was needed
     H0 = model.hessian(p, np.zeros(p.n), np.ones(p.m)).toarray()
     assert np.min(np.linalg.eigvalsh(H0)) < 0
+
+
+@pytest.mark.parametrize("maker", [lambda: w.nlp_grid(24, 20), lambda: w.qp_param(12, 15).base,
+                                   lambda: w.lp_block(nblocks=3, block_rows=150, block_cols=300,
+                                                      link_cols_per_block=10)])
+def test_augmented_form_same_optimum(maker):
+    """The augmented SQD form reaches the primal form's optimum (NLP and a
+    QP with a non-diagonal Hessian included) with interior iterates."""
+    p = maker()
+    r = ipm.solve(p, tol=1e-9, form="augmented")
+    ref = ipm.solve(p, tol=1e-9)
+    assert r["status"] == ipm.OK and ref["status"] == ipm.OK
+    assert abs(r["f"] - ref["f"]) <= 1e-7 * max(1.0, abs(ref["f"]))
+    for h in r["history"]:
+        assert h["min_lam"] > 0 and h["min_s"] > 0
+
+
+def test_augmented_form_stops_on_an_indefinite_hessian():
+    """A nonconvex Hessian breaks the SQD structure: a pivot takes the wrong
+    sign and the augmented form ends with NUMERICAL (the paper's reason to
+    use the primal condensed form with inertia correction there)."""
+    r = ipm.solve(w.nlp_grid_nonconvex(20, 20, 0, 0.5, 0.2, 5.0), tol=1e-9, form="augmented")
+    assert r["status"] == ipm.NUMERICAL

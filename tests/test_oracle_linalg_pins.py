@@ -236,3 +236,88 @@ def test_dual_pattern_is_the_structure_of_j_jt(seed):
     S = (B @ B.T) > 0
     for v in range(p.m):
         assert adj[v] == [u for u in range(p.m) if S[v, u] and u != v]
+
+
+def _augmented_step(p, x, s, lam, zl, zu, t_s, t_l, t_u, dp, dd):
+    """Step through the augmented SQD system (eq. augmentedKKT), factored by
+    the oracle's signed LDL' under its symbolic ordering."""
+    xl, xu = model.bounds(p)
+    il, iu = np.isfinite(xl), np.isfinite(xu)
+    J = model.jacobian(p, x).tocsr(); H = model.hessian(p, x, lam)
+    gf = model.gradient(p, x); g = model.constraints(p, x)
+    r_d = gf - J.T @ lam - zl + zu
+    _, sig_x = kkt.sigmas(x, s, lam, zl, zu, xl, xu, il, iu, dd)
+    A = kkt.augmented_matrix(H, J, s, lam, sig_x, dp, dd)
+    Hl = sp.tril(H).tocsr()
+    sym = symbolic.analyze(symbolic.augmented_pattern(p.n, p.m, J.indptr, J.indices, Hl.indptr, Hl.indices),
+                           p.n + p.m)
+    F = chol.SparseFactor(sym["perm"], sym["structs"]).factor_ldlt(A)
+    rt = kkt.reduced_dual_residual(r_d, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+    dx, dlam = kkt.augmented_split(F.solve_ldlt(kkt.augmented_rhs(rt, g, lam, t_s)), p.n)
+    ds = J @ dx + (g - s) + dd * dlam
+    dzl, dzu = kkt.bound_steps(dx, x, zl, zu, xl, xu, il, iu, t_l, t_u)
+    return dx, ds, dlam, dzl, dzu
+
+
+@pytest.mark.parametrize("which", ["lp", "qp", "nlp", "halfbounds"])
+def test_p5_augmented_equals_full_kkt(which):
+    """eq. augmentedKKT through a signed LDL': the step equals the Newton
+    step of the full regularised system (dense partial-pivot LU)."""
+    rng = np.random.default_rng(9)
+    if which == "lp":
+        p = w.random_lp(12, 7, 3, 11)
+    elif which == "qp":
+        p = w.qp_instance(14, 3)
+    elif which == "nlp":
+        p = w.nlp_grid(4, 4)
+    else:
+        p = w.random_lp(10, 6, 3, 12)
+        p.xl = np.where(np.arange(10) % 3 == 0, -np.inf, 0.0)
+        p.xu = np.where(np.arange(10) % 3 == 1, np.inf, 10.0)
+    pt = _random_point(p, rng)
+    for dp, dd in [(1e-8, 1e-8), (0.3, 0.2)]:
+        a = _full_kkt_step(p, *pt, dp, dd)
+        b = _augmented_step(p, *pt, dp, dd)
+        for u, v in zip(a, b):
+            assert np.max(np.abs(u - v)) <= 1e-9 * max(1.0, np.max(np.abs(u)))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sqd_strong_factorisability_and_pivot_signs(seed):
+    """Section 2: an SQD matrix [E A'; A -F] (E, F SPD) has P'KP = LDL' for
+    every permutation P, and each pivot carries the sign of its block
+    (positive for E's variables, negative for F's): inertia (n, m, 0).
+    Checked under random permutations with the oracle's LDL' (dense
+    structure, so any order is a valid symbolic structure); the factor
+    reproduces P'KP to 1e-12."""
+    rng = np.random.default_rng(seed)
+    n, m = 9 + seed, 6 + seed
+    Bn = rng.standard_normal((n, n)); E = Bn @ Bn.T / n + 0.1 * np.eye(n)
+    Bm = rng.standard_normal((m, m)); F = Bm @ Bm.T / m + 0.1 * np.eye(m)
+    A = rng.standard_normal((m, n))
+    K = np.block([[E, A.T], [A, -F]])
+    N = n + m
+    structs = [np.arange(j + 1, N) for j in range(N)]
+    sign = np.concatenate([np.ones(n), -np.ones(m)])
+    for _ in range(6):
+        perm = rng.permutation(N)
+        Fc = chol.SparseFactor(perm, structs).factor_ldlt(sp.csr_matrix(K))
+        assert np.array_equal(np.sign(Fc.D), sign[perm])
+        Ld = Fc.to_dense()
+        Kp = K[np.ix_(perm, perm)]
+        assert np.linalg.norm(Kp - Ld @ np.diag(Fc.D) @ Ld.T) / np.linalg.norm(Kp) <= 1e-12
+        b = rng.standard_normal(N)
+        assert np.max(np.abs(K @ Fc.solve_ldlt(b) - b)) <= 1e-10 * np.max(np.abs(b)) * np.linalg.cond(K)
+
+
+def test_augmented_pattern_is_the_structure_of_the_block_matrix():
+    p = w.nlp_grid(5, 4)
+    x = np.linspace(0.1, 0.9, p.n)
+    J = model.jacobian(p, x).tocsr()
+    Hl = sp.tril(model.hessian(p, x, np.ones(p.m))).tocsr()
+    adj = symbolic.augmented_pattern(p.n, p.m, J.indptr, J.indices, Hl.indptr, Hl.indices)
+    Jd = J.toarray() != 0
+    Hd = (Hl + Hl.T).toarray() != 0
+    S = np.block([[Hd, Jd.T], [Jd, np.zeros((p.m, p.m), bool)]])
+    for v in range(p.n + p.m):
+        assert adj[v] == [u for u in range(p.n + p.m) if S[v, u] and u != v]
