@@ -153,7 +153,7 @@ def bench_warm(args, log):
     t = time.time()
     pb = warm.ParamBatch(pq, chunk=args.chunk)
     log(f"[bench] parametric QP n={n} m={m}: batch of {args.chunk} analysed and bound in {time.time() - t:.1f}s")
-    res, X, Lm, t_train_solve = pb.solve(th_train)
+    res, X, Lm, t_train_solve = pb.solve(th_train, log=log)
     ok_train = sum(r["status"] == 0 for r in res)
     log(f"[bench] training set: {ok_train}/{len(res)} solved in {t_train_solve:.1f}s")
     keep = np.array([r["status"] == 0 for r in res])
@@ -167,16 +167,18 @@ def bench_warm(args, log):
     torch.cuda.synchronize()
     t_train = time.time() - t
     train_tf = model.flops(args.mlp_batch, 1) * args.mlp_steps / t_train / 1e12
-    cold, _, _, t_cold = pb.solve(th_test)
+    cold, _, _, t_cold = pb.solve(th_test, log=log)
     torch.cuda.synchronize()
     t0 = time.time()
     xh, lh = warm.predict(model, th_test)
     torch.cuda.synchronize()
     t_inf = time.time() - t0
-    wres, _, _, t_warm = pb.solve(th_test, starts=(xh, lh))
+    wres, _, _, t_warm = pb.solve(th_test, starts=(xh, lh), log=log)
     ic = np.array([r["iterations"] for r in cold])
     iw = np.array([r["iterations"] for r in wres])
     fails = int(sum(r["status"] != 0 for r in wres))
+    fallbacks = int(sum(1 for r in wres if r.get("fallback")))
+    f_diff = max(abs(a["f"] - b["f"]) / max(1.0, abs(b["f"])) for a, b in zip(wres, cold))
     value = len(th_test) / (t_warm + t_inf)
     out = {
         "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
@@ -192,7 +194,7 @@ def bench_warm(args, log):
                  "iterations_p95": float(np.percentile(ic, 95))},
         "warm": {"solves_per_s": value, "iterations_mean": float(iw.mean()),
                  "iterations_p95": float(np.percentile(iw, 95)), "inference_s": t_inf,
-                 "failures": fails},
+                 "failures": fails, "cold_fallbacks": fallbacks, "max_rel_f_diff_vs_cold": f_diff},
         "training": {"instances": int(keep.sum()), "solve_s": t_train_solve, "mlp_steps": args.mlp_steps,
                      "mlp_batch": args.mlp_batch, "mlp_s": t_train, "loss_first": losses[0][1],
                      "loss_last": losses[-1][1]},

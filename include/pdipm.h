@@ -58,6 +58,10 @@ extern "C" {
 
 #define PDIPM_KKT_PRIMAL 0        /* primal condensed K (Section 3, eq. kkt_primal) */
 #define PDIPM_KKT_DUAL 1          /* dual condensed M (Section 3, eq. kkt_dual) */
+#define PDIPM_KKT_AUGMENTED 2     /* augmented SQD system (Section 3, eq. augmentedKKT) */
+
+#define PDIPM_ORDER_LEVELS 0      /* nested dissection, separators = BFS levels */
+#define PDIPM_ORDER_MULTILEVEL 1  /* nested dissection, separators from multilevel bisection */
 
 typedef struct pdipm_csr {
   int64_t nrows, ncols;
@@ -109,7 +113,29 @@ typedef struct ipm_options {
                             empty) and m >= 1; a non-positive pivot ends
                             ipm_solve with PDIPM_ERR_NUMERICAL (no inertia
                             correction).  The symbolic, pattern, value and
-                            factor calls then describe M. */
+                            factor calls then describe M.
+                            PDIPM_KKT_AUGMENTED: factor the augmented matrix
+                            [H + diag(Sigma_x + delta_p), J'; J, -1/Sigma_s]
+                            (order n + m, x first; Section 3, eq.
+                            augmentedKKT), symmetric quasi-definite for convex
+                            problems, as P'AP = L S L' with S = +1 on x
+                            pivots and -1 on lambda pivots (Section 2: strong
+                            factorisability, no pivoting), and solve K d = r
+                            from A (d, w) = (r, 0), refined against K.  A
+                            pivot of the wrong sign (a nonconvex H) ends
+                            ipm_solve with PDIPM_ERR_NUMERICAL.  The factor
+                            calls then describe A; kkt_get_factor gives L. */
+  int32_t ordering;      /* fill-reducing ordering, computed once on the host
+                            (Section 2: minimum degree or nested dissection):
+                            PDIPM_ORDER_LEVELS (default) takes BFS level sets
+                            as separators; PDIPM_ORDER_MULTILEVEL bisects each
+                            component the multilevel way (heavy-edge matching
+                            down to 64 vertices, a BFS-grown bisection, greedy
+                            boundary refinement on every level, parts of at
+                            most 11/20 of the weight) and separates by the
+                            smaller boundary side.  Both end in exact minimum
+                            degree on components of at most nd_leaf vertices
+                            and are deterministic. */
 } ipm_options;
 
 typedef struct kkt_symbolic_stats {

@@ -85,6 +85,36 @@ def gradients(params, X, target, n_x, x_scale=10.0, x_weight=1.0):
     return loss, backward(params, hs, dz)
 
 
+def gradient_magnitudes(params, X, target, n_x, x_scale=10.0, x_weight=1.0, band=2.0 ** -6):
+    """For every gradient entry, the sum of the absolute values of the terms
+    that make it up (|dL/dz|' |h| propagated back with |W|), the scale
+    against which a lower-precision evaluation is judged entry by entry.
+    A unit counts as active, and its activation as max(pre + band * |pre|_1, 0),
+    when its pre-activation lies within band times the sum of the absolute
+    values of its own terms (|W| |h| + |b|) above zero, so that units a
+    rounded evaluation may see on either side of the ReLU are included."""
+    hs, relaxed = [np.asarray(X, np.float64)], [np.abs(np.asarray(X, np.float64))]
+    keeps = []
+    for W, b in params[:-1]:
+        pre = hs[-1] @ W.T + b
+        scale = relaxed[-1] @ np.abs(W).T + np.abs(b)
+        keep = pre + band * scale > 0
+        keeps.append(keep)
+        hs.append(np.maximum(pre, 0.0))
+        relaxed.append(np.where(keep, np.abs(pre) + band * scale, 0.0))
+    W, b = params[-1]
+    z = hs[-1] @ W.T + b
+    _, dz = loss_and_dz(z, target, n_x, x_scale, x_weight)
+    mags = [None] * len(params)
+    d = np.abs(dz)
+    for l in range(len(params) - 1, -1, -1):
+        Wl, _ = params[l]
+        mags[l] = (d.T @ relaxed[l], d.sum(axis=0))
+        if l > 0:
+            d = (d @ np.abs(Wl)) * keeps[l - 1]
+    return mags
+
+
 class Adam:
     """Adam with bias correction (beta1, beta2, eps as in the usual setting)."""
 

@@ -195,13 +195,188 @@ def _choose_separator(levels):
     return best[3]
 
 
+# ------------------------------------------- multilevel bisection (ORD-ML)
+# Multilevel graph bisection in the style of METIS (Karypis and Kumar):
+# coarsen by heavy-edge matching, bisect the coarsest graph, refine the
+# partition on every level on the way back, then take a vertex separator
+# from the edge cut.  Every step is deterministic (ties by smallest index).
+ML_COARSEN_TO = 64          # stop coarsening at this many vertices ...
+ML_SHRINK_NUM, ML_SHRINK_DEN = 9, 10   # ... or when a level keeps > 9/10 of them
+ML_PASSES = 8               # refinement passes per level
+ML_BAL_NUM, ML_BAL_DEN = 11, 20        # a part may hold at most 11/20 of the weight
+
+
+def _ml_local_graph(adj, comp, inset):
+    """G[comp] with local ids (positions in the sorted comp), unit weights."""
+    idx = {v: i for i, v in enumerate(comp)}
+    nbrs = [[idx[w] for w in adj[v] if inset[w]] for v in comp]
+    return nbrs, [[1] * len(r) for r in nbrs], [1] * len(comp)
+
+
+def _ml_coarsen(nbrs, ew, vw):
+    """Heavy-edge matching: vertices in increasing index; an unmatched v
+    takes the unmatched neighbour of largest edge weight (ties: smaller
+    vertex weight, then smaller index), or stays alone.  Coarse vertices are
+    numbered in the order their first member is visited; parallel edges add
+    their weights, vertex weights add."""
+    n = len(vw)
+    matched = [False] * n
+    cmap = [-1] * n
+    groups = []
+    for v in range(n):
+        if matched[v]:
+            continue
+        best, bkey = -1, None
+        for u, w in zip(nbrs[v], ew[v]):
+            if matched[u]:
+                continue
+            key = (-w, vw[u], u)
+            if best < 0 or key < bkey:
+                best, bkey = u, key
+        matched[v] = True
+        cmap[v] = len(groups)
+        if best >= 0:
+            matched[best] = True
+            cmap[best] = len(groups)
+            groups.append((v, best))
+        else:
+            groups.append((v,))
+    cn, ce, cw = [], [], []
+    for c, g in enumerate(groups):
+        acc = {}
+        for v in g:
+            for u, w in zip(nbrs[v], ew[v]):
+                if cmap[u] != c:
+                    acc[cmap[u]] = acc.get(cmap[u], 0) + w
+        keys = sorted(acc)
+        cn.append(keys)
+        ce.append([acc[k] for k in keys])
+        cw.append(sum(vw[v] for v in g))
+    return cmap, cn, ce, cw
+
+
+def _ml_bfs_levels(nbrs, root):
+    levels = [[root]]
+    seen = {root}
+    while True:
+        nxt = []
+        for u in levels[-1]:
+            for w in nbrs[u]:
+                if w not in seen:
+                    seen.add(w)
+                    nxt.append(w)
+        if not nxt:
+            return levels
+        levels.append(nxt)
+
+
+def _ml_initial(nbrs, vw):
+    """Part 0 = the shortest prefix of a BFS order from a pseudo-peripheral
+    vertex whose weight reaches half the total; the rest is part 1."""
+    n = len(vw)
+    total = sum(vw)
+    deg = [len(r) for r in nbrs]
+    r = min(range(n), key=lambda v: (deg[v], v))
+    levels = _ml_bfs_levels(nbrs, r)
+    while True:
+        v = min(levels[-1], key=lambda u: (deg[u], u))
+        lv = _ml_bfs_levels(nbrs, v)
+        if len(lv) > len(levels):
+            levels = lv
+        else:
+            break
+    part = [1] * n
+    w0 = 0
+    for v in (u for L in levels for u in L):
+        if 2 * w0 >= total:
+            break
+        part[v] = 0
+        w0 += vw[v]
+    return part
+
+
+def _ml_refine(nbrs, ew, vw, part):
+    """Greedy boundary refinement: each pass visits the boundary vertices in
+    order of decreasing gain (cut edge weight removed by moving; ties by
+    index), with gains kept current, and moves a vertex when its gain is
+    positive and the target part stays within the balance bound, or when its
+    gain is zero and the move strictly narrows the weight difference.  Passes
+    repeat until none moves (at most ML_PASSES)."""
+    n = len(vw)
+    total = sum(vw)
+    maxw = ML_BAL_NUM * total // ML_BAL_DEN
+    pw = [0, 0]
+    for v in range(n):
+        pw[part[v]] += vw[v]
+    ext, inn = [0] * n, [0] * n
+    for v in range(n):
+        for u, w in zip(nbrs[v], ew[v]):
+            if part[u] == part[v]:
+                inn[v] += w
+            else:
+                ext[v] += w
+    for _ in range(ML_PASSES):
+        cands = sorted((v for v in range(n) if ext[v] > 0), key=lambda v: (inn[v] - ext[v], v))
+        moved = False
+        for v in cands:
+            gain = ext[v] - inn[v]
+            src, dst = part[v], 1 - part[v]
+            if not ((gain > 0 and pw[dst] + vw[v] <= maxw) or (gain == 0 and pw[src] > pw[dst] + vw[v])):
+                continue
+            part[v] = dst
+            pw[src] -= vw[v]
+            pw[dst] += vw[v]
+            ext[v], inn[v] = inn[v], ext[v]
+            for u, w in zip(nbrs[v], ew[v]):
+                if part[u] == dst:
+                    inn[u] += w
+                    ext[u] -= w
+                else:
+                    ext[u] += w
+                    inn[u] -= w
+            moved = True
+        if not moved:
+            break
+    return part
+
+
+def multilevel_separator(adj, comp, inset):
+    """(lower, upper, separator) of the connected component comp (sorted),
+    or None when the bisection leaves a side empty.  The separator is the
+    smaller of the two boundary sets of the refined edge bisection (ties:
+    part 0's); lower = part 0 without it, upper = part 1 without it."""
+    graphs = [_ml_local_graph(adj, comp, inset)]
+    cmaps = []
+    while len(graphs[-1][2]) > ML_COARSEN_TO:
+        cmap, cn, ce, cw = _ml_coarsen(*graphs[-1])
+        if len(cw) * ML_SHRINK_DEN > ML_SHRINK_NUM * len(graphs[-1][2]):
+            break
+        cmaps.append(cmap)
+        graphs.append((cn, ce, cw))
+    part = _ml_refine(*graphs[-1], _ml_initial(graphs[-1][0], graphs[-1][2]))
+    for lvl in range(len(cmaps) - 1, -1, -1):
+        part = _ml_refine(*graphs[lvl], [part[c] for c in cmaps[lvl]])
+    nbrs = graphs[0][0]
+    bnd = [[v for v in range(len(comp)) if part[v] == p and any(part[u] != p for u in nbrs[v])]
+           for p in (0, 1)]
+    sep = set(bnd[0] if len(bnd[0]) <= len(bnd[1]) else bnd[1])
+    lower = [comp[v] for v in range(len(comp)) if part[v] == 0 and v not in sep]
+    upper = [comp[v] for v in range(len(comp)) if part[v] == 1 and v not in sep]
+    if not lower or not upper:
+        return None
+    return lower, upper, [comp[v] for v in sorted(sep)]
+
+
 def _degree_order(adj, comp, inset):
     deg = {v: sum(1 for u in adj[v] if inset[u]) for v in comp}
     return sorted(comp, key=lambda v: (deg[v], v))
 
 
-def nested_dissection(adj, n, leaf=ND_LEAF):
-    """ND order as a list: entry k = vertex placed at position k."""
+def nested_dissection(adj, n, leaf=ND_LEAF, method="levels"):
+    """ND order as a list: entry k = vertex placed at position k.  method
+    "levels": separators are BFS levels (ORD); "multilevel": separators from
+    multilevel bisection (ORD-ML), the level rule where that leaves a side
+    empty."""
     out = []
     inset = [False] * n
     # work stack of ("order", vertex list) or ("emit", vertex list)
@@ -224,20 +399,25 @@ def nested_dissection(adj, n, leaf=ND_LEAF):
             if h < 2:
                 tasks.append(("emit", _degree_order(adj, comp, inset)))
                 continue
-            l = _choose_separator(levels)
-            lower = [v for L in levels[:l] for v in L]
-            upper = [v for L in levels[l + 1:] for v in L]
-            for v in levels[l]:
+            ml = multilevel_separator(adj, comp, inset) if method == "multilevel" else None
+            if ml is not None:
+                lower, upper, sep = ml
+            else:
+                l = _choose_separator(levels)
+                lower = [v for L in levels[:l] for v in L]
+                upper = [v for L in levels[l + 1:] for v in L]
+                sep = levels[l]
+            for v in sep:
                 inset[v] = False
             biggest = max(len(c) for c in _components(adj, lower + upper, inset))
-            for v in levels[l]:
+            for v in sep:
                 inset[v] = True
             if 8 * biggest > 7 * len(comp):
                 tasks.append(("emit", _degree_order(adj, comp, inset)))
                 continue
             tasks.append(("order", sorted(lower)))
             tasks.append(("order", sorted(upper)))
-            tasks.append(("emit", sorted(levels[l])))
+            tasks.append(("emit", sorted(sep)))
         for v in verts:
             inset[v] = False
         for t in reversed(tasks):
@@ -348,11 +528,12 @@ def amalgamate(starts, parent, cc, menu=AMALGAMATION_MENU[0]):
     return [a for a, _ in sns] + [n]
 
 
-def analyze(adj, n, leaf=ND_LEAF, menu=AMALGAMATION_MENU[0]):
+def analyze(adj, n, leaf=ND_LEAF, menu=AMALGAMATION_MENU[0], method="levels"):
     """Full symbolic analysis.  Returns a dict with perm (perm[k] = original
     index at position k), etree, colcount, sn_start, sn_rowptr, sn_rows,
-    nnz_L (true) and flops = sum_j (c_j^2 - 1)."""
-    nd = nested_dissection(adj, n, leaf)
+    nnz_L (true) and flops = sum_j (c_j^2 - 1).  method selects the
+    separators of the nested dissection ("levels" or "multilevel")."""
+    nd = nested_dissection(adj, n, leaf, method)
     cols = permuted_lower_columns(adj, nd)
     _, par0 = symbolic_factor(cols)
     post = postorder(par0)

@@ -60,6 +60,8 @@ struct ipm_handle {
   ipm_options opt{};
   bool standalone = false;
   bool dual = false;            // steps through the dual condensed system M
+  bool aug = false;             // steps through the augmented SQD system (signed L S L')
+  std::vector<signed char> psign;  // pivot signs, permuted numbering (augmented form)
   HostProblem hp;
   Graph graph;
   Symbolic sym;
@@ -81,7 +83,8 @@ struct ipm_handle {
     size_t gemm64, potrf64, gemm32, potrf32, ext, small;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
     size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
-    size_t vec[53];
+    size_t vec[55];
+    size_t sign;
   } o{};
   DevProblem dp{};
   DevPlan dpl64{}, dpl32{};
@@ -105,6 +108,7 @@ struct ipm_handle {
   double *dxa, *dsa, *dla, *dzla, *dzua, *dx, *ds, *dl, *dzl, *dzu, *ts, *tl, *tu, *rhs, *ir_r, *ir_c,
       *ir_kx, *xhat, *lamhat, *cg_p;
   double *dual_d = nullptr, *dual_e = nullptr, *dual_tn = nullptr, *dual_tm = nullptr;
+  double *aug_in = nullptr, *aug_out = nullptr;
   // factor state
   int assembled_prec = -1, factor_prec = -1;
   bool values_set = false, factored = false;
@@ -280,9 +284,11 @@ void layout(ipm_handle* h) {
       mv, nv, nv, nv,              // 39 ts, 40 tl, 41 tu, 42 rhs
       nv, nv, nv, nv, mv,          // 43 ir_r, 44 ir_c, 45 ir_kx, 46 xhat, 47 lamhat
       nv,                          // 48 cg direction
-      nv, mv, nv, mv};             // 49 D, 50 E, 51..52 dual solve temporaries
+      nv, mv, nv, mv,              // 49 D, 50 E, 51..52 dual solve temporaries
+      std::max<int64_t>(n, 1), std::max<int64_t>(n, 1)};  // 53..54 augmented solve vectors
   static_assert(sizeof(sizes) / sizeof(sizes[0]) == sizeof(o.vec) / sizeof(o.vec[0]), "vector table");
-  for (int i = 0; i < 53; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+  for (int i = 0; i < 55; ++i) o.vec[i] = r.take((size_t)sizes[i] * 8);
+  o.sign = r.take(std::max<size_t>(1, h->psign.size()));
   if (h->bcount > 0) {
     auto& b = h->bo;
     b.xoff = r.take(bytes_of(h->bxoff)); b.roff = r.take(bytes_of(h->broff));
@@ -336,6 +342,7 @@ int bind_workspace(ipm_handle* h) {
   UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(sld, P.sld); UP(cptr, P.child_ptr); UP(child, P.child);
   UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
   UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv);
+  if (!h->psign.empty()) UP(sign, h->psign);
   int rcp = upload_plans(h);
   if (rcp) return rcp;
   if (h->bcount > 0) {
@@ -369,6 +376,7 @@ int bind_workspace(ipm_handle* h) {
   }
   DevKMap& k = h->dk;
   k.nk = (int64_t)h->km.kc.size();
+  k.npos = h->aug ? p.n : INT64_MAX;
   k.krow = at<int32_t>(h, o.kmrow); k.kc = at<int32_t>(h, o.kmc); k.pos = at<int64_t>(h, o.kmpos);
   if (!h->standalone) {
     k.kh = at<int32_t>(h, o.kmh); k.tp = at<int64_t>(h, o.kmtp); k.tk = at<int32_t>(h, o.kmtk);
@@ -390,6 +398,7 @@ int bind_workspace(ipm_handle* h) {
     q.ssmall = at<int32_t>(h, prec == 0 ? o.ssmall64 : o.ssmall32);
     q.slarge = at<int32_t>(h, prec == 0 ? o.slarge64 : o.slarge32);
     q.sinv = at<int64_t>(h, prec == 0 ? o.sinv64 : o.sinv32);
+    q.sign = h->psign.empty() ? nullptr : at<signed char>(h, o.sign);
   }
   h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;
   h->bad = at<int>(h, o.bad); h->partials = at<double>(h, o.partials);
@@ -397,8 +406,8 @@ int bind_workspace(ipm_handle* h) {
   h->dscale = at<double>(h, o.dscale);
   h->ysol = at<double>(h, o.ysol);
   h->part = at<double>(h, o.part);
-  double* V[53];
-  for (int i = 0; i < 53; ++i) V[i] = at<double>(h, o.vec[i]);
+  double* V[55];
+  for (int i = 0; i < 55; ++i) V[i] = at<double>(h, o.vec[i]);
   IpmVecs& v = h->v;
   v.x = V[0]; v.s = V[1]; v.lam = V[2]; v.zl = V[3]; v.zu = V[4]; v.gf = V[5]; v.qx = V[6]; v.g = V[7];
   v.jv = V[8]; v.hv = V[9]; v.rd = V[10]; v.rp = V[11]; v.sig_s = V[12]; v.sig_x = V[13];
@@ -413,6 +422,7 @@ int bind_workspace(ipm_handle* h) {
   h->ir_r = V[43]; h->ir_c = V[44]; h->ir_kx = V[45]; h->xhat = V[46]; h->lamhat = V[47];
   h->cg_p = V[48];
   h->dual_d = V[49]; h->dual_e = V[50]; h->dual_tn = V[51]; h->dual_tm = V[52];
+  h->aug_in = V[53]; h->aug_out = V[54];
   h->ws_ready = true;
   h->assembled_prec = h->factor_prec = -1;
   h->factored = h->values_set = false;
@@ -526,6 +536,8 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
   }
   launch_permute_in(D, rhs, d, h->xperm, h->stream);
   for (const std::vector<Op>* ops : {&P.fwd_ops, &P.bwd_ops}) {
+    // L S L' (signed factor): between L y = b and L' x = z comes z = S y
+    if (ops == &P.bwd_ops && D.sign) launch_sign_scale(D.n, D.sign, h->ysol, h->stream);
     for (const Op& op : *ops) {
       if (prec == PDIPM_FP64)
         launch_solve_op<double>(op, D, (const double*)h->panel, (const double*)h->inv, h->xperm, h->ysol,
@@ -543,6 +555,16 @@ void trisolve(ipm_handle* h, const double* rhs, double* out) {
 // is of M = diag(E) + J D J', and K^-1 = D - D J' M^-1 J D, so
 // x = D (rhs - J' M^-1 J D rhs).
 void ksolve(ipm_handle* h, const double* rhs, double* out) {
+  if (h->aug) {
+    // augmented form (Section 3, eq. augmentedKKT): [H' J'; J -1/Sigma_s] (x, w)
+    // = (rhs, 0) gives w = Sigma_s J x and (H' + J' Sigma_s J) x = rhs
+    const int64_t n = h->dp.n, m = h->dp.m;
+    launch_copy(n, h->aug_in, rhs, h->stream);
+    if (m > 0) launch_fill_f64(h->aug_in + n, m, 0.0, h->stream);
+    trisolve(h, h->aug_in, h->aug_out);
+    launch_copy(n, out, h->aug_out, h->stream);
+    return;
+  }
   if (!h->dual) { trisolve(h, rhs, out); return; }
   const DevProblem& P = h->dp;
   launch_mul_vec(P.n, h->dual_d, rhs, h->dual_tn, h->stream);
@@ -639,7 +661,11 @@ int solve_refined(ipm_handle* h, const double* rhs, double* out, kkt_solve_info*
 // D = (H + Sigma_x + delta_p)^-1 (the assembly map of M has no Hessian term;
 // its triples scale by D and its diagonal adds E = 1 / Sigma_s).
 void assemble_values(ipm_handle* h, double delta_p) {
-  if (h->dual) {
+  if (h->aug) {
+    launch_assemble_aug(h->dk, h->dp.n, h->v.hv, h->v.jv, h->v.sig_s, h->v.sig_x, delta_p, h->kval, h->stream);
+    // diagonal part of K's (1,1) block, for the norm estimate of K
+    launch_dual_prep(h->dp, h->v.hv, h->v.sig_x, h->v.sig_s, delta_p, h->dual_d, h->dual_e, h->stream);
+  } else if (h->dual) {
     launch_dual_prep(h->dp, h->v.hv, h->v.sig_x, h->v.sig_s, delta_p, h->dual_d, h->dual_e, h->stream);
     launch_assemble<double>(h->dk, h->v.hv, h->v.jv, h->dual_d, h->dual_e, 0.0, nullptr, h->kval, h->stream);
   } else {
@@ -655,12 +681,12 @@ int load_panels(ipm_handle* h, int prec, double shift) {
   if (prec == PDIPM_FP32 && !h->need32) return fail(h, PDIPM_ERR_INVALID_ARG, "workspace has no FP32 plan");
   const size_t es = prec == PDIPM_FP64 ? 8 : 4;
   launch_fill_bytes0(h->panel, (int64_t)h->plan64.panel_elems * es, h->stream);
-  launch_diag_scale(h->sym.n, at<int64_t>(h, h->o.kmkp), h->kval, h->dscale, h->partials, h->stream);
+  launch_diag_scale(h->sym.n, at<int64_t>(h, h->o.kmkp), h->kval, h->dscale, h->partials, h->stream, h->dk.npos);
   double dd[3];
   int rc = read_back(h, red_out(h), dd, 3);
   if (rc) return rc;
   h->kmax = dd[0] > 0 ? dd[0] : 1.0;
-  if (h->dual && dd[1] == 0) {
+  if ((h->dual || h->aug) && dd[1] == 0) {
     // the backward error refers to K, whose largest diagonal entry is
     // formed from D, Sigma_s and J
     launch_kdiag_max(h->dp, h->v.jv, h->v.sig_s, h->dual_d, h->partials, h->stream);
@@ -841,9 +867,10 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
       R.fp64_refactors++;
       rc = factor_k(h, fprec, &fi, &R.ms_factor, nullptr);
     }
-    if (rc == PDIPM_ERR_NOT_PD && h->dual) {
-      // the dual condensed form needs H + Sigma_x + delta_p > 0; the
-      // inertia correction belongs to the primal condensed form
+    if (rc == PDIPM_ERR_NOT_PD && (h->dual || h->aug)) {
+      // the dual condensed form needs H + Sigma_x + delta_p > 0 and the
+      // augmented one an SQD matrix; the inertia correction belongs to the
+      // primal condensed form
       status = PDIPM_ERR_NUMERICAL;
       break;
     }
@@ -1242,6 +1269,7 @@ void ipm_default_options(ipm_options* o) {
   o->fp64_fallback = 1;
   o->use_graphs = 1;
   o->kkt_form = PDIPM_KKT_PRIMAL;
+  o->ordering = PDIPM_ORDER_LEVELS;
 }
 
 const char* ipm_status_string(int s) {
@@ -1273,11 +1301,20 @@ static void create_lap(const char* what) {
 }
 
 static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** out) {
+  if (h->opt.ordering != PDIPM_ORDER_LEVELS && h->opt.ordering != PDIPM_ORDER_MULTILEVEL) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "ordering must be PDIPM_ORDER_LEVELS or PDIPM_ORDER_MULTILEVEL");
+  }
   try {
     h->need64 = h->opt.precision == PDIPM_FP64 || h->opt.fp64_fallback;
     h->need32 = h->opt.precision == PDIPM_FP32;
-    analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym);
+    analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym, h->opt.ordering);
     create_lap("symbolic analysis");
+    if (h->aug) {
+      // SQD: the pivot of an x variable is positive, of a lambda one negative
+      h->psign.resize(h->sym.n);
+      for (int64_t k = 0; k < h->sym.n; ++k) h->psign[k] = h->sym.perm[k] < h->hp.n ? 1 : -1;
+    }
     finish_analysis(h);
     create_lap("plans and K map");
     layout(h);
@@ -1303,14 +1340,26 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
   }
-  if (h->opt.kkt_form != PDIPM_KKT_PRIMAL && h->opt.kkt_form != PDIPM_KKT_DUAL) {
+  if (h->opt.kkt_form != PDIPM_KKT_PRIMAL && h->opt.kkt_form != PDIPM_KKT_DUAL &&
+      h->opt.kkt_form != PDIPM_KKT_AUGMENTED) {
     delete h;
-    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_form must be PDIPM_KKT_PRIMAL or PDIPM_KKT_DUAL");
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_form must be PDIPM_KKT_PRIMAL, _DUAL or _AUGMENTED");
   }
   create_lap("start");
   std::string e = build_problem(prob, &h->hp);
   if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
   create_lap("problem copy and patterns");
+  if (h->opt.kkt_form == PDIPM_KKT_AUGMENTED) {
+    h->aug = true;
+    try {
+      build_augmented_structures(h->hp, &h->graph, &h->km);
+    } catch (const std::exception& ex) {
+      delete h;
+      return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());
+    }
+    create_lap("graph of the augmented matrix and its map");
+    return finish_create(h, opts, out);
+  }
   if (h->opt.kkt_form == PDIPM_KKT_DUAL) {
     if ((int64_t)h->hp.hc.size() != h->hp.n) {
       delete h;

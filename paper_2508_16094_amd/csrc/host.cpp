@@ -382,6 +382,56 @@ void build_dual_structures(const HostProblem& p, Graph* g, KMap* km) {
   for (int32_t& b : km->tb) b = p.jte[b];
 }
 
+void build_augmented_structures(const HostProblem& p, Graph* g, KMap* km) {
+  const int64_t n = p.n, m = p.m, N = n + m;
+  // graph: x_i ~ x_j through H, x_j ~ lambda_k through J (lambda_k = n + k)
+  g->n = N;
+  g->ptr.assign(N + 1, 0);
+  g->adj.clear();
+  std::vector<int32_t> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    for (int64_t q = p.hsp[i]; q < p.hsp[i + 1]; ++q)
+      if (p.hsc[q] != i) row.push_back(p.hsc[q]);
+    for (int64_t q = p.jtp[i]; q < p.jtp[i + 1]; ++q) row.push_back((int32_t)(n + p.jtr[q]));
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    g->adj.insert(g->adj.end(), row.begin(), row.end());
+    g->ptr[i + 1] = (int64_t)g->adj.size();
+  }
+  for (int64_t k = 0; k < m; ++k) {
+    for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) g->adj.push_back(p.jc[e]);
+    g->ptr[n + k + 1] = (int64_t)g->adj.size();
+  }
+  // lower pattern: x rows = H's lower rows; lambda row k = J row k, then its
+  // diagonal.  kh holds the H entry (x rows) or the J entry (lambda rows,
+  // -1 on the diagonal); there are no product triples.
+  km->n = N;
+  km->kp.assign(N + 1, 0);
+  km->kc.clear(); km->krow.clear(); km->kh.clear();
+  km->tk.clear(); km->ta.clear(); km->tb.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = p.hp[i]; e < p.hp[i + 1]; ++e) {
+      km->kc.push_back(p.hc[e]);
+      km->krow.push_back((int32_t)i);
+      km->kh.push_back((int32_t)e);
+    }
+    km->kp[i + 1] = (int64_t)km->kc.size();
+  }
+  for (int64_t k = 0; k < m; ++k) {
+    for (int64_t e = p.jp[k]; e < p.jp[k + 1]; ++e) {
+      km->kc.push_back(p.jc[e]);
+      km->krow.push_back((int32_t)(n + k));
+      km->kh.push_back((int32_t)e);
+    }
+    km->kc.push_back((int32_t)(n + k));
+    km->krow.push_back((int32_t)(n + k));
+    km->kh.push_back(-1);
+    km->kp[n + k + 1] = (int64_t)km->kc.size();
+  }
+  km->tp.assign(km->kc.size() + 1, 0);
+}
+
 void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km) {
   km->n = n;
   km->kp.assign(rp, rp + n + 1);
@@ -523,8 +573,9 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     const int tm = esize == 8 ? GEMM_TILE_F64 : GEMM_TILE_F32;
     auto add_gemm = [&](int64_t c_off, int64_t a_off, int64_t b_off, int32_t ldc, int32_t lda, int32_t ldb,
                         int32_t M, int32_t N, int32_t K, int32_t c_buf, int32_t b_buf, int32_t mode,
-                        int32_t lower, int64_t& tiles) {
+                        int32_t lower, int32_t kcol, int64_t& tiles) {
       GemmDesc g{};
+      g.kcol = kcol;
       g.c_off = c_off; g.a_off = a_off; g.b_off = b_off;
       g.ldc = ldc; g.lda = lda; g.ldb = ldb;
       g.M = M; g.N = N; g.K = K;
@@ -551,7 +602,8 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
             if (P.sw[k] <= c0) continue;
             const int32_t h = P.sh[k], ld = P.sld[k], bw = std::min(nb, P.sw[k] - c0);
             add_gemm(P.spanel[k] + (int64_t)c0 * ld + c0, P.spanel[k] + (int64_t)o0 * ld + c0,
-                     P.spanel[k] + (int64_t)o0 * ld + c0, ld, ld, ld, h - c0, bw, c0 - o0, 0, 0, 0, 1, tiles);
+                     P.spanel[k] + (int64_t)o0 * ld + c0, ld, ld, ld, h - c0, bw, c0 - o0, 0, 0, 0, 1,
+                     P.sfirst[k] + o0, tiles);
           }
           if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
         }
@@ -581,7 +633,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
           int32_t M = P.sh[k] - c0 - bw;
           if (M <= 0) continue;
           int64_t off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0 + bw;
-          add_gemm(off, off, inv_of[q], P.sld[k], P.sld[k], nb, M, bw, bw, 0, 1, 1, 0, tiles);
+          add_gemm(off, off, inv_of[q], P.sld[k], P.sld[k], nb, M, bw, bw, 0, 1, 1, 0, P.sfirst[k] + c0, tiles);
         }
         if (tiles) P.ops.push_back({OP_TRSM, gb, (int64_t)P.gemm.size(), tiles});
       }
@@ -594,10 +646,11 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
         int32_t o1 = std::min(o0 + nbo, w), K = o1 - o0;
         if (w - o1 > 0)
           add_gemm(P.spanel[k] + (int64_t)o1 * ld + o1, P.spanel[k] + (int64_t)o0 * ld + o1,
-                   P.spanel[k] + (int64_t)o0 * ld + o1, ld, ld, ld, h - o1, w - o1, K, 0, 0, 0, 1, tiles);
+                   P.spanel[k] + (int64_t)o0 * ld + o1, ld, ld, ld, h - o1, w - o1, K, 0, 0, 0, 1,
+                   P.sfirst[k] + o0, tiles);
         if (h - w > 0)
           add_gemm(P.su[k], P.spanel[k] + (int64_t)o0 * ld + w, P.spanel[k] + (int64_t)o0 * ld + w, h - w, ld,
-                   ld, h - w, h - w, K, 1, 0, 0, 1, tiles);
+                   ld, h - w, h - w, K, 1, 0, 0, 1, P.sfirst[k] + o0, tiles);
       }
       if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});
     }

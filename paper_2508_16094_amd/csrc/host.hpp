@@ -69,6 +69,9 @@ struct GemmDesc {          // C (-)= A * B^T on an M x N block, K inner
   int32_t mode;            // 0 subtract (lower masked when lower=1), 1 set
   int32_t lower;
   int32_t tiles_m, tiles_n;
+  int32_t kcol;            // permuted column of inner index 0 (mode 0) or of
+                           // output column 0 (mode 1): the pivot signs of a
+                           // signed (SQD) factorisation
   int64_t tile_begin;      // first tile of this descriptor in its launch
 };
 
@@ -156,6 +159,12 @@ void build_kmap_lower(int64_t n, const int64_t* rp, const int32_t* ci, KMap* km)
 // (m x m; Section 3, eq. kkt_dual): M(e) = [row == col] E_row
 // + sum_t D[tk[t]] J[ta[t]] J[tb[t]], tk a column of J, ta/tb J entries.
 void build_dual_structures(const HostProblem& p, Graph* g, KMap* km);
+// Graph and assembly map of the augmented SQD matrix (Section 3, eq.
+// augmentedKKT) of order n + m, x block first:
+//   [ H + diag(Sigma_x + delta_p)   J'           ]
+//   [ J                             -1 / Sigma_s ]
+// x rows: kh = H entry; lambda rows: kh = J entry, -1 on the diagonal.
+void build_augmented_structures(const HostProblem& p, Graph* g, KMap* km);
 // Blocking of the numeric plan: fronts of height <= small_h (at most 64) use
 // the one-workgroup LDS kernel; larger fronts take rank-(outer_blocks * nb)
 // trailing updates.

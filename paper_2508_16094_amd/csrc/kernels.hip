@@ -175,13 +175,15 @@ __global__ void k_set_values(DevKMap K, const double* kval, T* panel) {
   if (e < K.nk) panel[K.pos[e]] = (T)kval[e];
 }
 
-// Symmetric scaling D = diag(K)^(-1/2): partials give max K_ii and the count
-// of non-positive diagonal entries.
-__global__ void k_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials) {
+// Symmetric scaling D = |diag(K)|^(-1/2): partials give max |K_ii| and the
+// count of diagonal entries without their pivot's sign (positive below npos,
+// negative from npos on; a plain SPD K has npos >= n).
+__global__ void k_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
+                             int64_t npos) {
   RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
   double a[3] = {0.0, 0.0, INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-    const double kii = kval[kp[i + 1] - 1];
+    const double kii = (i < npos ? 1.0 : -1.0) * kval[kp[i + 1] - 1];
     if (kii > 0.0 && isfinite(kii)) {
       d[i] = 1.0 / sqrt(kii);
       a[0] = fmax(a[0], kii);
@@ -200,8 +202,31 @@ __global__ void k_set_scaled(DevKMap K, const double* kval, const double* d, dou
   if (e >= K.nk) return;
   const int32_t r = K.krow[e], c = K.kc[e];
   double v = kval[e] * d[r] * d[c];
-  if (r == c) v += shift;
+  if (r == c) v += r < K.npos ? shift : -shift;   // the shift takes the pivot's sign
   panel[K.pos[e]] = (T)v;
+}
+
+// Augmented SQD matrix [H + diag(Sigma_x + delta_p), J'; J, -1/Sigma_s] in
+// the order of its assembly map: x rows take an H entry, lambda rows a J
+// entry (kh) or, on the diagonal, -1/Sigma_s.
+__global__ void k_assemble_aug(DevKMap K, int64_t n, const double* hv, const double* jv, const double* sig_s,
+                               const double* sig_x, double delta_p, double* kval) {
+  const int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (e >= K.nk) return;
+  const int32_t r = K.krow[e], c = K.kc[e], q = K.kh[e];
+  double v;
+  if (r < n) {
+    v = hv[q];
+    if (r == c) v += sig_x[r] + delta_p;
+  } else {
+    v = r == c ? -1.0 / sig_s[r - n] : jv[q];
+  }
+  kval[e] = v;
+}
+
+__global__ void k_sign_scale(int64_t n, const signed char* sign, double* y) {
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < n && sign[i] < 0) y[i] = -y[i];
 }
 
 __global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc, const int64_t* kss,
@@ -281,8 +306,11 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
     __syncthreads();
   }
   for (int k = 0; k < w; ++k) {
+    // signed factorisation (P.sign): L S L' with l_kk = sqrt(s_k a_kk),
+    // l_ik = a_ik / (s_k l_kk) and a_ij -= l_ik s_k l_jk
+    const T sk = P.sign && P.sign[P.sfirst[S] + k] < 0 ? (T)-1 : (T)1;
     if (threadIdx.x == 0) {
-      T d = F[k + k * LD];
+      T d = sk * F[k + k * LD];
       if (!(d > (T)0) || !isfinite((double)d)) {
         atomicMin(bad, P.sfirst[S] + k);
         d = (T)1;
@@ -290,13 +318,13 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
       F[k + k * LD] = sqrt(d);
     }
     __syncthreads();
-    const T piv = F[k + k * LD];
+    const T piv = sk * F[k + k * LD];
     for (int i = k + 1 + threadIdx.x; i < h; i += BS) F[i + k * LD] /= piv;
     __syncthreads();
     const int r = h - k - 1;
     for (int idx = threadIdx.x; idx < r * r; idx += BS) {
       int i = k + 1 + idx % r, j = k + 1 + idx / r;
-      if (i >= j) F[i + j * LD] -= F[i + k * LD] * F[j + k * LD];
+      if (i >= j) F[i + j * LD] -= sk * F[i + k * LD] * F[j + k * LD];
     }
     __syncthreads();
   }
@@ -375,7 +403,10 @@ __device__ inline double lane_bcast(double v, int src) {
 // wide supernode is latency-bound: 135 instead of 190 us per block); larger
 // launches and FP64 take 4 waves (two workgroups per CU; 8 waves would not
 // fit the FP64 panel work in registers).
-template <typename T, int NB, int PT>
+// SG: signed factorisation L S L' of an SQD block (pivot signs from
+// P.sign): l_kk = sqrt(s_k a_kk), l_ik = a_ik / (s_k l_kk), trailing
+// a_ij -= l_ik s_k l_jk; the inverse is that of L.
+template <typename T, int NB, int PT, bool SG>
 __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
   constexpr int GR = PT / 16, GC = 16, PB = 16, NP = NB / PB, LDA = NB + 1, S = NB / 64;
   constexpr int TR = NB / GR, TC = NB / GC;   // rows and columns of a thread's tile
@@ -383,6 +414,7 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
   __shared__ T A[NB * LDA];
   __shared__ T xd[NB];
   __shared__ T rdiag[NB];   // 1 / L(k, k)
+  __shared__ T ssg[SG ? NB : 1];   // pivot signs of the block (padding +1)
   const PotrfDesc d = P.potrf[d0 + blockIdx.x];
   const int bw = d.bw;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -407,6 +439,7 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
     }
   }
   if (tid < NB) xd[tid] = (T)1;
+  if (SG && tid < NB) ssg[tid] = tid < bw && P.sign[d.col0 + tid] < 0 ? (T)-1 : (T)1;
   __syncthreads();
   // ---- factor
   for (int p = 0; p < NP; ++p) {
@@ -421,22 +454,24 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
       }
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
-        T dk = lane_bcast(a[0][k], k);
+        const T sk = SG ? ssg[c0 + k] : (T)1;
+        T dk = sk * lane_bcast(a[0][k], k);
         if (!(dk > (T)0) || !isfinite((double)dk)) {
           if (lane == 0 && c0 + k < bw) atomicMin(bad, d.col0 + c0 + k);
           dk = (T)1;
         }
         const T piv = sqrt(dk), rp = (T)1 / piv;
         if (lane == 0) rdiag[c0 + k] = rp;
+        const T rs = SG ? sk * rp : rp;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int rel = lane + 64 * s;
-          if (rel > k) a[s][k] *= rp;
+          if (rel > k) a[s][k] *= rs;
           else if (rel == k) a[s][k] = piv;
         }
 #pragma unroll
         for (int j = k + 1; j < PB; ++j) {
-          const T ljk = lane_bcast(a[0][k], j);
+          const T ljk = SG ? sk * lane_bcast(a[0][k], j) : lane_bcast(a[0][k], j);
 #pragma unroll
           for (int s = 0; s < S; ++s)
             if (lane + 64 * s > k) a[s][j] -= a[s][k] * ljk;
@@ -461,10 +496,11 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
 #pragma unroll 4
       for (int t = 0; t < PB; ++t) {
         T li[TR], lj[TC];
+        const T st = SG ? ssg[c0 + t] : (T)1;
 #pragma unroll
         for (int r = 0; r < TR; ++r) li[r] = A[tr * TR + r + (c0 + t) * LDA];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) lj[c] = A[tc * TC + c + (c0 + t) * LDA];
+        for (int c = 0; c < TC; ++c) lj[c] = SG ? st * A[tc * TC + c + (c0 + t) * LDA] : A[tc * TC + c + (c0 + t) * LDA];
 #pragma unroll
         for (int r = 0; r < TR; ++r)
 #pragma unroll
@@ -639,7 +675,11 @@ __device__ inline double2u load2(const double* p, int valid) {
 // waves, each a (16 BX) x (16 BY) strip of BX x BY MFMA blocks; K chunks of
 // 32 (16 for 128 x 128 tiles, to fit two workgroups per CU) staged through
 // LDS with the next chunk prefetched into registers.
+// SG: signed factorisation (L S L'): updates subtract A S B' (the sign of
+// inner index k, at permuted column kcol + k, applied to A), the panel solve
+// scales output column j by the sign at kcol + j.
 constexpr int BS64 = 512;  // threads of the FP64 GEMM (8 waves)
+template <bool SG>
 __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
                                                    double* ubuf, const double* inv) {
   constexpr int TM = GEMM_TILE_F64, BX = TM == 128 ? 4 : 1, BY = 2;
@@ -676,6 +716,8 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
       const int gk = k0 + kb + KS * r;
       ra[r] = load2(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load2(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
+      if constexpr (SG)
+        if (d.mode == 0 && gk < d.K && P.sign[d.kcol + gk] < 0) ra[r] = -ra[r];
     }
   };
   load(0);
@@ -713,7 +755,7 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
         if (i < d.M && j < d.N && (!d.lower || i >= j)) {
           double* cp = C + i + (int64_t)j * d.ldc;
           if (d.mode == 0) *cp -= acc[x][y][r];
-          else *cp = acc[x][y][r];
+          else *cp = SG && P.sign[d.kcol + j] < 0 ? -acc[x][y][r] : acc[x][y][r];
         }
       }
 }
@@ -723,6 +765,7 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
 // staged through LDS in chunks of 32 with the next chunk prefetched into
 // registers.
 constexpr int BS32 = 512;  // threads of the FP32 GEMM (8 waves)
+template <bool SG>
 __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
                                                    float* ubuf, const float* inv) {
   constexpr int TM = GEMM_TILE_F32, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
@@ -759,6 +802,8 @@ __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_
       const int gk = k0 + kb + 16 * r;
       ra[r] = load4(Ap + (int64_t)gk * d.lda, gk < d.K ? arows : 0);
       rb[r] = load4(Bp + (int64_t)gk * d.ldb, gk < d.K ? brows : 0);
+      if constexpr (SG)
+        if (d.mode == 0 && gk < d.K && P.sign[d.kcol + gk] < 0) ra[r] = -ra[r];
     }
   };
   load(0);
@@ -791,7 +836,7 @@ __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_
       if (i < d.M && j < d.N && (!d.lower || i >= j)) {
         float* cp = C + i + (int64_t)j * d.ldc;
         if (d.mode == 0) *cp -= acc[x][r];
-        else *cp = acc[x][r];
+        else *cp = SG && P.sign[d.kcol + j] < 0 ? -acc[x][r] : acc[x][r];
       }
     }
 }
@@ -1538,15 +1583,27 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
     case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf); break;
     case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad); break;
     case OP_POTRF:
-      if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
-      else if (op.grid <= 256) k_potrf<T, 128, 512><<<g, 512, 0, s>>>(P, op.begin, panel, inv, bad);
-      else k_potrf<T, 128, 256><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+      if (P.sign) {
+        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+        else k_potrf<T, 128, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+      } else {
+        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+        else if (op.grid <= 256) k_potrf<T, 128, 512, false><<<g, 512, 0, s>>>(P, op.begin, panel, inv, bad);
+        else k_potrf<T, 128, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+      }
       break;
     case OP_TRSM:
     case OP_UPDATE: {
       const unsigned g8 = (unsigned)((op.grid + 7) / 8 * 8);
-      if constexpr (sizeof(T) == 8) k_gemm_f64<<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
-      else k_gemm_f32<<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      if (P.sign) {
+        if constexpr (sizeof(T) == 8)
+          k_gemm_f64<true><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+        else k_gemm_f32<true><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      } else {
+        if constexpr (sizeof(T) == 8)
+          k_gemm_f64<false><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+        else k_gemm_f32<false><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+      }
       break;
     }
   }
@@ -1554,6 +1611,13 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
 template void launch_factor_op<double>(const Op&, const DevPlan&, double*, double*, double*, int*, hipStream_t);
 template void launch_factor_op<float>(const Op&, const DevPlan&, float*, float*, float*, int*, hipStream_t);
 
+void launch_sign_scale(int64_t n, const signed char* sign, double* y, hipStream_t s) {
+  if (n > 0) k_sign_scale<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, sign, y);
+}
+void launch_assemble_aug(const DevKMap& K, int64_t n, const double* hv, const double* jv, const double* sig_s,
+                         const double* sig_x, double delta_p, double* kval, hipStream_t s) {
+  k_assemble_aug<<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, n, hv, jv, sig_s, sig_x, delta_p, kval);
+}
 void launch_permute_in(const DevPlan& P, const double* rhs, const double* d, double* xp, hipStream_t s) {
   k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, d, xp);
 }
@@ -1561,9 +1625,9 @@ void launch_permute_out(const DevPlan& P, const double* xp, const double* d, dou
   k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, d, x);
 }
 void launch_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
-                       hipStream_t s) {
+                       hipStream_t s, int64_t npos) {
   int g = red_grid(n);
-  k_diag_scale<<<g, BS, 0, s>>>(n, kp, kval, d, partials);
+  k_diag_scale<<<g, BS, 0, s>>>(n, kp, kval, d, partials, npos);
   RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }

@@ -26,10 +26,14 @@ struct DevPlan {
   const int64_t *spanel, *su, *srow, *suv, *sinv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
   const SolveDesc* sdesc; const int32_t *ssmall, *slarge;
+  // pivot signs of a signed factorisation P'AP = L S L' (S = diag(sign),
+  // permuted numbering; Section 2, SQD matrices); null: Cholesky, S = I
+  const signed char* sign;
 };
 
 struct DevKMap {
   int64_t nk;
+  int64_t npos;   // original indices below npos carry pivot sign +1, the rest -1
   const int32_t *krow, *kc, *kh, *tk, *ta, *tb;
   const int64_t *tp, *pos;
 };
@@ -78,9 +82,16 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
 // triangular solves (vectors FP64, panels T)
 void launch_permute_in(const DevPlan& P, const double* rhs, const double* d, double* xperm, hipStream_t s);
 void launch_permute_out(const DevPlan& P, const double* xperm, const double* d, double* x, hipStream_t s);
-// symmetric scaling of K (FP32 factor): d = diag(K)^(-1/2), max diag, count of bad pivots
+// symmetric scaling of K (FP32 factor): d = |diag(K)|^(-1/2), max |diag|, count
+// of diagonal entries whose sign is not their pivot's (indices below npos
+// positive, the rest negative)
 void launch_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
-                       hipStream_t s);
+                       hipStream_t s, int64_t npos = INT64_MAX);
+// y *= sign (permuted numbering): the middle factor of L S L' solves
+void launch_sign_scale(int64_t n, const signed char* sign, double* y, hipStream_t s);
+// augmented SQD matrix values in its assembly map's order (x block n first)
+void launch_assemble_aug(const DevKMap& K, int64_t n, const double* hv, const double* jv, const double* sig_s,
+                         const double* sig_x, double delta_p, double* kval, hipStream_t s);
 template <typename T>
 void launch_set_scaled(const DevKMap& K, const double* kval, const double* d, double shift, T* panel,
                        hipStream_t s);

@@ -127,9 +127,228 @@ std::vector<int32_t> degree_order(const NdState& st, const std::vector<int32_t>&
   return out;
 }
 
+// ---------------------------------------------- multilevel bisection
+// Separators from multilevel graph bisection in the style of METIS (Karypis
+// and Kumar): heavy-edge matching down to a small graph, a BFS-grown
+// bisection there, greedy boundary refinement on every level on the way
+// back, and the smaller boundary side of the edge cut as the vertex
+// separator.  Integer weights and explicit tie-breaks throughout, so the
+// result is reproducible bit for bit by an independent implementation.
+constexpr int64_t ML_COARSEN_TO = 64;
+constexpr int64_t ML_SHRINK_NUM = 9, ML_SHRINK_DEN = 10;
+constexpr int ML_PASSES = 8;
+constexpr int64_t ML_BAL_NUM = 11, ML_BAL_DEN = 20;
+
+struct MlGraph {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> adj;
+  std::vector<int64_t> ew, vw;
+  int64_t n() const { return (int64_t)vw.size(); }
+};
+
+// Heavy-edge matching in increasing vertex order (partner: largest edge
+// weight, then smaller vertex weight, then smaller index); coarse ids in
+// order of the first member's visit; parallel edges and weights add.
+void ml_coarsen(const MlGraph& f, std::vector<int32_t>& cmap, MlGraph& c) {
+  const int64_t n = f.n();
+  std::vector<char> matched(n, 0);
+  cmap.assign(n, -1);
+  std::vector<int32_t> first, second;
+  for (int64_t v = 0; v < n; ++v) {
+    if (matched[v]) continue;
+    int32_t best = -1;
+    int64_t bw = 0, bvw = 0;
+    for (int64_t e = f.ptr[v]; e < f.ptr[v + 1]; ++e) {
+      const int32_t u = f.adj[e];
+      if (matched[u]) continue;
+      const int64_t w = f.ew[e];
+      if (best < 0 || w > bw || (w == bw && (f.vw[u] < bvw || (f.vw[u] == bvw && u < best)))) {
+        best = u; bw = w; bvw = f.vw[u];
+      }
+    }
+    matched[v] = 1;
+    cmap[v] = (int32_t)first.size();
+    if (best >= 0) { matched[best] = 1; cmap[best] = (int32_t)first.size(); }
+    first.push_back((int32_t)v);
+    second.push_back(best);
+  }
+  const int64_t nc = (int64_t)first.size();
+  c.ptr.assign(nc + 1, 0);
+  c.adj.clear(); c.ew.clear(); c.vw.assign(nc, 0);
+  std::vector<int64_t> acc(nc, 0);
+  std::vector<int32_t> touched;
+  for (int64_t k = 0; k < nc; ++k) {
+    touched.clear();
+    for (int32_t v : {first[k], second[k]}) {
+      if (v < 0) continue;
+      c.vw[k] += f.vw[v];
+      for (int64_t e = f.ptr[v]; e < f.ptr[v + 1]; ++e) {
+        const int32_t cu = cmap[f.adj[e]];
+        if (cu == k) continue;
+        if (acc[cu] == 0) touched.push_back(cu);
+        acc[cu] += f.ew[e];
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t cu : touched) { c.adj.push_back(cu); c.ew.push_back(acc[cu]); acc[cu] = 0; }
+    c.ptr[k + 1] = (int64_t)c.adj.size();
+  }
+}
+
+// BFS levels (discovery order) from root, flat with level pointers.
+int ml_bfs(const MlGraph& g, int32_t root, std::vector<int32_t>& order, std::vector<int64_t>& lp,
+           std::vector<int32_t>& seen, int32_t stamp) {
+  order.clear(); lp.clear();
+  order.push_back(root);
+  seen[root] = stamp;
+  lp.push_back(0);
+  size_t begin = 0;
+  while (true) {
+    const size_t end = order.size();
+    lp.push_back((int64_t)end);
+    for (size_t q = begin; q < end; ++q)
+      for (int64_t e = g.ptr[order[q]]; e < g.ptr[order[q] + 1]; ++e) {
+        const int32_t w = g.adj[e];
+        if (seen[w] != stamp) { seen[w] = stamp; order.push_back(w); }
+      }
+    if (order.size() == end) break;
+    begin = end;
+  }
+  return (int)lp.size() - 1;
+}
+
+// Part 0 = the shortest prefix of a BFS order from a pseudo-peripheral vertex
+// whose weight reaches half the total.
+std::vector<int8_t> ml_initial(const MlGraph& g) {
+  const int64_t n = g.n();
+  int64_t total = 0;
+  for (int64_t w : g.vw) total += w;
+  auto deg = [&](int32_t v) { return g.ptr[v + 1] - g.ptr[v]; };
+  int32_t r = 0;
+  for (int32_t v = 1; v < n; ++v)
+    if (deg(v) < deg(r)) r = v;
+  std::vector<int32_t> seen(n, 0), order, order2;
+  std::vector<int64_t> lp, lp2;
+  int32_t stamp = 1;
+  int nl = ml_bfs(g, r, order, lp, seen, stamp);
+  while (true) {
+    int32_t v = order[lp[nl - 1]];
+    for (int64_t q = lp[nl - 1]; q < lp[nl]; ++q) {
+      const int32_t u = order[q];
+      if (deg(u) < deg(v) || (deg(u) == deg(v) && u < v)) v = u;
+    }
+    const int nl2 = ml_bfs(g, v, order2, lp2, seen, ++stamp);
+    if (nl2 > nl) { std::swap(order, order2); std::swap(lp, lp2); nl = nl2; }
+    else break;
+  }
+  std::vector<int8_t> part(n, 1);
+  int64_t w0 = 0;
+  for (int32_t v : order) {
+    if (2 * w0 >= total) break;
+    part[v] = 0;
+    w0 += g.vw[v];
+  }
+  return part;
+}
+
+// Greedy boundary refinement: boundary vertices by decreasing gain (ties by
+// index) with gains kept current; a vertex moves when its gain is positive
+// and the target part stays within the balance bound, or its gain is zero
+// and the move strictly narrows the weight difference.
+void ml_refine(const MlGraph& g, std::vector<int8_t>& part) {
+  const int64_t n = g.n();
+  int64_t total = 0;
+  for (int64_t w : g.vw) total += w;
+  const int64_t maxw = ML_BAL_NUM * total / ML_BAL_DEN;
+  int64_t pw[2] = {0, 0};
+  for (int64_t v = 0; v < n; ++v) pw[part[v]] += g.vw[v];
+  std::vector<int64_t> ext(n, 0), inn(n, 0);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e)
+      (part[g.adj[e]] == part[v] ? inn[v] : ext[v]) += g.ew[e];
+  std::vector<int32_t> cands;
+  for (int pass = 0; pass < ML_PASSES; ++pass) {
+    cands.clear();
+    for (int64_t v = 0; v < n; ++v)
+      if (ext[v] > 0) cands.push_back((int32_t)v);
+    std::sort(cands.begin(), cands.end(), [&](int32_t a, int32_t b) {
+      const int64_t ka = inn[a] - ext[a], kb = inn[b] - ext[b];
+      return ka != kb ? ka < kb : a < b;
+    });
+    bool moved = false;
+    for (int32_t v : cands) {
+      const int64_t gain = ext[v] - inn[v];
+      const int src = part[v], dst = 1 - part[v];
+      if (!((gain > 0 && pw[dst] + g.vw[v] <= maxw) || (gain == 0 && pw[src] > pw[dst] + g.vw[v]))) continue;
+      part[v] = (int8_t)dst;
+      pw[src] -= g.vw[v];
+      pw[dst] += g.vw[v];
+      std::swap(ext[v], inn[v]);
+      for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e) {
+        const int32_t u = g.adj[e];
+        if (part[u] == dst) { inn[u] += g.ew[e]; ext[u] -= g.ew[e]; }
+        else { ext[u] += g.ew[e]; inn[u] -= g.ew[e]; }
+      }
+      moved = true;
+    }
+    if (!moved) break;
+  }
+}
+
+// Separator of the connected component comp (sorted; its vertices carry
+// mark cst): false when the bisection leaves a side empty.
+bool multilevel_separator(const Graph& g, const std::vector<int32_t>& comp, const std::vector<int32_t>& mark,
+                          int32_t cst, std::vector<int32_t>& local, std::vector<int32_t>& lo,
+                          std::vector<int32_t>& hi, std::vector<int32_t>& sep) {
+  const int64_t nc = (int64_t)comp.size();
+  std::vector<MlGraph> graphs(1);
+  MlGraph& g0 = graphs[0];
+  for (int64_t i = 0; i < nc; ++i) local[comp[i]] = (int32_t)i;
+  g0.ptr.assign(nc + 1, 0);
+  g0.vw.assign(nc, 1);
+  for (int64_t i = 0; i < nc; ++i) {
+    const int32_t v = comp[i];
+    for (int64_t e = g.ptr[v]; e < g.ptr[v + 1]; ++e)
+      if (mark[g.adj[e]] == cst) g0.adj.push_back(local[g.adj[e]]);
+    g0.ptr[i + 1] = (int64_t)g0.adj.size();
+  }
+  g0.ew.assign(g0.adj.size(), 1);
+  std::vector<std::vector<int32_t>> cmaps;
+  while (graphs.back().n() > ML_COARSEN_TO) {
+    std::vector<int32_t> cmap;
+    MlGraph c;
+    ml_coarsen(graphs.back(), cmap, c);
+    if (c.n() * ML_SHRINK_DEN > ML_SHRINK_NUM * graphs.back().n()) break;
+    cmaps.push_back(std::move(cmap));
+    graphs.push_back(std::move(c));
+  }
+  std::vector<int8_t> part = ml_initial(graphs.back());
+  ml_refine(graphs.back(), part);
+  for (int64_t l = (int64_t)cmaps.size() - 1; l >= 0; --l) {
+    std::vector<int8_t> fine(cmaps[l].size());
+    for (size_t v = 0; v < fine.size(); ++v) fine[v] = part[cmaps[l][v]];
+    part.swap(fine);
+    ml_refine(graphs[l], part);
+  }
+  const MlGraph& f = graphs[0];
+  std::vector<char> bnd(nc, 0);
+  int64_t nb[2] = {0, 0};
+  for (int64_t v = 0; v < nc; ++v)
+    for (int64_t e = f.ptr[v]; e < f.ptr[v + 1]; ++e)
+      if (part[f.adj[e]] != part[v]) { bnd[v] = 1; ++nb[part[v]]; break; }
+  const int side = nb[0] <= nb[1] ? 0 : 1;
+  lo.clear(); hi.clear(); sep.clear();
+  for (int64_t v = 0; v < nc; ++v) {
+    if (bnd[v] && part[v] == side) sep.push_back(comp[v]);
+    else if (part[v] == 0) lo.push_back(comp[v]);
+    else hi.push_back(comp[v]);
+  }
+  return !lo.empty() && !hi.empty();
+}
+
 }  // namespace
 
-std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
+std::vector<int32_t> nested_dissection(const Graph& g, int leaf, int method) {
   const int64_t n = g.n;
   std::vector<int32_t> out;
   out.reserve(n);
@@ -142,6 +361,7 @@ std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
   }
   std::vector<int32_t> comp, order, order2;
   std::vector<int64_t> lp, lp2;
+  std::vector<int32_t> local(method == 1 ? n : 0), mlo, mhi, msep;
   while (!stack.empty()) {
     Task t = std::move(stack.back());
     stack.pop_back();
@@ -206,6 +426,37 @@ std::vector<int32_t> nested_dissection(const Graph& g, int leaf) {
         const int h = nl - 1;
         if (h < 2) {
           tasks.push_back(Task{true, degree_order(st, comp)});
+        } else if (method == 1 && multilevel_separator(g, comp, st.mark, cst, local, mlo, mhi, msep)) {
+          // multilevel separator, with the same rejection rule as below
+          const int64_t total = (int64_t)comp.size();
+          for (int32_t v : msep) st.mark[v] = -2;
+          ++st.bstamp;
+          const int32_t cs2 = st.bstamp;
+          int64_t biggest = 0;
+          for (int32_t v0 : comp) {
+            if (st.mark[v0] != cst || st.seen[v0] == cs2) continue;
+            int64_t cnt = 0;
+            order2.clear();
+            order2.push_back(v0);
+            st.seen[v0] = cs2;
+            for (size_t qq = 0; qq < order2.size(); ++qq) {
+              int32_t u = order2[qq];
+              ++cnt;
+              for (int64_t e = g.ptr[u]; e < g.ptr[u + 1]; ++e) {
+                int32_t w2 = g.adj[e];
+                if (st.mark[w2] == cst && st.seen[w2] != cs2) { st.seen[w2] = cs2; order2.push_back(w2); }
+              }
+            }
+            biggest = std::max(biggest, cnt);
+          }
+          for (int32_t v : msep) st.mark[v] = cst;
+          if (8 * biggest > 7 * total) {
+            tasks.push_back(Task{true, degree_order(st, comp)});
+            continue;
+          }
+          tasks.push_back(Task{false, mlo});
+          tasks.push_back(Task{false, mhi});
+          tasks.push_back(Task{true, msep});
         } else {
           const int64_t total = (int64_t)comp.size();
           int best = -1;
@@ -394,7 +645,7 @@ std::vector<int64_t> column_counts(const Graph& h, const std::vector<int32_t>& p
 
 }  // namespace
 
-void analyze(const Graph& g, int leaf, int menu, Symbolic* out) {
+void analyze(const Graph& g, int leaf, int menu, Symbolic* out, int method) {
   const int64_t n = g.n;
   const bool timing = std::getenv("PDIPM_TIMING") != nullptr;
   auto t0 = std::chrono::steady_clock::now();
@@ -406,7 +657,7 @@ void analyze(const Graph& g, int leaf, int menu, Symbolic* out) {
   };
   Symbolic& s = *out;
   s.n = n;
-  std::vector<int32_t> nd = nested_dissection(g, leaf);
+  std::vector<int32_t> nd = nested_dissection(g, leaf, method);
   lap("nested dissection");
   std::vector<int32_t> pinv(n);
   for (int64_t k = 0; k < n; ++k) pinv[nd[k]] = (int32_t)k;

@@ -44,8 +44,11 @@ struct Symbolic {
 // PDIPM_HOST_THREADS when set (1 to 64, at any size; the results never
 // depend on it), else up to 8 once the work reaches work_min.
 int64_t host_threads(int64_t work, int64_t work_min);
-std::vector<int32_t> nested_dissection(const Graph& g, int leaf);
+// method 0: separators are BFS levels; 1: separators from multilevel
+// bisection (heavy-edge coarsening, boundary refinement), the level rule
+// where the bisection leaves a side empty.
+std::vector<int32_t> nested_dissection(const Graph& g, int leaf, int method = 0);
 // Full analysis: order, postorder, etree, column counts, supernodes.
-void analyze(const Graph& g, int leaf, int menu, Symbolic* out);
+void analyze(const Graph& g, int leaf, int menu, Symbolic* out, int method = 0);
 
 }  // namespace pdipm

@@ -18,7 +18,8 @@ PDIPM_ERR_INVALID_ARG, PDIPM_ERR_OUT_OF_MEMORY, PDIPM_ERR_NOT_PD = -1, -2, -3
 PDIPM_ERR_NUMERICAL, PDIPM_ERR_DEVICE, PDIPM_ERR_NOT_ANALYZED = -4, -5, -6
 PDIPM_FP64, PDIPM_FP32 = 0, 1
 PDIPM_HOST, PDIPM_DEVICE = 0, 1
-PDIPM_KKT_PRIMAL, PDIPM_KKT_DUAL = 0, 1
+PDIPM_KKT_PRIMAL, PDIPM_KKT_DUAL, PDIPM_KKT_AUGMENTED = 0, 1, 2
+PDIPM_ORDER_LEVELS, PDIPM_ORDER_MULTILEVEL = 0, 1
 
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -39,7 +40,7 @@ class ipm_options(ctypes.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("max_wall_time", _f64), ("delta_p", _f64),
                 ("delta_d", _f64), ("precision", _i32), ("ir_max", _i32), ("ir_tol", _f64),
                 ("nd_leaf", _i32), ("amalg_menu", _i32), ("print_level", _i32),
-                ("fp64_fallback", _i32), ("use_graphs", _i32), ("kkt_form", _i32)]
+                ("fp64_fallback", _i32), ("use_graphs", _i32), ("kkt_form", _i32), ("ordering", _i32)]
 
 
 class kkt_symbolic_stats(ctypes.Structure):

@@ -22,15 +22,23 @@ class ParamBatch:
         self.solver = L.BatchSolver([pq.instance(zero) for _ in range(chunk)], precision=precision, **opts).bind()
         self.n, self.m = pq.base.n, pq.base.m
 
-    def solve(self, thetas, starts=None):
+    def solve(self, thetas, starts=None, fallback=True, log=None, log_every=60.0):
         """Solve b(theta) for every row of thetas; returns per-instance
-        results, x (count x n) and lambda (count x m), and the wall time."""
+        results, x (count x n) and lambda (count x m), and the wall time.
+        With starts (predicted x, lambda per row) the instances are warm
+        started; any that does not reach status OK is solved again from the
+        cold start (fallback, inside the timed region) and its result says
+        so ("fallback": 1)."""
         count = thetas.shape[0]
         X = np.empty((count, self.n))
         Lm = np.empty((count, self.m))
         results = []
         t0 = time.time()
+        t_log = t0
         for c0 in range(0, count, self.chunk):
+            if log and time.time() - t_log >= log_every:
+                t_log = time.time()
+                log(f"[warm] solved {c0} of {count} instances in {t_log - t0:.0f}s")
             th = thetas[c0:c0 + self.chunk]
             k = th.shape[0]
             pad = np.concatenate([th, np.repeat(th[-1:], self.chunk - k, axis=0)]) if k < self.chunk else th
@@ -46,6 +54,12 @@ class ParamBatch:
                 start = (xs.ravel(), ls.ravel())
             res, _ = self.solver.solve(start=start)
             sol = self.solver.solution()
+            failed = [i for i in range(k) if res[i]["status"] != 0] if start is not None and fallback else []
+            if failed:
+                cold, _ = self.solver.solve()
+                csol = self.solver.solution()
+                for i in failed:
+                    res[i], sol[i] = dict(cold[i], fallback=1), csol[i]
             for i in range(k):
                 results.append(res[i])
                 X[c0 + i] = sol[i]["x"]

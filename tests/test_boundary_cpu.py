@@ -183,4 +183,77 @@ def test_dual_form_rejects_what_it_cannot_solve():
     with pytest.raises(L.PdipmError):
         L.BatchSolver([w.qp_instance(60, 2)], kkt_form=L.PDIPM_KKT_DUAL)
     with pytest.raises(L.PdipmError):
-        L.IpmSolver(w.lp_small(), kkt_form=2)
+        L.IpmSolver(w.lp_small(), kkt_form=3)
+
+
+@pytest.mark.parametrize("name", ["lp_small", "qp", "nlp_grid", "lp_block"])
+def test_augmented_form_symbolic_bit_exact(name):
+    """Augmented SQD form: the library orders and analyses [H J'; J diag]
+    (order n + m, x block first) exactly as the oracle does."""
+    p = {"lp_small": lambda: w.lp_small(1),
+         "qp": lambda: w.qp_instance(500, 12),
+         "nlp_grid": lambda: w.nlp_grid(30, 26),
+         "lp_block": lambda: w.lp_block(nblocks=5, block_rows=200, block_cols=400, link_cols_per_block=20)}[name]()
+    s = L.IpmSolver(p, kkt_form=L.PDIPM_KKT_AUGMENTED)
+    got = s.symbolic()
+    (jrp, jci), (hrp, hci) = s.patterns()
+    N = p.n + p.m
+    ref = osym.analyze(osym.augmented_pattern(p.n, p.m, jrp, jci, hrp, hci), N)
+    for k in ["perm", "etree", "colcount", "sn_start", "sn_rowptr", "sn_rows"]:
+        assert np.array_equal(got[k], ref[k]), k
+    st = s.stats()
+    assert st["n"] == N and st["nnz_L"] == ref["nnz_L"] and st["flops"] == ref["flops"]
+    rp, ci = s.k_pattern()
+    Jb = sp.csr_matrix((np.ones(len(jci)), jci, jrp), shape=(p.m, p.n))
+    Hb = sp.csr_matrix((np.ones(len(hci)), hci, hrp), shape=(p.n, p.n))
+    S = sp.tril(sp.bmat([[Hb + Hb.T, None], [Jb, sp.eye(p.m)]], format="csr")).tocsr()
+    S.sort_indices()
+    assert np.array_equal(rp, S.indptr) and np.array_equal(ci, S.indices)
+
+
+def _geometric_lower(n, k, seed):
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    P = rng.random((n, 2))
+    _, nb = cKDTree(P).query(P, k + 1)
+    r = np.repeat(np.arange(n), k)
+    S = sp.csr_matrix((np.ones(n * k), (r, nb[:, 1:].ravel())), shape=(n, n))
+    K = sp.tril((((S + S.T) > 0).astype(float) + sp.eye(n)).tocsr()).tocsr()
+    K.sort_indices()
+    return K
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_multilevel_ordering_bit_exact_on_irregular_graphs(seed):
+    n = [1500, 4000, 9000][seed]
+    K = _geometric_lower(n, 6, 60 + seed)
+    s = L.KktSolver(n, K.indptr, K.indices, L.default_options(ordering=L.PDIPM_ORDER_MULTILEVEL))
+    got = s.symbolic()
+    ref = osym.analyze(osym.pattern_from_lower_csr(n, K.indptr, K.indices), n, method="multilevel")
+    for k in ["perm", "etree", "colcount", "sn_start", "sn_rowptr", "sn_rows"]:
+        assert np.array_equal(got[k], ref[k]), k
+
+
+@pytest.mark.parametrize("name,form", [("nlp_grid", 0), ("lp_block", 0), ("lp_block", 1), ("qp", 2), ("lp_small", 0)])
+def test_multilevel_ordering_bit_exact_on_workloads(name, form):
+    p = {"lp_small": lambda: w.lp_small(3),
+         "qp": lambda: w.qp_instance(700, 11),
+         "nlp_grid": lambda: w.nlp_grid(45, 37),
+         "lp_block": lambda: w.lp_block(nblocks=6, block_rows=300, block_cols=600, link_cols_per_block=30)}[name]()
+    s = L.IpmSolver(p, kkt_form=form, ordering=L.PDIPM_ORDER_MULTILEVEL)
+    got = s.symbolic()
+    (jrp, jci), (hrp, hci) = s.patterns()
+    if form == 0:
+        adj, N = osym.kkt_pattern(p.n, jrp, jci, hrp, hci), p.n
+    elif form == 1:
+        adj, N = osym.dual_pattern(p.m, p.n, jrp, jci), p.m
+    else:
+        adj, N = osym.augmented_pattern(p.n, p.m, jrp, jci, hrp, hci), p.n + p.m
+    ref = osym.analyze(adj, N, method="multilevel")
+    for k in ["perm", "etree", "colcount", "sn_start", "sn_rowptr", "sn_rows"]:
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def test_ordering_option_is_checked():
+    with pytest.raises(L.PdipmError):
+        L.IpmSolver(w.lp_small(), ordering=2)

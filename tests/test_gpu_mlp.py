@@ -97,3 +97,38 @@ def test_mlp_deterministic_and_errors():
     with pytest.raises(L.PdipmError) as e:
         m.forward(_dev(np.zeros((33, DIMS[0]))))
     assert e.value.code == L.PDIPM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("B", [256, 512])
+def test_mlp_gradients_elementwise_at_production_shapes(B):
+    """64 -> 512 -> 512 -> 4096 (the production net's layer shapes with a
+    narrower output): the K = 512 products of the forward pass and the
+    K = 4096 product of the last layer's backward pass run split-K, and so do
+    the weight gradients (K = B) at B = 512.  Every gradient entry is within
+    16 u_bf16 (u_bf16 = 2^-8) of the FP64 oracle's, relative to the sum of
+    the absolute values of its terms (the rounding-error scale of a dot
+    product whose factors are rounded to BF16; 16 covers the roundings of
+    the three layers' inputs and of dL/dz)."""
+    dims = [64, 512, 512, 4096]
+    nx = 2731
+    params = w.mlp_init(dims, 11)
+    rng = np.random.default_rng(12)
+    params = [(W, rng.uniform(-0.1, 0.1, b.shape)) for W, b in params]
+    X = rng.standard_normal((B, dims[0]))
+    T = np.concatenate([rng.uniform(0.5, 9.5, (B, nx)), rng.uniform(0.01, 3.0, (B, dims[-1] - nx))], axis=1)
+    print(f"case mlp gradients production shapes B={B}", flush=True)
+    m = L.MlpModel(dims, nx, max_batch=B, x_weight=1e4).bind()
+    m.set_params(params)
+    loss, grads = m.gradients(_dev(X), _dev(T))
+    pb, Xb = _bf16_params(params), bf16_round(X)
+    lref, gref = omlp.gradients(pb, Xb, T, nx, x_weight=1e4)
+    mags = omlp.gradient_magnitudes(pb, Xb, T, nx, x_weight=1e4)
+    assert abs(loss - lref) <= 2e-2 * lref, (loss, lref)
+    bound = 16 * 2.0 ** -8
+    worst = 0.0
+    for (gW, gb), (rW, rb), (mW, mb) in zip(grads, gref, mags):
+        for a, r, mg in ((gW, rW, mW), (gb, rb, mb)):
+            err = np.abs(a.astype(np.float64) - r)
+            assert np.all(err <= bound * mg + 1e-30), np.max(err / (mg + 1e-300))
+            worst = max(worst, float(np.max(err / (mg + 1e-300))))
+    print(f"worst |g - g_ref| / magnitude = {worst:.3e} (bound {bound:.3e})", flush=True)

@@ -77,3 +77,26 @@ def test_training_reduces_loss():
         _, g = mlp.gradients(params, X, T, 3)
         params = opt.step(params, g, 1e-2)
     assert mlp.loss_of(params, X, T, 3) < 0.2 * l0
+
+
+def test_gradient_magnitudes_bound_the_gradients():
+    """Each magnitude is a sum of absolute values of the gradient's own terms
+    (over a superset of the active units): it bounds |gradient| entry by
+    entry, with equality when every term has one sign."""
+    from paper_2508_16094_amd import workloads as w
+    dims = [8, 32, 24, 20]
+    params = w.mlp_init(dims, 5)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((17, 8))
+    T = np.concatenate([rng.uniform(1, 9, (17, 12)), rng.uniform(0.1, 2, (17, 8))], axis=1)
+    _, g = mlp.gradients(params, X, T, 12)
+    mags = mlp.gradient_magnitudes(params, X, T, 12)
+    for (gW, gb), (mW, mb) in zip(g, mags):
+        assert np.all(np.abs(gW) <= mW * (1 + 1e-12) + 1e-300)
+        assert np.all(np.abs(gb) <= mb * (1 + 1e-12) + 1e-300)
+    # a batch of one with one output: every term of the last layer's weight
+    # gradient is a single product, so magnitude = |gradient|
+    one = [(rng.standard_normal((1, 8)), np.zeros(1))]
+    _, g1 = mlp.gradients(one, np.abs(X[:1]), T[:1, :1], 1)
+    m1 = mlp.gradient_magnitudes(one, np.abs(X[:1]), T[:1, :1], 1)
+    assert np.allclose(np.abs(g1[0][0]), m1[0][0], rtol=1e-14)

@@ -199,3 +199,121 @@ def test_p6_amalgamation_rejects_too_many_zeros():
     assert fund == [0, 10]
     assert symbolic.amalgamate(fund, parent, cc) == [0, 10, 20]
     assert symbolic.amalgamate(fund, parent, cc, (1 << 30, 20, 1, 10)) == [0, 20]
+
+
+# ------------------------------------------------- multilevel bisection
+def _geometric_adj(n, k, seed):
+    """k-nearest-neighbour graph of n random points in the unit square."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    P = rng.random((n, 2))
+    _, nb = cKDTree(P).query(P, k + 1)
+    r = np.repeat(np.arange(n), k)
+    S = sp.csr_matrix((np.ones(n * k), (r, nb[:, 1:].ravel())), shape=(n, n))
+    S = ((S + S.T) > 0).astype(float).tocsr()
+    return symbolic.adjacency_from_sym(S, n)
+
+
+def _local(adj, n):
+    return symbolic._ml_local_graph(adj, list(range(n)), [True] * n)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ml_coarsening_invariants(seed):
+    """Heavy-edge matching: each coarse vertex has one or two adjacent
+    members, the matching is maximal (no edge joins two unmatched vertices),
+    vertex weight is preserved, and the coarse edge weights are exactly the
+    fine edges between different coarse vertices."""
+    adj = _geometric_adj(300, 5, seed)
+    nbrs, ew, vw = _local(adj, 300)
+    for _ in range(3):
+        cmap, cn, ce, cw = symbolic._ml_coarsen(nbrs, ew, vw)
+        members = {}
+        for v, c in enumerate(cmap):
+            members.setdefault(c, []).append(v)
+        assert sorted(members) == list(range(len(cw)))
+        for c, ms in members.items():
+            assert len(ms) in (1, 2)
+            if len(ms) == 2:
+                assert ms[1] in nbrs[ms[0]]
+            assert cw[c] == sum(vw[v] for v in ms)
+        singles = {ms[0] for ms in members.values() if len(ms) == 1}
+        for v in singles:
+            assert not any(u in singles for u in nbrs[v])
+        want = {}
+        for v in range(len(vw)):
+            for u, wt in zip(nbrs[v], ew[v]):
+                if cmap[u] != cmap[v]:
+                    want[(cmap[v], cmap[u])] = want.get((cmap[v], cmap[u]), 0) + wt
+        got = {(c, u): wt for c in range(len(cw)) for u, wt in zip(cn[c], ce[c])}
+        assert got == want
+        nbrs, ew, vw = cn, ce, cw
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ml_refinement_is_locally_optimal(seed):
+    """After refinement no single move has positive gain within the balance
+    bound, the parts hold every vertex, and the cut never grew."""
+    adj = _geometric_adj(200, 4, 10 + seed)
+    nbrs, ew, vw = _local(adj, 200)
+    part0 = symbolic._ml_initial(nbrs, vw)
+
+    def cut(part):
+        return sum(wt for v in range(200) for u, wt in zip(nbrs[v], ew[v]) if part[u] != part[v]) // 2
+    c0 = cut(part0)
+    part = symbolic._ml_refine(nbrs, ew, vw, list(part0))
+    assert cut(part) <= c0
+    total = sum(vw)
+    maxw = symbolic.ML_BAL_NUM * total // symbolic.ML_BAL_DEN
+    pw = [sum(vw[v] for v in range(200) if part[v] == p) for p in (0, 1)]
+    for v in range(200):
+        ext = sum(wt for u, wt in zip(nbrs[v], ew[v]) if part[u] != part[v])
+        inn = sum(wt for u, wt in zip(nbrs[v], ew[v]) if part[u] == part[v])
+        assert not (ext - inn > 0 and pw[1 - part[v]] + vw[v] <= maxw), v
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ml_separator_separates(seed):
+    """lower, upper and the separator partition the component, no edge joins
+    lower to upper, and every separator vertex touches the other part."""
+    n = 400 + 100 * seed
+    adj = _geometric_adj(n, 5, 20 + seed)
+    inset = [True] * n
+    comps = symbolic._components(adj, list(range(n)), inset)
+    comp = max(comps, key=len)
+    inset = [False] * n
+    for v in comp:
+        inset[v] = True
+    lower, upper, sep = symbolic.multilevel_separator(adj, comp, inset)
+    assert sorted(lower + upper + sep) == comp
+    lo = set(lower)
+    for v in upper:
+        assert not any(u in lo for u in adj[v])
+    up = set(upper)
+    for s in sep:
+        assert any(inset[u] and (u in lo or u in up) for u in adj[s])
+
+
+def test_ml_barbell_is_cut_at_one_vertex():
+    """Two 30-cliques joined by a path of 5 vertices: the multilevel
+    separator is a single path vertex (the optimum), and the ordering
+    eliminates the two cliques before it."""
+    A, P, B = list(range(30)), list(range(30, 35)), list(range(35, 65))
+    edges = [(a, b) for X in (A, B) for a in X for b in X if a < b]
+    edges += [(29, 30), (30, 31), (31, 32), (32, 33), (33, 34), (34, 35)]
+    adj = _adj_from_edges(65, edges)
+    lower, upper, sep = symbolic.multilevel_separator(adj, list(range(65)), [True] * 65)
+    assert len(sep) == 1 and sep[0] in P
+    nd = symbolic.nested_dissection(adj, 65, leaf=16, method="multilevel")
+    assert nd[-1] == sep[0]
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_ml_ordering_fills_less_than_level_ordering(seed):
+    """The reason for the multilevel rule: on irregular (geometric) graphs its
+    separators are far smaller than BFS level sets, and so is the fill."""
+    n = 3000
+    adj = _geometric_adj(n, 6, 40 + seed)
+    a = symbolic.analyze(adj, n)
+    b = symbolic.analyze(adj, n, method="multilevel")
+    assert b["nnz_L"] < 0.8 * a["nnz_L"] and b["flops"] < 0.5 * a["flops"]
