@@ -30,7 +30,10 @@ def test_warm_start_from_trained_mlp():
     pb = warm.ParamBatch(pq, chunk=64)
     res, X, Lm, _ = pb.solve(th_train)
     assert all(r["status"] == 0 for r in res)
-    model = L.MlpModel([8, 64, 64, n + m], n_x=n, max_batch=64).bind()
+    # x term weighted 1e4 as in the benchmark: with weight 1 the log-lambda
+    # term dominates and x is left unfitted (warm starts then take more
+    # iterations than cold ones)
+    model = L.MlpModel([8, 64, 64, n + m], n_x=n, max_batch=64, x_weight=1e4).bind()
     model.set_params(w.mlp_init([8, 64, 64, n + m]))
     losses = warm.train(model, th_train, np.concatenate([X, Lm], axis=1), steps=300, batch=64, lr=3e-3)
     print("loss", losses[0], losses[-1], flush=True)
