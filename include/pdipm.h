@@ -303,6 +303,19 @@ int ipm_get_patterns(ipm_handle* h, int64_t* j_rowptr, int32_t* j_colind,
  * Returns the status (>= 0: best iterate kept) or an error code. */
 int ipm_solve(ipm_handle* h, const ipm_start* start, ipm_result* res);
 
+/* ipm_solve without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The handle is bound to the library's
+ * own static device array of 64 MiB (one per GPU, held until the process
+ * ends) and solved there; nothing is allocated.  Every call re-uploads the
+ * handle's data into the array, so calls with different handles follow
+ * one another safely, but calls that overlap on one GPU race, and
+ * ipm_get_solution must come before the next call on that GPU.  Errors:
+ * OUT_OF_MEMORY when ipm_workspace_query exceeds 64 MiB, INVALID_ARG on a
+ * standalone or batch handle or when the current device is not the one
+ * current at create; otherwise as ipm_solve. */
+int ipm_solve_static(ipm_handle* h, const ipm_start* start, ipm_result* res);
+
 /* Precision of the next ipm_solve on this handle: PDIPM_FP64, or
  * PDIPM_FP32 (FP32 factor, FP64 refinement).  The workspace must hold that
  * precision's factor: FP64 needs precision FP64 or fp64_fallback at create,

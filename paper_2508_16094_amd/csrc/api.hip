@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1248,6 +1249,36 @@ int batch_autotune(ipm_handle* h, int32_t* chosen, double* ms_out, int reps) {
   return PDIPM_OK;
 }
 
+// ------------------------------------------------ allocation-free solve
+// The device memory of ipm_solve_static: one array per GPU that the library
+// runs on, held until the process ends and shared by every such call on
+// that GPU (each call re-uploads its handle's data; calls that overlap on
+// one GPU race).  Host code never passes the array's name to a kernel or a
+// copy: it uses the address hipGetSymbolAddress returns on each device.
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
+constexpr int STATIC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[STATIC_MAX_DEVICES] = {};
+
+// Address of the current device's array (looked up once per device).
+int static_scratch(ipm_handle* h, void** out) {
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev != h->device) return fail(h, PDIPM_ERR_INVALID_ARG, "call ipm_solve_static on the handle's device");
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(h, PDIPM_ERR_INVALID_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(h, PDIPM_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PDIPM_OK;
+}
+
 }  // namespace
 
 // ================================================================= ABI
@@ -1668,6 +1699,23 @@ int ipm_get_patterns(ipm_handle* h, int64_t* jrp, int32_t* jci, int64_t* hrp, in
   if (hrp) memcpy(hrp, h->hp.hp.data(), bytes_of(h->hp.hp));
   if (hci) memcpy(hci, h->hp.hc.data(), bytes_of(h->hp.hc));
   return PDIPM_OK;
+}
+
+int ipm_solve_static(ipm_handle* h, const ipm_start* st, ipm_result* res) {
+  if (!h) return PDIPM_ERR_INVALID_ARG;
+  if (h->standalone || h->bcount > 0) return fail(h, PDIPM_ERR_INVALID_ARG, "needs an ipm_create handle");
+  if (h->ws_need > STATIC_WS_BYTES)
+    return fail(h, PDIPM_ERR_OUT_OF_MEMORY, "workspace needs " + std::to_string(h->ws_need) +
+                                                " bytes; the static array holds " + std::to_string(STATIC_WS_BYTES));
+  void* p = nullptr;
+  int rc = static_scratch(h, &p);
+  if (rc) return rc;
+  // every call binds afresh: another handle may have used the array since
+  h->ws = (char*)p;
+  h->ws_bytes = STATIC_WS_BYTES;
+  h->profiling = false;
+  if ((rc = bind_workspace(h))) return rc;
+  return run_ipm(h, st, res);
 }
 
 int ipm_set_precision(ipm_handle* h, int precision) {

@@ -105,6 +105,7 @@ _SIGS = {
     "ipm_get_patterns": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "ipm_solve": (ctypes.c_int, [_p, _p, _p]),
     "ipm_set_precision": (ctypes.c_int, [_p, ctypes.c_int]),
+    "ipm_solve_static": (ctypes.c_int, [_p, _p, _p]),
     "ipm_get_solution": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, ctypes.c_int]),
     "ipm_set_profiling": (ctypes.c_int, [_p, ctypes.c_int]),
     "ipm_get_profile": (ctypes.c_int, [_p, _p]),
@@ -381,6 +382,15 @@ class IpmSolver(_Handle):
         out = np.empty(self.stats()["nnz_K"], np.float64)
         self._check(lib().kkt_get_values(self.h, _ptr(out)), "kkt_get_values")
         return out
+
+    def solve_static(self, start=None):
+        """ipm_solve_static: solve in the library's static device array (no
+        workspace tensor); start as in solve()."""
+        res = ipm_result()
+        st = self._start(start)
+        rc = lib().ipm_solve_static(self.h, ctypes.byref(st) if st is not None else None, ctypes.byref(res))
+        self._check(rc, "ipm_solve_static")
+        return {k: getattr(res, k) for k, _ in res._fields_}
 
     def set_precision(self, precision):
         self._check(lib().ipm_set_precision(self.h, int(precision)), "ipm_set_precision")
