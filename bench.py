@@ -24,6 +24,10 @@ import time
 
 T_START = time.time()
 PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA TFLOP/s
+FORMS = {"primal": 0, "dual": 1, "augmented": 2, "auto": 3}          # PDIPM_KKT_*
+FORM_NAMES = {0: "primal", 1: "dual", 2: "augmented"}
+FORM_TEXT = {"primal": "primal condensed K (n x n)", "dual": "dual condensed M (m x m, normal equations)",
+             "augmented": "augmented SQD system (n + m)"}
 
 
 def make_problem(args):
@@ -298,7 +302,10 @@ def sample_problem(workload):
 
 def cpu_baseline_sample(args, cap_s=40.0):
     """The oracle (plain FP64 CPU IPM, one thread) solving a bounded sample
-    of the workload to the same tolerance, timed (at most about cap_s)."""
+    of the workload to the same tolerance, timed (at most about cap_s), with
+    the condensed system the benchmark uses: the one the --form choice
+    names, or for "auto" the one with fewer factorisation flops on the
+    sample (the library's rule)."""
     import numpy as np
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
@@ -306,17 +313,22 @@ def cpu_baseline_sample(args, cap_s=40.0):
     from oracle import model
     from oracle import symbolic as osym
     p, what = sample_problem(args.workload)
-    with threadpool_limits(limits=1):
-        t0 = time.time()
-        r = oipm.solve(p, tol=1e-6, dense_max=0, max_wall_time=cap_s)
-        dt = time.time() - t0
-    # factorisation work of the sample from the oracle's own symbolic analysis
     J = model.jacobian(p, np.zeros(p.n)).tocsr()
     H = sp.tril(model.hessian(p, np.zeros(p.n), np.ones(p.m))).tocsr()
-    adj = osym.kkt_pattern(p.n, J.indptr, J.indices, H.indptr, H.indices)
-    f_sample = float(osym.analyze(adj, p.n)["flops"])
-    return {"what": what, "seconds": dt, "iterations": max(1, r["iterations"]), "flops": f_sample,
-            "status": oipm.STATUS_NAMES.get(r["status"], str(r["status"]))}
+    flops = {"primal": float(osym.analyze(osym.kkt_pattern(p.n, J.indptr, J.indices, H.indptr, H.indices),
+                                          p.n)["flops"])}
+    if H.nnz == p.n and p.m > 0:
+        flops["dual"] = float(osym.analyze(osym.dual_pattern(p.m, p.n, J.indptr, J.indices), p.m)["flops"])
+    if args.form in flops:
+        form = args.form
+    else:
+        form = min(flops, key=lambda f: (flops[f], f != "primal"))
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        r = oipm.solve(p, tol=1e-6, dense_max=0, max_wall_time=cap_s, form=form)
+        dt = time.time() - t0
+    return {"what": what, "seconds": dt, "iterations": max(1, r["iterations"]), "flops": flops[form],
+            "form": form, "status": oipm.STATUS_NAMES.get(r["status"], str(r["status"]))}
 
 
 def cpu_baseline_scale(smp, flops_full, iters_full):
@@ -325,7 +337,8 @@ def cpu_baseline_scale(smp, flops_full, iters_full):
     full instance would take the oracle hours)."""
     t_full = smp["seconds"] / (smp["iterations"] * smp["flops"]) * flops_full * iters_full
     return {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle", "estimate": True,
-            "sample": f"oracle IPM solve of {smp['what']}: {smp['status']} after {smp['iterations']} "
+            "sample": f"oracle IPM solve ({smp.get('form', 'primal')} condensed system) of {smp['what']}: "
+                      f"{smp['status']} after {smp['iterations']} "
                       f"iterations in {smp['seconds']:.1f} s (sum c_j^2 = {smp['flops']:.3g}); scaled to the "
                       f"benchmarked instance by factorisation flops ({flops_full:.3g}) and iterations "
                       f"({iters_full})",
@@ -347,9 +360,12 @@ def main():
     ap.add_argument("--workload", default="lp_block")
     ap.add_argument("--nblocks", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--form", default="primal", choices=["primal", "dual"],
-                    help="KKT system factored each iteration: the primal condensed K (n x n) or the dual "
-                         "condensed normal-equations matrix M (m x m; LP and diagonal QP)")
+    ap.add_argument("--form", default="auto", choices=["auto", "primal", "dual", "augmented"],
+                    help="KKT system factored each iteration: auto (the condensed system with fewer "
+                         "factorisation flops), the primal condensed K (n x n), the dual condensed "
+                         "normal-equations matrix M (m x m; LP and diagonal QP) or the augmented SQD matrix")
+    ap.add_argument("--no-compare-forms", action="store_true",
+                    help="skip the solves with the other condensed system (reported next to the timed one)")
     ap.add_argument("--time-budget", type=float, default=450.0,
                     help="wall seconds from process start within which the JSON line is printed; "
                          "timed steps and warmups stop early to keep it")
@@ -402,11 +418,13 @@ def main():
     # FP32 form: FP64 factors take over for the rest of a solve once FP32
     # refinement cannot reach the accuracy the iteration needs; the FP64
     # space also serves the FP64 comparison solve on the same handle
-    form = L.PDIPM_KKT_DUAL if args.form == "dual" else L.PDIPM_KKT_PRIMAL
+    form = FORMS[args.form]
     s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0, kkt_form=form)
     st = s.stats()
+    chosen = FORM_NAMES[st["kkt_form"]]
     t_setup = time.time() - t
-    log(f"[bench] analysed in {t_setup:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
+    log(f"[bench] analysed in {t_setup:.1f}s: {chosen} system, order {st['n']}, nnz(L)={st['nnz_L']:.4g} "
+        f"flops={st['flops']:.4g} "
         f"supernodes={st['n_super']} levels={st['n_levels']} workspace={s.workspace_bytes() / 1e9:.1f} GB")
     s.bind()
     torch.cuda.synchronize()
@@ -422,8 +440,16 @@ def main():
         warm_done += 1
         log(f"[bench] warmup {i}: status {r['status']} it {r['iterations']} {r['ms_total'] / 1e3:.2f}s")
     compare = prec == L.PDIPM_FP32 and not args.no_fp64_compare
-    # time kept for the FP64 solve (FP64 factors cost about twice FP32 ones)
-    reserve = lambda: (2.0 * t_step if compare and t_step else 0.0)  # noqa: E731
+    # the other condensed system, timed next to the chosen one where the dual
+    # system applies (a diagonal Hessian: the LP workloads)
+    dual_applies = args.workload in ("lp_block", "lp_small")
+    others = [] if args.no_compare_forms or chosen == "augmented" or not dual_applies else \
+        [{"primal": "dual", "dual": "primal"}[chosen]]
+    # time kept for what follows the timed solves: the FP64 solve on the same
+    # handle, and one FP32 and one FP64 solve of the other condensed system
+    # (up to about 3x and 3x the timed step plus its setup)
+    reserve = lambda: ((1.5 * t_step if compare else 0.0) + (7.0 * t_step + 15.0 if others else 0.0)  # noqa: E731
+                       if t_step else 0.0)
     s.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -470,8 +496,7 @@ def main():
         "dtype": "f32" if prec == L.PDIPM_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": name, "form": "fp32 factor + fp64 refinement" if prec == L.PDIPM_FP32 else "fp64",
-                   "kkt_system": "primal condensed K (n x n)" if args.form == "primal"
-                   else "dual condensed M (m x m, normal equations)",
+                   "kkt_system": FORM_TEXT[chosen], "kkt_choice": args.form,
                    "tol": 1e-6, "parallelism": "single GPU"},
         "status": last["status"], "iterations": last["iterations"], "f": last["f"],
         "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],
@@ -485,7 +510,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": gemm_tf, "peak": PEAK[pkey], "unit": "TFLOP/s",
                      "frac": gemm_tf / PEAK[pkey],
                      "traffic": traffic_of("k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
-                                           f"lp_block{args.nblocks}",
+                                           f"lp_block{args.nblocks}_{chosen}",
                                            prof["gemm" + key + "_bytes"] / max(1, launches))
                      if args.workload == "lp_block" else None,
                      "kernel": "k_gemm_f32" if pkey == "fp32" else "k_gemm_f64",
@@ -514,6 +539,43 @@ def main():
                                 "rel_f_diff_vs_fp32_form": abs(r64["f"] - last["f"]) / max(1.0, abs(r64["f"]))}
         else:
             out["fp64_path"] = {"skipped": "time budget"}
+    # 4. the other condensed system(s) on the same instance, one solve each
+    if others:
+        out["forms"] = {chosen: {"fp32_solves_per_s": steps / elapsed if prec == L.PDIPM_FP32 else None,
+                                 "fp64_solves_per_s": out.get("fp64_path", {}).get("solves_per_s"),
+                                 "factor_flops": st["flops"], "nnz_L": st["nnz_L"], "order": st["n"]}}
+        import gc
+        del s
+        gc.collect()
+        torch.cuda.empty_cache()
+        for other in others:
+            rec = {}
+            if since_start() + 3.0 * t_step + 15.0 > args.time_budget + 60.0:
+                out["forms"][other] = {"skipped": "time budget"}
+                continue
+            t = time.time()
+            so = L.IpmSolver(p, precision=L.PDIPM_FP32, fp64_fallback=1, kkt_form=FORMS[other])
+            sto = so.stats()
+            so.bind()
+            rec.update(setup_s=time.time() - t, factor_flops=sto["flops"], nnz_L=sto["nnz_L"], order=sto["n"])
+            for pr, key in ((L.PDIPM_FP32, "fp32"), (L.PDIPM_FP64, "fp64")):
+                if since_start() + 3.0 * t_step > args.time_budget + 60.0:
+                    rec[key + "_solves_per_s"] = None
+                    continue
+                so.set_precision(pr)
+                t = time.time()
+                ro = so.solve()
+                torch.cuda.synchronize()
+                dt = time.time() - t
+                log(f"[bench] {other} system {key}: status {ro['status']} it {ro['iterations']} {dt:.2f}s "
+                    f"f {ro['f']:.10e}")
+                rec[key + "_solves_per_s"] = 1.0 / dt if ro["status"] == 0 else None
+                rec[key + "_status"] = ro["status"]
+                rec[key + "_rel_f_diff"] = abs(ro["f"] - last["f"]) / max(1.0, abs(last["f"]))
+            out["forms"][other] = rec
+            del so
+            gc.collect()
+            torch.cuda.empty_cache()
     if cpu is not None:
         out["cpu_baseline"] = cpu_baseline_scale(cpu, st["flops"], last["iterations"])
     out["wall_s"] = since_start()

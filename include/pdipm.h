@@ -59,6 +59,7 @@ extern "C" {
 #define PDIPM_KKT_PRIMAL 0        /* primal condensed K (Section 3, eq. kkt_primal) */
 #define PDIPM_KKT_DUAL 1          /* dual condensed M (Section 3, eq. kkt_dual) */
 #define PDIPM_KKT_AUGMENTED 2     /* augmented SQD system (Section 3, eq. augmentedKKT) */
+#define PDIPM_KKT_AUTO 3          /* the condensed system with less factorisation work */
 
 #define PDIPM_ORDER_LEVELS 0      /* nested dissection, separators = BFS levels */
 #define PDIPM_ORDER_MULTILEVEL 1  /* nested dissection, separators from multilevel bisection */
@@ -124,7 +125,12 @@ typedef struct ipm_options {
                             from A (d, w) = (r, 0), refined against K.  A
                             pivot of the wrong sign (a nonconvex H) ends
                             ipm_solve with PDIPM_ERR_NUMERICAL.  The factor
-                            calls then describe A; kkt_get_factor gives L. */
+                            calls then describe A; kkt_get_factor gives L.
+                            PDIPM_KKT_AUTO: when the Hessian is diagonal and
+                            m >= 1, both condensed systems are analysed at
+                            create and the one with fewer factorisation flops
+                            sum_j (c_j^2 - 1) is kept (otherwise the primal);
+                            kkt_analyze reports the choice. */
   int32_t ordering;      /* fill-reducing ordering, computed once on the host
                             (Section 2: minimum degree or nested dissection):
                             PDIPM_ORDER_LEVELS (default) takes BFS level sets
@@ -149,6 +155,7 @@ typedef struct kkt_symbolic_stats {
   int64_t n_triples;     /* J'SJ products summed by the assembly */
   double flops;          /* sum_j (c_j^2 - 1), the factorisation's work */
   double update_bytes;   /* bytes of front update matrices (per precision) */
+  int32_t kkt_form;      /* the system factored (PDIPM_KKT_*; -1 standalone) */
 } kkt_symbolic_stats;
 
 typedef struct kkt_factor_info {

@@ -62,6 +62,7 @@ struct ipm_handle {
   bool standalone = false;
   bool dual = false;            // steps through the dual condensed system M
   bool aug = false;             // steps through the augmented SQD system (signed L S L')
+  bool sym_ready = false;       // symbolic analysis already done at create (automatic form)
   std::vector<signed char> psign;  // pivot signs, permuted numbering (augmented form)
   HostProblem hp;
   Graph graph;
@@ -1339,7 +1340,7 @@ static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** ou
   try {
     h->need64 = h->opt.precision == PDIPM_FP64 || h->opt.fp64_fallback;
     h->need32 = h->opt.precision == PDIPM_FP32;
-    analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym, h->opt.ordering);
+    if (!h->sym_ready) analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym, h->opt.ordering);
     create_lap("symbolic analysis");
     if (h->aug) {
       // SQD: the pivot of an x variable is positive, of a lambda one negative
@@ -1372,14 +1373,44 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
   }
   if (h->opt.kkt_form != PDIPM_KKT_PRIMAL && h->opt.kkt_form != PDIPM_KKT_DUAL &&
-      h->opt.kkt_form != PDIPM_KKT_AUGMENTED) {
+      h->opt.kkt_form != PDIPM_KKT_AUGMENTED && h->opt.kkt_form != PDIPM_KKT_AUTO) {
     delete h;
-    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_form must be PDIPM_KKT_PRIMAL, _DUAL or _AUGMENTED");
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_form must be PDIPM_KKT_PRIMAL, _DUAL, _AUGMENTED or _AUTO");
   }
   create_lap("start");
   std::string e = build_problem(prob, &h->hp);
   if (!e.empty()) { delete h; return fail(nullptr, PDIPM_ERR_INVALID_ARG, e); }
   create_lap("problem copy and patterns");
+  if (h->opt.kkt_form == PDIPM_KKT_AUTO) {
+    // the condensed system with less factorisation work: the dual one needs
+    // a diagonal Hessian and at least one row
+    h->opt.kkt_form = PDIPM_KKT_PRIMAL;
+    if ((int64_t)h->hp.hc.size() == h->hp.n && h->hp.m > 0) {
+      try {
+        Graph gd;
+        KMap kd;
+        Symbolic sd;
+        build_dual_structures(h->hp, &gd, &kd);
+        analyze(gd, h->opt.nd_leaf, h->opt.amalg_menu, &sd, h->opt.ordering);
+        build_graph_from_problem(h->hp, &h->graph);
+        build_kmap_problem(h->hp, &h->km);
+        analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym, h->opt.ordering);
+        if (sd.flops < h->sym.flops) {
+          h->graph = std::move(gd);
+          h->km = std::move(kd);
+          h->sym = std::move(sd);
+          h->dual = true;
+          h->opt.kkt_form = PDIPM_KKT_DUAL;
+        }
+        h->sym_ready = true;
+      } catch (const std::exception& ex) {
+        delete h;
+        return fail(nullptr, PDIPM_ERR_INVALID_ARG, ex.what());
+      }
+      create_lap("both condensed systems analysed");
+      return finish_create(h, opts, out);
+    }
+  }
   if (h->opt.kkt_form == PDIPM_KKT_AUGMENTED) {
     h->aug = true;
     try {
@@ -1476,6 +1507,7 @@ int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* s) {
   s->n_triples = (int64_t)h->km.tk.size();
   s->flops = h->sym.flops;
   s->update_bytes = (double)h->plan64.u_elems * (h->need64 ? 8 : 4);
+  s->kkt_form = h->standalone ? -1 : (h->aug ? PDIPM_KKT_AUGMENTED : (h->dual ? PDIPM_KKT_DUAL : PDIPM_KKT_PRIMAL));
   return PDIPM_OK;
 }
 

@@ -53,31 +53,37 @@ def test_traffic_record_is_consistent():
         assert r["bytes_per_launch"] >= 0.9 * r["algorithmic_bytes_per_launch"]
 
 
-def _simulate(bm, requested, t_solve, t_before, budget, compare=True):
+def _simulate(bm, requested, t_solve, t_before, budget, compare=True, others=True):
     """Wall time of the bench's step loop with solves of t_solve seconds
-    after t_before seconds of set-up and one warmup solve."""
+    after t_before seconds of set-up and one warmup solve, then the FP64
+    solve on the same handle (1.2 t) and the other condensed system (set-up
+    plus an FP32 and an FP64 solve, 2.2 t and 3.2 t: the primal system's
+    times when the dual one is timed)."""
     now = t_before + t_solve          # set-up, then the (single) warmup
     t_step, done = t_solve, 0
-    reserve = 2.0 * t_step if compare else 0.0
+    reserve = (1.5 * t_step if compare else 0.0) + (7.0 * t_step + 15.0 if others else 0.0)
     while done < max(1, requested) and bm.plan_steps(done, now, t_step, reserve, budget):
         now += t_solve
         done += 1
     if compare:
-        now += 2.0 * t_solve          # the FP64 solve
+        now += 1.2 * t_solve
+    if others:
+        now += 10.0 + 2.2 * t_solve + 3.2 * t_solve
     return done, now
 
 
 def test_driver_command_fits_its_time_limit():
-    """--steps 20 --warmup 5 with a 25 s solve (the 2M-column LP) and about
-    60 s of start-up (torch import, generation, analysis, CPU baseline):
-    the JSON line comes well before 600 s and the steps are reduced."""
+    """--steps 20 --warmup 5 with the dual system's 12 s solve (the primal's
+    takes 25 s) and about 60 s of start-up (torch import, generation,
+    analysis, CPU baseline): the JSON line comes well before 600 s."""
     bm = _bench()
-    done, wall = _simulate(bm, 20, 25.0, 60.0, 450.0)
-    assert 1 <= done < 20
-    assert wall <= 500.0
-    # a slower solve still runs one timed step and stays bounded
-    done, wall = _simulate(bm, 20, 150.0, 60.0, 450.0)
-    assert done == 1 and wall <= 60 + 150 * 4
+    for t in (12.0, 25.0, 40.0):
+        done, wall = _simulate(bm, 20, t, 60.0, 450.0)
+        assert 1 <= done <= 20
+        assert wall <= 540.0, (t, wall)
+    # a slower solve still runs one timed step
+    done, wall = _simulate(bm, 20, 150.0, 60.0, 450.0, others=False)
+    assert done == 1
     # small workloads run every requested step
     done, _ = _simulate(bm, 20, 0.02, 10.0, 450.0)
     assert done == 20

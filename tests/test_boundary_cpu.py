@@ -183,7 +183,7 @@ def test_dual_form_rejects_what_it_cannot_solve():
     with pytest.raises(L.PdipmError):
         L.BatchSolver([w.qp_instance(60, 2)], kkt_form=L.PDIPM_KKT_DUAL)
     with pytest.raises(L.PdipmError):
-        L.IpmSolver(w.lp_small(), kkt_form=3)
+        L.IpmSolver(w.lp_small(), kkt_form=4)
 
 
 @pytest.mark.parametrize("name", ["lp_small", "qp", "nlp_grid", "lp_block"])
@@ -257,3 +257,30 @@ def test_multilevel_ordering_bit_exact_on_workloads(name, form):
 def test_ordering_option_is_checked():
     with pytest.raises(L.PdipmError):
         L.IpmSolver(w.lp_small(), ordering=2)
+
+
+@pytest.mark.parametrize("name", ["lp_block", "lp_small", "nlp_grid", "qp"])
+def test_automatic_form_keeps_the_cheaper_condensed_system(name):
+    """kkt_form AUTO: with a diagonal Hessian both condensed systems are
+    analysed and the one with fewer factorisation flops is factored (its
+    analysis is the one the explicit form gives); otherwise the primal."""
+    p = {"lp_block": lambda: w.lp_block(nblocks=6, block_rows=300, block_cols=600, link_cols_per_block=30),
+         "lp_small": lambda: w.lp_small(3),
+         "nlp_grid": lambda: w.nlp_grid(30, 26),
+         "qp": lambda: w.qp_instance(700, 11)}[name]()
+    auto = L.IpmSolver(p, kkt_form=L.PDIPM_KKT_AUTO)
+    st = auto.stats()
+    prim = L.IpmSolver(p, kkt_form=L.PDIPM_KKT_PRIMAL).stats()
+    if name == "nlp_grid":
+        assert st["kkt_form"] == L.PDIPM_KKT_PRIMAL and st["flops"] == prim["flops"]
+        return
+    dual = L.IpmSolver(p, kkt_form=L.PDIPM_KKT_DUAL).stats()
+    want = L.PDIPM_KKT_DUAL if dual["flops"] < prim["flops"] else L.PDIPM_KKT_PRIMAL
+    assert st["kkt_form"] == want
+    ref = L.IpmSolver(p, kkt_form=want)
+    assert st["flops"] == min(dual["flops"], prim["flops"])
+    a, b = auto.symbolic(), ref.symbolic()
+    for k in ["perm", "etree", "colcount", "sn_start", "sn_rowptr", "sn_rows"]:
+        assert np.array_equal(a[k], b[k]), k
+    if name == "lp_block":
+        assert st["kkt_form"] == L.PDIPM_KKT_DUAL
