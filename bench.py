@@ -140,6 +140,11 @@ def bench_batch(args, log):
     return 0
 
 
+# stated sizes of the learned warm-start workload: training solves, fresh
+# parameter vectors
+WARM_TRAIN, WARM_TEST = 50000, 10000
+
+
 def bench_warm(args, log):
     """Learned warm start on the parametric QP (100 x 200 grid, 64 parameters):
     training set solved by the batched solver, MLP 64-512-512-(n+m) trained
@@ -193,7 +198,11 @@ def bench_warm(args, log):
                                f"MLP 64-512-512-{n + m} trained on {int(keep.sum())} solved instances, "
                                f"tested on {len(th_test)} fresh ones (batches of {args.chunk})",
                    "form": "warm start (bf16 MLP) + batched fp64 IPM", "tol": 1e-6,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "scale": ("stated sizes" if args.n_train >= WARM_TRAIN and args.n_test >= WARM_TEST else
+                             f"reduced: {args.n_train} of {WARM_TRAIN} training and {args.n_test} of "
+                             f"{WARM_TEST} test instances (--n-train {WARM_TRAIN} --n-test {WARM_TEST} "
+                             f"runs the stated sizes)")},
         "cold": {"solves_per_s": len(th_test) / t_cold, "iterations_mean": float(ic.mean()),
                  "iterations_p95": float(np.percentile(ic, 95))},
         "warm": {"solves_per_s": value, "iterations_mean": float(iw.mean()),

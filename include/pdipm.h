@@ -103,6 +103,11 @@ typedef struct ipm_options {
                             the accuracy an iteration needs (default 1) */
   int32_t use_graphs;    /* batched solve: 1 replays captured HIP graphs
                             (default), 0 launches the same kernels eagerly */
+  int32_t graph_iters;   /* batched solve with graphs: Newton iterations held
+                            by the one captured graph, replayed until every
+                            instance has ended (default 20, 1 to 1000);
+                            iterations the batch no longer needs cost only
+                            their gated launches */
   int32_t kkt_form;      /* PDIPM_KKT_PRIMAL (default): factor the primal
                             condensed K (n x n).  PDIPM_KKT_DUAL: factor the
                             dual condensed (normal-equations) matrix

@@ -132,7 +132,7 @@ struct ipm_handle {
   PlanCaps cap64, cap32;
   BatchDev bd{};
   hipStream_t own_stream = nullptr;
-  hipGraphExec_t gstats = nullptr, gstep[2] = {nullptr, nullptr};
+  hipGraphExec_t gsolve = nullptr;  // whole batched iterations, one graph
   struct BOff { size_t xoff, roff, ix, ir, nc, lp, st, ist, flags; } bo{};
 };
 
@@ -362,6 +362,7 @@ int bind_workspace(ipm_handle* h) {
     d.ix = at<int32_t>(h, b.ix); d.ir = at<int32_t>(h, b.ir);
     d.nc = at<double>(h, b.nc); d.lp = at<int32_t>(h, b.lp);
     d.st = at<double>(h, b.st); d.ist = at<int32_t>(h, b.ist); d.flags = at<int32_t>(h, b.flags);
+    d.bad = at<int>(h, o.bad);
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   // device views
@@ -1002,16 +1003,18 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
 // analysis, assembly, factorisation and triangular solves treat them as
 // one matrix (instances are independent diagonal blocks, so every level of
 // the plan is one launch over all instances), while step lengths, centring
-// and termination are per instance.  Each iteration is two captured HIP
-// graphs: termination measures, then the Newton step.
+// and termination are per instance.  The whole solve is one captured HIP
+// graph of graph_iters iterations, replayed until every instance has ended:
+// a control kernel on the device decides, from device flags, whether the
+// next iteration runs and in which precision, and every other launch of the
+// graph reads its gate word first.
 
 int set_blocking(ipm_handle* h, int idx) {
   if (idx < 0 || idx >= (int)h->bcand.size()) return fail(h, PDIPM_ERR_INVALID_ARG, "blocking index out of range");
   build_plan(h->sym, 8, &h->plan64, h->bcand[idx]);
   build_plan(h->sym, 4, &h->plan32, h->bcand[idx]);
   h->bblocking = idx;
-  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
-    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  if (h->gsolve) { hipGraphExecDestroy(h->gsolve); h->gsolve = nullptr; }
   if (!h->ws_ready) return PDIPM_OK;
   int rc = upload_plans(h);
   if (rc) return rc;
@@ -1088,7 +1091,11 @@ void batch_step_ops(ipm_handle* h, int prec) {
   launch_batch_predict(P, h->bd, v, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, h->stream);
   launch_batch_targets(P, h->bd, h->dxa, h->dsa, h->dla, h->dzla, h->dzua, h->ts, h->tl, h->tu, h->stream);
   direction(h->ts, h->tl, h->tu, h->dx, h->ds, h->dl, h->dzl, h->dzu);
-  launch_batch_correct(P, h->bd, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->stream);
+  // an FP32 direction that missed its target is not taken: the instance
+  // repeats the iteration with FP64 factors (which the control step then
+  // switches to)
+  const int repeat = prec == PDIPM_FP32 && O.fp64_fallback && h->need64;
+  launch_batch_correct(P, h->bd, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, repeat, h->stream);
   launch_batch_update(P, h->bd, v, h->dx, h->ds, h->dl, h->dzl, h->dzu, h->stream);
   launch_batch_next(h->bd, h->stream);
 }
@@ -1120,7 +1127,7 @@ int batch_start(ipm_handle* h, const ipm_start* st) {
   IpmVecs& v = h->v;
   launch_copy(P.nnz_j, v.jv, P.ja, h->stream);
   launch_copy(P.nnz_h, v.hv, P.hq, h->stream);
-  launch_batch_init(h->bd, h->stream);
+  launch_batch_init(h->bd, h->opt.precision == PDIPM_FP64 ? 1 : 0, h->stream);
   if (st) {
     const hipMemcpyKind kd = st->memspace == PDIPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(h, hipMemcpyAsync(h->xhat, st->x, P.n * 8, kd, h->stream));
@@ -1143,54 +1150,61 @@ int run_batch(ipm_handle* h, const ipm_start* st, ipm_result* res, ipm_batch_inf
   const ipm_options& O = h->opt;
   ipm_batch_info I{};
   I.blocking = h->bblocking;
-  I.fp64_from = -1;
   if ((rc = batch_start(h, st))) return rc;
   const bool graphs = O.use_graphs != 0;
-  const auto tc = clk::now();
-  if (graphs && !h->gstats && (rc = capture(h, &h->gstats, [&] { batch_stats_ops(h); }))) return rc;
-  I.ms_capture += ms_since(tc);
-  bool stay64 = O.precision == PDIPM_FP64;
-  int it = 0;
+  const int allow64 = O.precision == PDIPM_FP32 && O.fp64_fallback && h->need64 ? 1 : 0;
+  const bool with32 = O.precision == PDIPM_FP32, with64 = O.precision == PDIPM_FP64 || allow64;
   int32_t hflags[BF_N];
-  int hbad = INT_MAX;
   bool timed_out = false;
-  while (true) {
-    if (graphs) HIPCHK(h, hipGraphLaunch(h->gstats, h->stream));
-    else batch_stats_ops(h);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(hflags, h->bd.flags, sizeof(hflags), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(&hbad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (graphs) I.graph_launches++;
-    if (it > 0) {
-      if (hbad != INT_MAX) I.factor_failures++;
-      if ((hflags[BF_REFINE_MISS] > 0 || hbad != INT_MAX) && !stay64 && O.fp64_fallback && h->need64) {
-        stay64 = true;
-        I.fp64_from = it;
-      }
-      if (hflags[BF_REFINE_MISS] > 0) I.refine_misses++;
+  if (graphs) {
+    if (!h->gsolve) {
+      const auto tc = clk::now();
+      rc = capture(h, &h->gsolve, [&] {
+        // each iteration holds the termination measures, the control step
+        // and both precisions' Newton steps, all gated by device flags
+        for (int k = 0; k < O.graph_iters; ++k) {
+          set_launch_gate(h->bd.flags + BF_RUN);
+          batch_stats_ops(h);
+          set_launch_gate(nullptr);
+          launch_batch_control(h->bd, O.max_iter, allow64, h->stream);
+          if (with32) { set_launch_gate(h->bd.flags + BF_RUN32); batch_step_ops(h, PDIPM_FP32); }
+          if (with64) { set_launch_gate(h->bd.flags + BF_RUN64); batch_step_ops(h, PDIPM_FP64); }
+        }
+        set_launch_gate(nullptr);
+      });
+      set_launch_gate(nullptr);
+      if (rc) return rc;
+      I.ms_capture += ms_since(tc);
     }
-    if (O.print_level > 0)
-      fprintf(stderr, "batch it %3d running %d refine-miss %d bad %d fac %s\n", it, hflags[BF_ACTIVE],
-              hflags[BF_REFINE_MISS], hbad == INT_MAX ? -1 : hbad, stay64 ? "fp64" : "fp32");
-    if (hflags[BF_ACTIVE] == 0 || it > O.max_iter) break;
-    if (ms_since(t0) > O.max_wall_time * 1e3) { timed_out = true; break; }
-    const int gi = stay64 ? 1 : 0;
-    const int sprec = stay64 ? PDIPM_FP64 : PDIPM_FP32;
-    if (graphs) {
-      if (!h->gstep[gi]) {
-        const auto tg = clk::now();
-        if ((rc = capture(h, &h->gstep[gi], [&] { batch_step_ops(h, sprec); }))) return rc;
-        I.ms_capture += ms_since(tg);
-      }
-      HIPCHK(h, hipGraphLaunch(h->gstep[gi], h->stream));
+    while (true) {
+      HIPCHK(h, hipGraphLaunch(h->gsolve, h->stream));
       I.graph_launches++;
-    } else {
-      batch_step_ops(h, sprec);
+      HIPCHK(h, hipMemcpyAsync(hflags, h->bd.flags, sizeof(hflags), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      if (!hflags[BF_RUN]) break;
+      if (ms_since(t0) > O.max_wall_time * 1e3) { timed_out = true; break; }
     }
-    HIPCHK(h, hipGetLastError());
-    ++it;
+  } else {
+    // the same sequence launched directly, the host reading the control words
+    while (true) {
+      batch_stats_ops(h);
+      launch_batch_control(h->bd, O.max_iter, allow64, h->stream);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(hflags, h->bd.flags, sizeof(hflags), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      if (O.print_level > 0)
+        fprintf(stderr, "batch it %3d running %d refine-miss %d fac %s\n", hflags[BF_STEPS], hflags[BF_ACTIVE],
+                hflags[BF_REFINE_MISS], hflags[BF_RUN64] ? "fp64" : "fp32");
+      if (!hflags[BF_RUN]) break;
+      if (ms_since(t0) > O.max_wall_time * 1e3) { timed_out = true; break; }
+      batch_step_ops(h, hflags[BF_RUN64] ? PDIPM_FP64 : PDIPM_FP32);
+      HIPCHK(h, hipGetLastError());
+    }
   }
+  const int it = hflags[BF_ITER];
+  I.fp64_from = hflags[BF_FP64_FROM];
+  I.factor_failures = hflags[BF_FAILURES];
+  I.refine_misses = hflags[BF_MISSES];
   std::vector<double> hst((size_t)h->bcount * BST_N);
   std::vector<int32_t> hist((size_t)h->bcount * IST_N);
   HIPCHK(h, hipMemcpyAsync(hst.data(), h->bd.st, hst.size() * 8, hipMemcpyDeviceToHost, h->stream));
@@ -1300,6 +1314,7 @@ void ipm_default_options(ipm_options* o) {
   o->print_level = 0;
   o->fp64_fallback = 1;
   o->use_graphs = 1;
+  o->graph_iters = 20;
   o->kkt_form = PDIPM_KKT_PRIMAL;
   o->ordering = PDIPM_ORDER_LEVELS;
 }
@@ -1784,8 +1799,7 @@ int ipm_get_solution(ipm_handle* h, double* x, double* s, double* lam, double* z
 
 void ipm_destroy(ipm_handle* h) {
   if (!h) return;
-  for (hipGraphExec_t g : {h->gstats, h->gstep[0], h->gstep[1]})
-    if (g) hipGraphExecDestroy(g);
+  if (h->gsolve) hipGraphExecDestroy(h->gsolve);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   for (hipEvent_t e : h->pev) hipEventDestroy(e);
@@ -1837,6 +1851,10 @@ int ipm_batch_create(int32_t count, const ipm_problem_desc* probs, const ipm_opt
   if (h->opt.kkt_form != PDIPM_KKT_PRIMAL) {
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "batches use the primal condensed form (kkt_form 0)");
+  }
+  if (h->opt.graph_iters < 1 || h->opt.graph_iters > 1000) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "graph_iters must be in 1..1000");
   }
   h->bcount = count;
   h->bxoff.assign(count + 1, 0);
@@ -1926,8 +1944,7 @@ int ipm_batch_workspace_query(ipm_batch* b, size_t* bytes) {
 int ipm_batch_set_workspace(ipm_batch* b, void* ws, size_t bytes) {
   if (!b) return PDIPM_ERR_INVALID_ARG;
   ipm_handle* h = b->h;
-  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
-    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  if (h->gsolve) { hipGraphExecDestroy(h->gsolve); h->gsolve = nullptr; }
   int rc = ensure_stream(h);
   if (rc) return rc;
   return ipm_set_workspace(h, ws, bytes);
@@ -1936,8 +1953,7 @@ int ipm_batch_set_workspace(ipm_batch* b, void* ws, size_t bytes) {
 int ipm_batch_set_stream(ipm_batch* b, void* stream) {
   if (!b) return PDIPM_ERR_INVALID_ARG;
   ipm_handle* h = b->h;
-  for (hipGraphExec_t* g : {&h->gstats, &h->gstep[0], &h->gstep[1]})
-    if (*g) { hipGraphExecDestroy(*g); *g = nullptr; }
+  if (h->gsolve) { hipGraphExecDestroy(h->gsolve); h->gsolve = nullptr; }
   h->stream = (hipStream_t)stream;
   return ensure_stream(h);
 }

@@ -5,6 +5,7 @@
 // Reductions use a fixed order, so the batch is deterministic as well.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 
@@ -55,18 +56,48 @@ __device__ inline void ratio_b(double& a, double val, double d) {
   if (d < 0.0) a = fmin(a, -val / d);
 }
 
-__global__ void k_batch_init(BatchDev B) {
+__global__ void k_batch_init(BatchDev B, int stay64, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < B.count) {
     B.ist[i * IST_N + IST_STATUS] = PDIPM_MAX_ITER;
     B.ist[i * IST_N + IST_ITERS] = 0;
     B.ist[i * IST_N + IST_DONE] = 0;
+    B.ist[i * IST_N + IST_MISS] = 0;
     for (int q = 0; q < BST_N; ++q) B.st[i * BST_N + q] = 0.0;
   }
-  if (i < BF_N) B.flags[i] = 0;
+  if (i < BF_N)
+    B.flags[i] = i == BF_RUN ? 1 : (i == BF_STAY64 ? stay64 : (i == BF_FP64_FROM ? -1 : 0));
 }
 
-__global__ void k_batch_push_duals(DevProblem P, BatchDev B, IpmVecs v) {
+__global__ void k_batch_control(BatchDev B, int max_iter, int allow64, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
+  if (threadIdx.x != 0) return;
+  int32_t* f = B.flags;
+  if (!f[BF_RUN]) { f[BF_RUN32] = 0; f[BF_RUN64] = 0; return; }
+  const int it = f[BF_STEPS];
+  if (it > 0) {
+    // factor failures are counted; the switch to FP64 factors follows the
+    // running instances' refinement misses alone (a pivot replaced in an
+    // ended instance, or one that refinement corrected, costs no accuracy)
+    if (*B.bad != INT_MAX) f[BF_FAILURES] += 1;
+    if (f[BF_REFINE_MISS] > 0 && !f[BF_STAY64] && allow64) {
+      f[BF_STAY64] = 1;
+      f[BF_FP64_FROM] = it;
+    }
+    if (f[BF_REFINE_MISS] > 0) f[BF_MISSES] += 1;
+  }
+  if (f[BF_ACTIVE] == 0 || it > max_iter) {
+    f[BF_RUN] = 0; f[BF_RUN32] = 0; f[BF_RUN64] = 0;
+    return;
+  }
+  f[BF_RUN32] = f[BF_STAY64] ? 0 : 1;
+  f[BF_RUN64] = f[BF_STAY64] ? 1 : 0;
+  f[BF_STEPS] = it + 1;
+}
+
+__global__ void k_batch_push_duals(DevProblem P, BatchDev B, IpmVecs v, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int b = blockIdx.x;
   const int64_t r0 = B.roff[b], r1 = B.roff[b + 1], c0 = B.xoff[b], c1 = B.xoff[b + 1];
   double a[1] = {0.0};
@@ -83,7 +114,8 @@ __global__ void k_batch_push_duals(DevProblem P, BatchDev B, IpmVecs v) {
 
 // P = ||g - s|| / (1 + ||g||), D = ||r_d|| / (1 + ||grad f||), C = comp / (1 + |f|)
 // (inf-norms) of one instance; decides its termination.
-__global__ void k_batch_stats(DevProblem P, BatchDev B, IpmVecs v, double tol, int max_iter) {
+__global__ void k_batch_stats(DevProblem P, BatchDev B, IpmVecs v, double tol, int max_iter, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int b = blockIdx.x;
   int32_t* is = B.ist + (int64_t)b * IST_N;
   if (is[IST_DONE]) return;
@@ -146,7 +178,8 @@ __device__ void instance_limits(const DevProblem& P, const BatchDev& B, const Ip
 }
 
 __global__ void k_batch_predict(DevProblem P, BatchDev B, IpmVecs v, const double* dx, const double* ds,
-                                const double* dlam, const double* dzl, const double* dzu) {
+                                const double* dlam, const double* dzl, const double* dzu, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int b = blockIdx.x;
   if (B.ist[(int64_t)b * IST_N + IST_DONE]) return;
   double lim[2];
@@ -172,7 +205,8 @@ __global__ void k_batch_predict(DevProblem P, BatchDev B, IpmVecs v, const doubl
 }
 
 __global__ void k_batch_targets(DevProblem P, BatchDev B, const double* dx, const double* ds, const double* dlam,
-                                const double* dzl, const double* dzu, double* ts, double* tl, double* tu) {
+                                const double* dzl, const double* dzu, double* ts, double* tl, double* tu, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.m) ts[i] = B.st[(int64_t)B.ir[i] * BST_N + BST_SMU] - ds[i] * dlam[i];
   if (i < P.n) {
@@ -183,11 +217,22 @@ __global__ void k_batch_targets(DevProblem P, BatchDev B, const double* dx, cons
 }
 
 __global__ void k_batch_correct(DevProblem P, BatchDev B, IpmVecs v, const double* dx, const double* ds,
-                                const double* dlam, const double* dzl, const double* dzu) {
+                                const double* dlam, const double* dzl, const double* dzu, int repeat_on_miss,
+                                const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int b = blockIdx.x;
   double* st = B.st + (int64_t)b * BST_N;
-  if (B.ist[(int64_t)b * IST_N + IST_DONE]) {
-    if (threadIdx.x == 0) { st[BST_AP] = 0.0; st[BST_AD] = 0.0; }
+  int32_t* is = B.ist + (int64_t)b * IST_N;
+  const int miss = is[IST_MISS];
+  // a direction whose refined residual missed the instance's target is not
+  // taken when FP64 factors can repeat the iteration; a non-finite one ends
+  // the instance at its current (finite) iterate
+  const bool repeat = repeat_on_miss && miss != MISS_NONE;
+  if (is[IST_DONE] || repeat || miss == MISS_NONFINITE) {
+    if (threadIdx.x == 0) {
+      st[BST_AP] = 0.0; st[BST_AD] = 0.0;
+      if (!is[IST_DONE] && !repeat) { is[IST_STATUS] = PDIPM_ERR_NUMERICAL; is[IST_DONE] = 1; }
+    }
     return;
   }
   double lim[2];
@@ -202,23 +247,29 @@ __global__ void k_batch_correct(DevProblem P, BatchDev B, IpmVecs v, const doubl
 }
 
 __global__ void k_batch_update(DevProblem P, BatchDev B, IpmVecs v, const double* dx, const double* ds,
-                               const double* dlam, const double* dzl, const double* dzu) {
+                               const double* dlam, const double* dzl, const double* dzu, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  // an instance that takes no step keeps its point exactly: its direction
+  // may be non-finite (ended instances are still factored), and 0 * inf is
+  // not 0
   if (i < P.m) {
     const double* st = B.st + (int64_t)B.ir[i] * BST_N;
-    v.s[i] += st[BST_AP] * ds[i];
-    v.lam[i] += st[BST_AD] * dlam[i];
+    const double ap = st[BST_AP], ad = st[BST_AD];
+    if (ap != 0.0) v.s[i] += ap * ds[i];
+    if (ad != 0.0) v.lam[i] += ad * dlam[i];
   }
   if (i < P.n) {
     const double* st = B.st + (int64_t)B.ix[i] * BST_N;
     const double ap = st[BST_AP], ad = st[BST_AD];
-    v.x[i] += ap * dx[i];
-    v.zl[i] = lo_b(P.xl[i]) ? v.zl[i] + ad * dzl[i] : 0.0;
-    v.zu[i] = hi_b(P.xu[i]) ? v.zu[i] + ad * dzu[i] : 0.0;
+    if (ap != 0.0) v.x[i] += ap * dx[i];
+    v.zl[i] = lo_b(P.xl[i]) ? (ad != 0.0 ? v.zl[i] + ad * dzl[i] : v.zl[i]) : 0.0;
+    v.zu[i] = hi_b(P.xu[i]) ? (ad != 0.0 ? v.zu[i] + ad * dzu[i] : v.zu[i]) : 0.0;
   }
 }
 
-__global__ void k_batch_check_residual(BatchDev B, const double* r) {
+__global__ void k_batch_check_residual(BatchDev B, const double* r, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int b = blockIdx.x;
   if (B.ist[(int64_t)b * IST_N + IST_DONE]) return;
   double a[1] = {0.0};
@@ -228,58 +279,72 @@ __global__ void k_batch_check_residual(BatchDev B, const double* r) {
     a[0] = isfinite(x) ? fmax(a[0], x) : INFINITY;
   }
   wg_reduce<1>(a, op);
-  if (threadIdx.x == 0 && !(a[0] <= B.st[(int64_t)b * BST_N + BST_TARGET])) atomicAdd(B.flags + BF_REFINE_MISS, 1);
+  if (threadIdx.x == 0 && !(a[0] <= B.st[(int64_t)b * BST_N + BST_TARGET])) {
+    int32_t* is = B.ist + (int64_t)b * IST_N;
+    if (is[IST_MISS] == MISS_NONE) atomicAdd(B.flags + BF_REFINE_MISS, 1);
+    is[IST_MISS] = isfinite(a[0]) ? max(is[IST_MISS], (int32_t)MISS_TARGET) : MISS_NONFINITE;
+  }
 }
 
-__global__ void k_batch_next(BatchDev B) {
+__global__ void k_batch_next(BatchDev B, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   if (threadIdx.x == 0) B.flags[BF_ITER] += 1;
 }
 
-__global__ void k_batch_clear_miss(BatchDev B) {
-  if (threadIdx.x == 0) B.flags[BF_REFINE_MISS] = 0;
+__global__ void k_batch_clear_miss(BatchDev B, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
+  const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (i < B.count) B.ist[i * IST_N + IST_MISS] = 0;
+  if (i == 0) B.flags[BF_REFINE_MISS] = 0;
 }
 
-__global__ void k_set_int(int* p, int v) {
+__global__ void k_set_int(int* p, int v, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   if (threadIdx.x == 0) *p = v;
 }
 
 }  // namespace
 
-void launch_batch_init(const BatchDev& B, hipStream_t s) {
-  k_batch_init<<<grid_for(B.count > BF_N ? B.count : BF_N), BS, 0, s>>>(B);
+void launch_batch_init(const BatchDev& B, int stay64, hipStream_t s) {
+  k_batch_init<<<grid_for(B.count > BF_N ? B.count : BF_N), BS, 0, s>>>(B, stay64, launch_gate());
+}
+void launch_batch_control(const BatchDev& B, int max_iter, int allow64, hipStream_t s) {
+  k_batch_control<<<1, 64, 0, s>>>(B, max_iter, allow64, launch_gate());
 }
 void launch_batch_push_duals(const DevProblem& P, const BatchDev& B, IpmVecs& v, hipStream_t s) {
-  k_batch_push_duals<<<(unsigned)B.count, BS, 0, s>>>(P, B, v);
+  k_batch_push_duals<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, launch_gate());
 }
 void launch_batch_stats(const DevProblem& P, const BatchDev& B, IpmVecs& v, double tol, int max_iter,
                         hipStream_t s) {
-  k_batch_stats<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, tol, max_iter);
+  k_batch_stats<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, tol, max_iter, launch_gate());
 }
 void launch_batch_predict(const DevProblem& P, const BatchDev& B, IpmVecs& v, const double* dx,
                           const double* ds, const double* dlam, const double* dzl, const double* dzu,
                           hipStream_t s) {
-  k_batch_predict<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu);
+  k_batch_predict<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu, launch_gate());
 }
 void launch_batch_targets(const DevProblem& P, const BatchDev& B, const double* dx, const double* ds,
                           const double* dlam, const double* dzl, const double* dzu, double* ts, double* tl,
                           double* tu, hipStream_t s) {
-  k_batch_targets<<<grid_for(P.n > P.m ? P.n : P.m), BS, 0, s>>>(P, B, dx, ds, dlam, dzl, dzu, ts, tl, tu);
+  k_batch_targets<<<grid_for(P.n > P.m ? P.n : P.m), BS, 0, s>>>(P, B, dx, ds, dlam, dzl, dzu, ts, tl, tu, launch_gate());
 }
 void launch_batch_correct(const DevProblem& P, const BatchDev& B, IpmVecs& v, const double* dx,
                           const double* ds, const double* dlam, const double* dzl, const double* dzu,
-                          hipStream_t s) {
-  k_batch_correct<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu);
+                          int repeat_on_miss, hipStream_t s) {
+  k_batch_correct<<<(unsigned)B.count, BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu, repeat_on_miss, launch_gate());
 }
 void launch_batch_update(const DevProblem& P, const BatchDev& B, IpmVecs& v, const double* dx,
                          const double* ds, const double* dlam, const double* dzl, const double* dzu,
                          hipStream_t s) {
-  k_batch_update<<<grid_for(P.n > P.m ? P.n : P.m), BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu);
+  k_batch_update<<<grid_for(P.n > P.m ? P.n : P.m), BS, 0, s>>>(P, B, v, dx, ds, dlam, dzl, dzu, launch_gate());
 }
 void launch_batch_check_residual(const BatchDev& B, const double* r, hipStream_t s) {
-  k_batch_check_residual<<<(unsigned)B.count, BS, 0, s>>>(B, r);
+  k_batch_check_residual<<<(unsigned)B.count, BS, 0, s>>>(B, r, launch_gate());
 }
-void launch_batch_next(const BatchDev& B, hipStream_t s) { k_batch_next<<<1, 64, 0, s>>>(B); }
-void launch_batch_clear_miss(const BatchDev& B, hipStream_t s) { k_batch_clear_miss<<<1, 64, 0, s>>>(B); }
-void launch_set_int(int* p, int v, hipStream_t s) { k_set_int<<<1, 64, 0, s>>>(p, v); }
+void launch_batch_next(const BatchDev& B, hipStream_t s) { k_batch_next<<<1, 64, 0, s>>>(B, launch_gate()); }
+void launch_batch_clear_miss(const BatchDev& B, hipStream_t s) {
+  k_batch_clear_miss<<<grid_for(B.count), BS, 0, s>>>(B, launch_gate());
+}
+void launch_set_int(int* p, int v, hipStream_t s) { k_set_int<<<1, 64, 0, s>>>(p, v, launch_gate()); }
 
 }  // namespace pdipm

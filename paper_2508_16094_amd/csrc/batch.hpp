@@ -12,10 +12,18 @@ namespace pdipm {
 
 // per-instance FP64 state, BST_N doubles per instance
 enum { BST_MU = 0, BST_F, BST_P, BST_D, BST_C, BST_TARGET, BST_SMU, BST_AP, BST_AD, BST_N = 12 };
-// per-instance integer state, IST_N ints per instance
-enum { IST_STATUS = 0, IST_ITERS, IST_DONE, IST_N = 4 };
-// global integer flags
-enum { BF_ACTIVE = 0, BF_REFINE_MISS, BF_ITER, BF_N = 4 };
+// per-instance integer state, IST_N ints per instance (IST_MISS: how a
+// direction of this iteration missed the instance's refinement target)
+enum { IST_STATUS = 0, IST_ITERS, IST_DONE, IST_MISS, IST_N = 4 };
+enum { MISS_NONE = 0, MISS_TARGET = 1, MISS_NONFINITE = 2 };
+// global integer flags: running count and refinement misses of the current
+// iteration, iterations taken; the control words of a captured solve (RUN:
+// stats and steps run, RUN32 / RUN64: the step in that precision runs,
+// STAY64: FP64 factors from now on) and its counters
+enum {
+  BF_ACTIVE = 0, BF_REFINE_MISS, BF_ITER, BF_RUN, BF_RUN32, BF_RUN64, BF_STAY64, BF_STEPS,
+  BF_FAILURES, BF_MISSES, BF_FP64_FROM, BF_N = 12
+};
 
 struct BatchDev {
   int32_t count;
@@ -26,10 +34,19 @@ struct BatchDev {
   double* st;                  // [count * BST_N]
   int32_t* ist;                // [count * IST_N]
   int32_t* flags;              // [BF_N]
+  const int* bad;              // first non-positive pivot of the last factorisation (INT_MAX: none)
 };
 
-// flags: active = refine_miss = iteration = 0; every instance running
-void launch_batch_init(const BatchDev& B, hipStream_t s);
+// flags: active = refine_miss = iteration = 0; every instance running; the
+// control words: RUN = 1, STAY64 = stay64, FP64_FROM = -1
+void launch_batch_init(const BatchDev& B, int stay64, hipStream_t s);
+// Decision of one iteration, after its termination measures (the host loop's
+// decision made on the device, so that a graph holds whole iterations):
+// after a step, count a factorisation failure and a refinement miss and
+// switch to FP64 factors on either (when allow64); stop (RUN = 0) when no
+// instance runs or more than max_iter steps were taken; otherwise open the
+// step of the current precision (RUN32 or RUN64) and count it.
+void launch_batch_control(const BatchDev& B, int max_iter, int allow64, hipStream_t s);
 // push the duals of a warm start: mu_w = max(1e-4, s'lambda / m_i) per instance
 void launch_batch_push_duals(const DevProblem& P, const BatchDev& B, IpmVecs& v, hipStream_t s);
 // termination measures of every running instance; counts the running ones
@@ -42,10 +59,13 @@ void launch_batch_predict(const DevProblem& P, const BatchDev& B, IpmVecs& v, co
 void launch_batch_targets(const DevProblem& P, const BatchDev& B, const double* dx, const double* ds,
                           const double* dlam, const double* dzl, const double* dzu, double* ts, double* tl,
                           double* tu, hipStream_t s);
-// corrector: step lengths per instance (zero for finished instances)
+// corrector: step lengths per instance (zero for finished instances, and
+// with repeat_on_miss for instances whose FP32 direction missed its target
+// or when the factorisation met a non-positive pivot: they repeat the
+// iteration, with FP64 factors once the control step switches)
 void launch_batch_correct(const DevProblem& P, const BatchDev& B, IpmVecs& v, const double* dx,
                           const double* ds, const double* dlam, const double* dzl, const double* dzu,
-                          hipStream_t s);
+                          int repeat_on_miss, hipStream_t s);
 void launch_batch_update(const DevProblem& P, const BatchDev& B, IpmVecs& v, const double* dx,
                          const double* ds, const double* dlam, const double* dzl, const double* dzu,
                          hipStream_t s);

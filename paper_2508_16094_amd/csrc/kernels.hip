@@ -54,7 +54,8 @@ __device__ void block_reduce_store(double (&v)[NQ], const RedSpec& spec, double*
   }
 }
 
-__global__ void k_finalize(const double* partials, int nblocks, RedSpec spec, double* out) {
+__global__ void k_finalize(const double* partials, int nblocks, RedSpec spec, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   __shared__ double sh[BS / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = 0; q < spec.nq; ++q) {
@@ -72,23 +73,27 @@ __global__ void k_finalize(const double* partials, int nblocks, RedSpec spec, do
   }
 }
 
-__global__ void k_fill_f64(double* p, int64_t n, double v) {
+__global__ void k_fill_f64(double* p, int64_t n, double v, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) p[i] = v;
 }
 
-__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+__global__ void k_zero_u32(uint32_t* p, int64_t n, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) p[i] = 0u;
 }
 
 // ------------------------------------------------------------ evaluation
 __global__ void k_jac_eval(int64_t nnz, const double* ja, const double* jw, const int32_t* jc,
-                           const double* x, double* jv) {
+                           const double* x, double* jv, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e < nnz) jv[e] = ja[e] - 2.0 * jw[e] * x[jc[e]];
 }
 
 __global__ void k_constraints(int64_t m, const int64_t* jp, const int32_t* jc, const double* ja,
-                              const double* jw, const double* x, const double* b, double* g) {
+                              const double* jw, const double* x, const double* b, double* g, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k >= m) return;
   double acc = 0.0;
@@ -101,7 +106,8 @@ __global__ void k_constraints(int64_t m, const int64_t* jp, const int32_t* jc, c
 
 __global__ void k_gradient(int64_t n, const int64_t* hsp, const int32_t* hsc, const int32_t* hss,
                            const double* hq, const double* c, const double* q4, const double* x,
-                           double* qx, double* gf) {
+                           double* qx, double* gf, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -114,7 +120,8 @@ __global__ void k_gradient(int64_t n, const int64_t* hsp, const int32_t* hsc, co
 __global__ void k_hess_eval(int64_t n, const int64_t* hp, const int64_t* hdiag, const double* hq,
                             const double* q4, const int64_t* jtp, const int32_t* jtr,
                             const int32_t* jte, const double* jw, const double* x, const double* lam,
-                            double* hv) {
+                            double* hv, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   for (int64_t e = hp[i]; e < hp[i + 1]; ++e) hv[e] = hq[e];
@@ -125,7 +132,8 @@ __global__ void k_hess_eval(int64_t n, const int64_t* hp, const int64_t* hdiag, 
 }
 
 __global__ void k_jt_mul(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
-                         const double* jv, const double* y, double* out) {
+                         const double* jv, const double* y, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -134,7 +142,8 @@ __global__ void k_jt_mul(int64_t n, const int64_t* jtp, const int32_t* jtr, cons
 }
 
 __global__ void k_j_mul(int64_t m, const int64_t* jp, const int32_t* jc, const double* jv,
-                        const double* v, double* out) {
+                        const double* v, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k >= m) return;
   double acc = 0.0;
@@ -143,7 +152,8 @@ __global__ void k_j_mul(int64_t m, const int64_t* jp, const int32_t* jc, const d
 }
 
 __global__ void k_h_mul(int64_t n, const int64_t* hsp, const int32_t* hsc, const int32_t* hss,
-                        const double* hv, const double* v, double* out) {
+                        const double* hv, const double* v, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -156,7 +166,8 @@ __global__ void k_h_mul(int64_t n, const int64_t* hsp, const int32_t* hsc, const
 // the J' Sigma_s J products plus the Hessian and diagonal terms.
 template <typename T>
 __global__ void k_assemble(DevKMap K, const double* hv, const double* jv, const double* sig_s,
-                           const double* sig_x, double delta_p, T* panel, double* kval) {
+                           const double* sig_x, double delta_p, T* panel, double* kval, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e >= K.nk) return;
   double v = 0.0;
@@ -170,7 +181,8 @@ __global__ void k_assemble(DevKMap K, const double* hv, const double* jv, const 
 }
 
 template <typename T>
-__global__ void k_set_values(DevKMap K, const double* kval, T* panel) {
+__global__ void k_set_values(DevKMap K, const double* kval, T* panel, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e < K.nk) panel[K.pos[e]] = (T)kval[e];
 }
@@ -179,7 +191,8 @@ __global__ void k_set_values(DevKMap K, const double* kval, T* panel) {
 // count of diagonal entries without their pivot's sign (positive below npos,
 // negative from npos on; a plain SPD K has npos >= n).
 __global__ void k_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
-                             int64_t npos) {
+                             int64_t npos, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
   double a[3] = {0.0, 0.0, INFINITY};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
@@ -197,7 +210,8 @@ __global__ void k_diag_scale(int64_t n, const int64_t* kp, const double* kval, d
 }
 
 template <typename T>
-__global__ void k_set_scaled(DevKMap K, const double* kval, const double* d, double shift, T* panel) {
+__global__ void k_set_scaled(DevKMap K, const double* kval, const double* d, double shift, T* panel, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e >= K.nk) return;
   const int32_t r = K.krow[e], c = K.kc[e];
@@ -210,7 +224,8 @@ __global__ void k_set_scaled(DevKMap K, const double* kval, const double* d, dou
 // the order of its assembly map: x rows take an H entry, lambda rows a J
 // entry (kh) or, on the diagonal, -1/Sigma_s.
 __global__ void k_assemble_aug(DevKMap K, int64_t n, const double* hv, const double* jv, const double* sig_s,
-                               const double* sig_x, double delta_p, double* kval) {
+                               const double* sig_x, double delta_p, double* kval, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (e >= K.nk) return;
   const int32_t r = K.krow[e], c = K.kc[e], q = K.kh[e];
@@ -224,13 +239,15 @@ __global__ void k_assemble_aug(DevKMap K, int64_t n, const double* hv, const dou
   kval[e] = v;
 }
 
-__global__ void k_sign_scale(int64_t n, const signed char* sign, double* y) {
+__global__ void k_sign_scale(int64_t n, const signed char* sign, double* y, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n && sign[i] < 0) y[i] = -y[i];
 }
 
 __global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc, const int64_t* kss,
-                               const double* kval, const double* v, double* out) {
+                               const double* kval, const double* v, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -243,7 +260,8 @@ __global__ void k_k_mul_stored(int64_t n, const int64_t* ksp, const int32_t* ksc
 // (= delta_d + s / lambda): the diagonal scalings of M = diag(E) + J D J'.
 __global__ void k_dual_prep(int64_t n, int64_t m, const double* hv, const int64_t* hdiag,
                             const double* sig_x, const double* sig_s, double delta_p, double* dd,
-                            double* de) {
+                            double* de, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) dd[i] = 1.0 / (hv[hdiag[i]] + sig_x[i] + delta_p);
   if (i < m) de[i] = 1.0 / sig_s[i];
@@ -251,12 +269,14 @@ __global__ void k_dual_prep(int64_t n, int64_t m, const double* hv, const int64_
 
 // out = a o b, and out = d o (r - w): the two diagonal steps of a K solve
 // through M (x = D r - D J' M^-1 J D r).
-__global__ void k_mul_vec(int64_t n, const double* a, const double* b, double* out) {
+__global__ void k_mul_vec(int64_t n, const double* a, const double* b, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) out[i] = a[i] * b[i];
 }
 
-__global__ void k_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out) {
+__global__ void k_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) out[i] = d[i] * (r[i] - w[i]);
 }
@@ -264,7 +284,8 @@ __global__ void k_dual_finish(int64_t n, const double* d, const double* r, const
 // max_i K_ii with K_ii = 1/D_i + sum_k Sigma_s[k] J_ki^2 (the norm estimate
 // of K used by the backward error when K itself is never formed)
 __global__ void k_kdiag_max(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
-                            const double* jv, const double* sig_s, const double* dd, double* partials) {
+                            const double* jv, const double* sig_s, const double* dd, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_MAX}};
   double a[1] = {0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
@@ -283,7 +304,8 @@ __global__ void k_kdiag_max(int64_t n, const int64_t* jtp, const int32_t* jtr, c
 // matrices are added in child order, then w columns are eliminated and the
 // panel and the new update matrix are written back.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* panel, T* ubuf, int* bad) {
+__global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* panel, T* ubuf, int* bad, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int LD = 65;
   __shared__ T F[64 * LD];
   const int32_t S = P.small[d0 + blockIdx.x];
@@ -344,7 +366,8 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
 // parent S and adds every child's update matrix entries landing there, one
 // child after the other.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* panel, T* ubuf) {
+__global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* panel, T* ubuf, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   const ExtAddDesc d = P.ext[d0 + blockIdx.x];
   const int32_t S = d.sn;
   const int hP = P.sh[S], wP = P.sw[S], ldP = P.sld[S];
@@ -407,7 +430,8 @@ __device__ inline double lane_bcast(double v, int src) {
 // P.sign): l_kk = sqrt(s_k a_kk), l_ik = a_ik / (s_k l_kk), trailing
 // a_ij -= l_ik s_k l_jk; the inverse is that of L.
 template <typename T, int NB, int PT, bool SG>
-__global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad) {
+__global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T* inv, int* bad, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int GR = PT / 16, GC = 16, PB = 16, NP = NB / PB, LDA = NB + 1, S = NB / 64;
   constexpr int TR = NB / GR, TC = NB / GC;   // rows and columns of a thread's tile
   static_assert(GR * GC == PT && TR * GR == NB && TC * GC == NB, "thread grid");
@@ -681,7 +705,8 @@ __device__ inline double2u load2(const double* p, int valid) {
 constexpr int BS64 = 512;  // threads of the FP64 GEMM (8 waves)
 template <bool SG>
 __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
-                                                   double* ubuf, const double* inv) {
+                                                   double* ubuf, const double* inv, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int TM = GEMM_TILE_F64, BX = TM == 128 ? 4 : 1, BY = 2;
   constexpr int WX = TM / (16 * BX);                       // waves along rows
   static_assert(WX * (TM / (16 * BY)) == BS64 / 64, "eight waves per tile");
@@ -767,7 +792,8 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
 constexpr int BS32 = 512;  // threads of the FP32 GEMM (8 waves)
 template <bool SG>
 __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
-                                                   float* ubuf, const float* inv) {
+                                                   float* ubuf, const float* inv, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int TM = GEMM_TILE_F32, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
   static_assert(TM == 128, "the FP32 wave layout assumes 128 x 128 tiles");
   __shared__ float As[KC * LDS_LD];
@@ -842,11 +868,13 @@ __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_
 }
 
 // --------------------------------------------------- triangular solves
-__global__ void k_permute_in(int64_t n, const int32_t* perm, const double* rhs, const double* d, double* xp) {
+__global__ void k_permute_in(int64_t n, const int32_t* perm, const double* rhs, const double* d, double* xp, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k < n) xp[k] = d ? rhs[perm[k]] * d[perm[k]] : rhs[perm[k]];
 }
-__global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, const double* d, double* x) {
+__global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, const double* d, double* x, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k < n) x[perm[k]] = d ? xp[k] * d[perm[k]] : xp[k];
 }
@@ -854,7 +882,8 @@ __global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, 
 // Forward solve, small supernodes (h <= 64): one workgroup, vector in LDS.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T* panel, const double* xp,
-                                                 double* ys, double* uvec) {
+                                                 double* ys, double* uvec, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   __shared__ double t[64];
   const int32_t S = P.ssmall[d0 + blockIdx.x];
   const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
@@ -931,7 +960,8 @@ struct InvBlock {
 // then y for the first column block.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, const T* inv, double* xp, double* ys,
-                                                  double* uvec) {
+                                                  double* uvec, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   typedef InvBlock<BS, T> IB;
   __shared__ double tb[IB::NB], red[IB::NW * IB::NB];
   const int32_t S = P.slarge[d0 + blockIdx.x];
@@ -985,7 +1015,8 @@ template <> struct VecOf<double> { typedef double2 type; static constexpr int n 
 // large launches).
 template <typename T>
 __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T* panel, const T* inv,
-                                                double* xp, double* ys, double* uvec) {
+                                                double* xp, double* ys, double* uvec, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   typedef InvBlock<SBS, T> IB;
   constexpr int VEC = VecOf<T>::n, NW = SBS / 64, CPW = 128 / NW, RW = 64 * VEC;
   typedef typename VecOf<T>::type V;
@@ -1058,7 +1089,8 @@ __global__ void __launch_bounds__(SBS) k_fwd_step(DevPlan P, int64_t d0, const T
 
 // Backward solve, small supernodes.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T* panel, double* ys) {
+__global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T* panel, double* ys, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   __shared__ double y[64], xr[64];
   const int32_t S = P.ssmall[d0 + blockIdx.x];
   const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S], ld = P.sld[S];
@@ -1091,7 +1123,8 @@ __global__ void __launch_bounds__(BS) k_bwd_small(DevPlan P, int64_t d0, const T
 // (17 exchanges in all instead of 6 per column).
 template <typename T>
 __global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T* panel, const double* ys,
-                                                double* part) {
+                                                double* part, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int CPW = 16, VEC = VecOf<T>::n;   // eight waves of 16 columns
   typedef typename VecOf<T>::type V;
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
@@ -1155,7 +1188,8 @@ __global__ void __launch_bounds__(SBS) k_bwd_part(DevPlan P, int64_t d0, const T
 // reduces its 16 columns by recursive halving.
 template <typename T>
 __global__ void __launch_bounds__(SBS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
-                                                const double* part) {
+                                                const double* part, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   constexpr int NB = sizeof(T) == 4 ? 128 : 64, CPW = 16, RPL = NB / 64;
   constexpr int NG = SBS / NB, PU = 16;   // thread groups per column; partial loads per round
   __shared__ double z[NB], zp[NG * NB];
@@ -1221,7 +1255,8 @@ __global__ void __launch_bounds__(SBS) k_bwd_diag(DevPlan P, int64_t d0, const T
 
 // -------------------------------------------------------- IPM vectors
 __global__ void k_residuals(DevProblem P, const double* jtl, const double* gf, const double* zl,
-                            const double* zu, const double* g, const double* s, double* rd, double* rp) {
+                            const double* zu, const double* g, const double* s, double* rd, double* rp, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.n) rd[i] = gf[i] - jtl[i] - (has_lo(P.xl[i]) ? zl[i] : 0.0) + (has_hi(P.xu[i]) ? zu[i] : 0.0);
   if (i < P.m) rp[i] = g[i] - s[i];
@@ -1229,7 +1264,8 @@ __global__ void k_residuals(DevProblem P, const double* jtl, const double* gf, c
 
 // Per-iteration statistics: max|r_p|, max|g|, max|r_d|, max|grad f|,
 // complementarity sum, objective sum, count of non-finite values.
-__global__ void k_stats_iter(DevProblem P, IpmVecs v, double* partials) {
+__global__ void k_stats_iter(DevProblem P, IpmVecs v, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{7, {RED_MAX, RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_SUM, RED_SUM}};
   double a[7] = {0, 0, 0, 0, 0, 0, 0};
   const int64_t N = P.n > P.m ? P.n : P.m;
@@ -1253,7 +1289,8 @@ __global__ void k_stats_iter(DevProblem P, IpmVecs v, double* partials) {
   block_reduce_store<7>(a, spec, partials);
 }
 
-__global__ void k_sigmas(DevProblem P, IpmVecs v, double dd) {
+__global__ void k_sigmas(DevProblem P, IpmVecs v, double dd, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.m) v.sig_s[i] = v.lam[i] / (v.s[i] + dd * v.lam[i]);
   if (i < P.n) {
@@ -1264,13 +1301,15 @@ __global__ void k_sigmas(DevProblem P, IpmVecs v, double dd) {
   }
 }
 
-__global__ void k_rhs_m(DevProblem P, IpmVecs v, const double* ts, double* wm) {
+__global__ void k_rhs_m(DevProblem P, IpmVecs v, const double* ts, double* wm, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k < P.m) wm[k] = v.sig_s[k] * (v.g[k] - (ts ? ts[k] / v.lam[k] : 0.0));
 }
 
 __global__ void k_rhs_n(DevProblem P, IpmVecs v, const double* jtw, const double* tl, const double* tu,
-                        double* rhs) {
+                        double* rhs, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= P.n) return;
   double rt = v.rd[i];
@@ -1280,7 +1319,8 @@ __global__ void k_rhs_n(DevProblem P, IpmVecs v, const double* jtw, const double
 }
 
 __global__ void k_recover_m(DevProblem P, IpmVecs v, const double* jdx, const double* ts, double dd,
-                            double* ds, double* dlam) {
+                            double* ds, double* dlam, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k >= P.m) return;
   const double dl = v.sig_s[k] * ((ts ? ts[k] / v.lam[k] : 0.0) - v.g[k] - jdx[k]);
@@ -1289,7 +1329,8 @@ __global__ void k_recover_m(DevProblem P, IpmVecs v, const double* jdx, const do
 }
 
 __global__ void k_recover_n(DevProblem P, IpmVecs v, const double* dx, const double* tl, const double* tu,
-                            double* dzl, double* dzu) {
+                            double* dzl, double* dzu, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= P.n) return;
   if (has_lo(P.xl[i])) {
@@ -1312,7 +1353,8 @@ __device__ inline void ratio(double& a, double val, double d) {
 
 // Largest steps keeping (s, x-l, u-x) and (lambda, z_l, z_u) non-negative.
 __global__ void k_step_limits(DevProblem P, IpmVecs v, const double* dx, const double* ds,
-                              const double* dlam, const double* dzl, const double* dzu, double* partials) {
+                              const double* dlam, const double* dzl, const double* dzu, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{2, {RED_MIN, RED_MIN}};
   double a[2] = {INFINITY, INFINITY};
   const int64_t N = P.n > P.m ? P.n : P.m;
@@ -1330,7 +1372,8 @@ __global__ void k_step_limits(DevProblem P, IpmVecs v, const double* dx, const d
 }
 
 __global__ void k_mu_aff(DevProblem P, IpmVecs v, const double* dx, const double* ds, const double* dlam,
-                         const double* dzl, const double* dzu, double ap, double ad, double* partials) {
+                         const double* dzl, const double* dzu, double ap, double ad, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_SUM}};
   double a[1] = {0.0};
   const int64_t N = P.n > P.m ? P.n : P.m;
@@ -1346,7 +1389,8 @@ __global__ void k_mu_aff(DevProblem P, IpmVecs v, const double* dx, const double
 
 __global__ void k_targets(DevProblem P, const double* dx, const double* ds, const double* dlam,
                           const double* dzl, const double* dzu, double smu, double* ts, double* tl,
-                          double* tu) {
+                          double* tu, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.m) ts[i] = smu - ds[i] * dlam[i];
   if (i < P.n) {
@@ -1356,7 +1400,8 @@ __global__ void k_targets(DevProblem P, const double* dx, const double* ds, cons
 }
 
 __global__ void k_axpy_point(DevProblem P, IpmVecs dst, IpmVecs src, const double* dx, const double* ds,
-                             const double* dlam, const double* dzl, const double* dzu, double ap, double ad) {
+                             const double* dlam, const double* dzl, const double* dzu, double ap, double ad, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.m) {
     dst.s[i] = src.s[i] + ap * ds[i];
@@ -1370,7 +1415,8 @@ __global__ void k_axpy_point(DevProblem P, IpmVecs dst, IpmVecs src, const doubl
 }
 
 // Squared residual norm of the perturbed KKT conditions (NLP line search).
-__global__ void k_phi(DevProblem P, IpmVecs v, double smu, double* partials) {
+__global__ void k_phi(DevProblem P, IpmVecs v, double smu, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_SUM}};
   double a[1] = {0.0};
   const int64_t N = P.n > P.m ? P.n : P.m;
@@ -1388,7 +1434,8 @@ __global__ void k_phi(DevProblem P, IpmVecs v, double smu, double* partials) {
   block_reduce_store<1>(a, spec, partials);
 }
 
-__global__ void k_init_point(DevProblem P, IpmVecs v) {
+__global__ void k_init_point(DevProblem P, IpmVecs v, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.n) {
     const bool lo = has_lo(P.xl[i]), hi = has_hi(P.xu[i]);
@@ -1403,7 +1450,8 @@ __global__ void k_init_point(DevProblem P, IpmVecs v) {
   if (i < P.m) v.lam[i] = 1.0;
 }
 
-__global__ void k_slack_from_g(DevProblem P, IpmVecs v, int warm) {
+__global__ void k_slack_from_g(DevProblem P, IpmVecs v, int warm, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k >= P.m) return;
   const double g = v.g[k];
@@ -1411,7 +1459,8 @@ __global__ void k_slack_from_g(DevProblem P, IpmVecs v, int warm) {
 }
 
 // Interior push of a supplied point (bound-push rule of Waechter-Biegler).
-__global__ void k_push_x(DevProblem P, IpmVecs v, const double* xhat, const double* lamhat) {
+__global__ void k_push_x(DevProblem P, IpmVecs v, const double* xhat, const double* lamhat, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < P.n) {
     const bool lo = has_lo(P.xl[i]), hi = has_hi(P.xu[i]);
@@ -1424,14 +1473,16 @@ __global__ void k_push_x(DevProblem P, IpmVecs v, const double* xhat, const doub
   if (i < P.m) v.lam[i] = fmax(lamhat[i], 1e-2);
 }
 
-__global__ void k_push_duals(DevProblem P, IpmVecs v, double mu_w) {
+__global__ void k_push_duals(DevProblem P, IpmVecs v, double mu_w, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= P.n) return;
   v.zl[i] = has_lo(P.xl[i]) ? mu_w / (v.x[i] - P.xl[i]) : 0.0;
   v.zu[i] = has_hi(P.xu[i]) ? mu_w / (P.xu[i] - v.x[i]) : 0.0;
 }
 
-__global__ void k_sum_sl(DevProblem P, IpmVecs v, double* partials) {
+__global__ void k_sum_sl(DevProblem P, IpmVecs v, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_SUM}};
   double a[1] = {0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < P.m; i += (int64_t)gridDim.x * BS)
@@ -1440,18 +1491,21 @@ __global__ void k_sum_sl(DevProblem P, IpmVecs v, double* partials) {
 }
 
 // K v = H v + (Sigma_x + delta_p) v + J'(Sigma_s (J v)), second part
-__global__ void k_kfree_m(int64_t m, const double* sig_s, double* jv_tmp) {
+__global__ void k_kfree_m(int64_t m, const double* sig_s, double* jv_tmp, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (k < m) jv_tmp[k] *= sig_s[k];
 }
 __global__ void k_kfree_n(int64_t n, const double* hv_v, const double* jt, const double* sig_x, double dp,
-                          const double* v, double* out) {
+                          const double* v, double* out, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) out[i] = hv_v[i] + jt[i] + (sig_x[i] + dp) * v[i];
 }
 
 __global__ void k_residual_norms(int64_t n, const double* rhs, const double* kx, const double* x, double* r,
-                                 double* partials) {
+                                 double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{3, {RED_MAX, RED_MAX, RED_MAX}};
   double a[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
@@ -1465,7 +1519,8 @@ __global__ void k_residual_norms(int64_t n, const double* rhs, const double* kx,
   block_reduce_store<3>(a, spec, partials);
 }
 
-__global__ void k_dot(int64_t n, const double* a, const double* b, double* partials) {
+__global__ void k_dot(int64_t n, const double* a, const double* b, double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_SUM}};
   double acc[1] = {0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) acc[0] += a[i] * b[i];
@@ -1474,7 +1529,8 @@ __global__ void k_dot(int64_t n, const double* a, const double* b, double* parti
 
 // x += alpha p, r -= alpha q; reports max|r| and max|x|.
 __global__ void k_cg_step(int64_t n, double alpha, const double* p, const double* q, double* x, double* r,
-                          double* partials) {
+                          double* partials, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{2, {RED_MAX, RED_MAX}};
   double a[2] = {0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
@@ -1489,16 +1545,19 @@ __global__ void k_cg_step(int64_t n, double alpha, const double* p, const double
   block_reduce_store<2>(a, spec, partials);
 }
 
-__global__ void k_xpby(int64_t n, const double* z, double beta, double* p) {
+__global__ void k_xpby(int64_t n, const double* z, double beta, double* p, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) p[i] = z[i] + beta * p[i];
 }
 
-__global__ void k_add(int64_t n, double* x, const double* c) {
+__global__ void k_add(int64_t n, double* x, const double* c, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) x[i] += c[i];
 }
-__global__ void k_copy(int64_t n, double* d, const double* s) {
+__global__ void k_copy(int64_t n, double* d, const double* s, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i < n) d[i] = s[i];
 }
@@ -1511,53 +1570,59 @@ inline int red_grid(int64_t N) {
 }  // namespace
 
 // ============================================================ wrappers
+namespace {
+thread_local const int* g_launch_gate = nullptr;
+}  // namespace
+void set_launch_gate(const int* gate) { g_launch_gate = gate; }
+const int* launch_gate() { return g_launch_gate; }
+
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   int64_t g = blocks_for(n);
   if (g > 65536) g = 65536;
-  k_fill_f64<<<(unsigned)g, BS, 0, s>>>(p, n, v);
+  k_fill_f64<<<(unsigned)g, BS, 0, s>>>(p, n, v, launch_gate());
 }
 void launch_fill_bytes0(void* p, int64_t bytes, hipStream_t s) {
   int64_t n = bytes / 4;
   if (n <= 0) return;
   int64_t g = blocks_for(n);
   if (g > 65536) g = 65536;
-  k_zero_u32<<<(unsigned)g, BS, 0, s>>>((uint32_t*)p, n);
+  k_zero_u32<<<(unsigned)g, BS, 0, s>>>((uint32_t*)p, n, launch_gate());
 }
 void launch_finalize(const double* partials, int nblocks, RedSpec spec, double* out, hipStream_t s) {
-  k_finalize<<<1, BS, 0, s>>>(partials, nblocks, spec, out);
+  k_finalize<<<1, BS, 0, s>>>(partials, nblocks, spec, out, launch_gate());
 }
 
 void launch_jac_eval(const DevProblem& P, const double* x, double* jv, hipStream_t s) {
   if (P.nnz_j == 0) return;
-  k_jac_eval<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.ja, P.jw, P.jc, x, jv);
+  k_jac_eval<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.ja, P.jw, P.jc, x, jv, launch_gate());
 }
 void launch_constraints(const DevProblem& P, const double* x, double* g, hipStream_t s) {
   if (P.m == 0) return;
-  k_constraints<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, P.ja, P.jw, x, P.b, g);
+  k_constraints<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, P.ja, P.jw, x, P.b, g, launch_gate());
 }
 void launch_gradient(const DevProblem& P, const double* x, double* qx, double* gf, hipStream_t s) {
-  k_gradient<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, P.hq, P.c, P.q4, x, qx, gf);
+  k_gradient<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, P.hq, P.c, P.q4, x, qx, gf, launch_gate());
 }
 void launch_hess_eval(const DevProblem& P, const double* x, const double* lam, double* hv, hipStream_t s) {
   k_hess_eval<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hp, P.hdiag, P.hq, P.q4, P.jtp, P.jtr, P.jte,
-                                                        P.jw, x, lam, hv);
+                                                        P.jw, x, lam, hv, launch_gate());
 }
 void launch_jt_mul(const DevProblem& P, const double* jv, const double* y, double* out, hipStream_t s) {
-  k_jt_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, y, out);
+  k_jt_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, y, out, launch_gate());
 }
 void launch_j_mul(const DevProblem& P, const double* jv, const double* v, double* out, hipStream_t s) {
   if (P.m == 0) return;
-  k_j_mul<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, jv, v, out);
+  k_j_mul<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, jv, v, out, launch_gate());
 }
 void launch_h_mul(const DevProblem& P, const double* hv, const double* v, double* out, hipStream_t s) {
-  k_h_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, hv, v, out);
+  k_h_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, hv, v, out, launch_gate());
 }
 
 template <typename T>
 void launch_assemble(const DevKMap& K, const double* hv, const double* jv, const double* sig_s,
                      const double* sig_x, double delta_p, T* panel, double* kval, hipStream_t s) {
-  k_assemble<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, hv, jv, sig_s, sig_x, delta_p, panel, kval);
+  k_assemble<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, hv, jv, sig_s, sig_x, delta_p, panel, kval, launch_gate());
 }
 template void launch_assemble<double>(const DevKMap&, const double*, const double*, const double*,
                                       const double*, double, double*, double*, hipStream_t);
@@ -1565,14 +1630,14 @@ template void launch_assemble<float>(const DevKMap&, const double*, const double
                                      const double*, double, float*, double*, hipStream_t);
 template <typename T>
 void launch_set_values(const DevKMap& K, const double* kval, T* panel, hipStream_t s) {
-  k_set_values<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, panel);
+  k_set_values<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, panel, launch_gate());
 }
 template void launch_set_values<double>(const DevKMap&, const double*, double*, hipStream_t);
 template void launch_set_values<float>(const DevKMap&, const double*, float*, hipStream_t);
 
 void launch_k_mul_stored(int64_t n, const int64_t*, const int32_t*, const int64_t* ksp, const int32_t* ksc,
                          const int64_t* kss, const double* kval, const double* v, double* out, hipStream_t s) {
-  k_k_mul_stored<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, ksp, ksc, kss, kval, v, out);
+  k_k_mul_stored<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, ksp, ksc, kss, kval, v, out, launch_gate());
 }
 
 template <typename T>
@@ -1580,16 +1645,16 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
   if (op.grid <= 0) return;
   const unsigned g = (unsigned)op.grid;
   switch (op.type) {
-    case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf); break;
-    case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad); break;
+    case OP_EXTEND_ADD: k_extend_add<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, launch_gate()); break;
+    case OP_SMALL: k_small_front<T><<<g, BS, 0, s>>>(P, op.begin, panel, ubuf, bad, launch_gate()); break;
     case OP_POTRF:
       if (P.sign) {
-        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
-        else k_potrf<T, 128, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad, launch_gate());
+        else k_potrf<T, 128, 256, true><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad, launch_gate());
       } else {
-        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
-        else if (op.grid <= 256) k_potrf<T, 128, 512, false><<<g, 512, 0, s>>>(P, op.begin, panel, inv, bad);
-        else k_potrf<T, 128, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad);
+        if constexpr (sizeof(T) == 8) k_potrf<T, 64, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad, launch_gate());
+        else if (op.grid <= 256) k_potrf<T, 128, 512, false><<<g, 512, 0, s>>>(P, op.begin, panel, inv, bad, launch_gate());
+        else k_potrf<T, 128, 256, false><<<g, 256, 0, s>>>(P, op.begin, panel, inv, bad, launch_gate());
       }
       break;
     case OP_TRSM:
@@ -1597,12 +1662,12 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
       const unsigned g8 = (unsigned)((op.grid + 7) / 8 * 8);
       if (P.sign) {
         if constexpr (sizeof(T) == 8)
-          k_gemm_f64<true><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
-        else k_gemm_f32<true><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+          k_gemm_f64<true><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv, launch_gate());
+        else k_gemm_f32<true><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv, launch_gate());
       } else {
         if constexpr (sizeof(T) == 8)
-          k_gemm_f64<false><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
-        else k_gemm_f32<false><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv);
+          k_gemm_f64<false><<<g8, BS64, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv, launch_gate());
+        else k_gemm_f32<false><<<g8, BS32, 0, s>>>(P, op.begin, op.end, op.grid, panel, ubuf, inv, launch_gate());
       }
       break;
     }
@@ -1612,29 +1677,29 @@ template void launch_factor_op<double>(const Op&, const DevPlan&, double*, doubl
 template void launch_factor_op<float>(const Op&, const DevPlan&, float*, float*, float*, int*, hipStream_t);
 
 void launch_sign_scale(int64_t n, const signed char* sign, double* y, hipStream_t s) {
-  if (n > 0) k_sign_scale<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, sign, y);
+  if (n > 0) k_sign_scale<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, sign, y, launch_gate());
 }
 void launch_assemble_aug(const DevKMap& K, int64_t n, const double* hv, const double* jv, const double* sig_s,
                          const double* sig_x, double delta_p, double* kval, hipStream_t s) {
-  k_assemble_aug<<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, n, hv, jv, sig_s, sig_x, delta_p, kval);
+  k_assemble_aug<<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, n, hv, jv, sig_s, sig_x, delta_p, kval, launch_gate());
 }
 void launch_permute_in(const DevPlan& P, const double* rhs, const double* d, double* xp, hipStream_t s) {
-  k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, d, xp);
+  k_permute_in<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, rhs, d, xp, launch_gate());
 }
 void launch_permute_out(const DevPlan& P, const double* xp, const double* d, double* x, hipStream_t s) {
-  k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, d, x);
+  k_permute_out<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.perm, xp, d, x, launch_gate());
 }
 void launch_diag_scale(int64_t n, const int64_t* kp, const double* kval, double* d, double* partials,
                        hipStream_t s, int64_t npos) {
   int g = red_grid(n);
-  k_diag_scale<<<g, BS, 0, s>>>(n, kp, kval, d, partials, npos);
+  k_diag_scale<<<g, BS, 0, s>>>(n, kp, kval, d, partials, npos, launch_gate());
   RedSpec spec{3, {RED_MAX, RED_SUM, RED_MIN}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 template <typename T>
 void launch_set_scaled(const DevKMap& K, const double* kval, const double* d, double shift, T* panel,
                        hipStream_t s) {
-  k_set_scaled<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, d, shift, panel);
+  k_set_scaled<T><<<(unsigned)blocks_for(K.nk), BS, 0, s>>>(K, kval, d, shift, panel, launch_gate());
 }
 template void launch_set_scaled<float>(const DevKMap&, const double*, const double*, double, float*, hipStream_t);
 template void launch_set_scaled<double>(const DevKMap&, const double*, const double*, double, double*, hipStream_t);
@@ -1644,12 +1709,12 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
   if (op.grid <= 0) return;
   const unsigned g = (unsigned)op.grid;
   switch (op.type) {
-    case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec); break;
-    case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec); break;
-    case OP_FWD_STEP: k_fwd_step<T><<<g, SBS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec); break;
-    case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys); break;
-    case OP_BWD_PART: k_bwd_part<T><<<g, SBS, 0, s>>>(P, op.begin, panel, ys, part); break;
-    case OP_BWD_DIAG: k_bwd_diag<T><<<g, SBS, 0, s>>>(P, op.begin, inv, ys, part); break;
+    case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec, launch_gate()); break;
+    case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec, launch_gate()); break;
+    case OP_FWD_STEP: k_fwd_step<T><<<g, SBS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec, launch_gate()); break;
+    case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, launch_gate()); break;
+    case OP_BWD_PART: k_bwd_part<T><<<g, SBS, 0, s>>>(P, op.begin, panel, ys, part, launch_gate()); break;
+    case OP_BWD_DIAG: k_bwd_diag<T><<<g, SBS, 0, s>>>(P, op.begin, inv, ys, part, launch_gate()); break;
   }
 }
 template void launch_solve_op<double>(const Op&, const DevPlan&, const double*, const double*, double*, double*,
@@ -1661,39 +1726,39 @@ void launch_residuals(const DevProblem& P, IpmVecs& v, hipStream_t s) {
   // J' lambda into tmp_n
   launch_jt_mul(P, v.jv, v.lam, v.tmp_n, s);
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_residuals<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v.tmp_n, v.gf, v.zl, v.zu, v.g, v.s, v.rd, v.rp);
+  k_residuals<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v.tmp_n, v.gf, v.zl, v.zu, v.g, v.s, v.rd, v.rp, launch_gate());
 }
 void launch_stats_iter(const DevProblem& P, IpmVecs& v, double* partials, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
   int g = red_grid(N);
-  k_stats_iter<<<g, BS, 0, s>>>(P, v, partials);
+  k_stats_iter<<<g, BS, 0, s>>>(P, v, partials, launch_gate());
   RedSpec spec{7, {RED_MAX, RED_MAX, RED_MAX, RED_MAX, RED_SUM, RED_SUM, RED_SUM}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_sigmas(const DevProblem& P, IpmVecs& v, double dd, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_sigmas<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, dd);
+  k_sigmas<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, dd, launch_gate());
 }
 void launch_rhs(const DevProblem& P, IpmVecs& v, const double* ts, const double* tl, const double* tu,
                 double* rhs, hipStream_t s) {
-  if (P.m > 0) k_rhs_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, ts, v.tmp_m);
+  if (P.m > 0) k_rhs_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, ts, v.tmp_m, launch_gate());
   launch_jt_mul(P, v.jv, v.tmp_m, v.tmp_n, s);
-  k_rhs_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, v.tmp_n, tl, tu, rhs);
+  k_rhs_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, v.tmp_n, tl, tu, rhs, launch_gate());
 }
 void launch_recover(const DevProblem& P, IpmVecs& v, const double* dx, const double* ts, const double* tl,
                     const double* tu, double dd, double* ds, double* dlam, double* dzl, double* dzu,
                     hipStream_t s) {
   if (P.m > 0) {
     launch_j_mul(P, v.jv, dx, v.tmp_m, s);
-    k_recover_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, v.tmp_m, ts, dd, ds, dlam);
+    k_recover_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, v.tmp_m, ts, dd, ds, dlam, launch_gate());
   }
-  k_recover_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, dx, tl, tu, dzl, dzu);
+  k_recover_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, dx, tl, tu, dzl, dzu, launch_gate());
 }
 void launch_step_limits(const DevProblem& P, IpmVecs& v, const double* dx, const double* ds, const double* dlam,
                         const double* dzl, const double* dzu, double* partials, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
   int g = red_grid(N);
-  k_step_limits<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, partials);
+  k_step_limits<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, partials, launch_gate());
   RedSpec spec{2, {RED_MIN, RED_MIN}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
@@ -1701,7 +1766,7 @@ void launch_mu_aff(const DevProblem& P, IpmVecs& v, const double* dx, const doub
                    const double* dzl, const double* dzu, double ap, double ad, double* partials, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
   int g = red_grid(N);
-  k_mu_aff<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, ap, ad, partials);
+  k_mu_aff<<<g, BS, 0, s>>>(P, v, dx, ds, dlam, dzl, dzu, ap, ad, partials, launch_gate());
   RedSpec spec{1, {RED_SUM}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
@@ -1709,40 +1774,40 @@ void launch_targets(const DevProblem& P, const double* dx, const double* ds, con
                     const double* dzl, const double* dzu, double smu, double* ts, double* tl, double* tu,
                     hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_targets<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dx, ds, dlam, dzl, dzu, smu, ts, tl, tu);
+  k_targets<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dx, ds, dlam, dzl, dzu, smu, ts, tl, tu, launch_gate());
 }
 void launch_axpy_point(const DevProblem& P, IpmVecs& dst, const IpmVecs& src, const double* dx, const double* ds,
                        const double* dlam, const double* dzl, const double* dzu, double ap, double ad,
                        hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_axpy_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dst, src, dx, ds, dlam, dzl, dzu, ap, ad);
+  k_axpy_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, dst, src, dx, ds, dlam, dzl, dzu, ap, ad, launch_gate());
 }
 void launch_phi(const DevProblem& P, IpmVecs& v, double smu, double* partials, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
   int g = red_grid(N);
-  k_phi<<<g, BS, 0, s>>>(P, v, smu, partials);
+  k_phi<<<g, BS, 0, s>>>(P, v, smu, partials, launch_gate());
   RedSpec spec{1, {RED_SUM}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_init_point(const DevProblem& P, IpmVecs& v, hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_init_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v);
+  k_init_point<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, launch_gate());
   launch_constraints(P, v.x, v.g, s);
-  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 0);
+  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 0, launch_gate());
 }
 void launch_push_start(const DevProblem& P, IpmVecs& v, const double* xhat, const double* lamhat, double,
                        hipStream_t s) {
   int64_t N = P.n > P.m ? P.n : P.m;
-  k_push_x<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, xhat, lamhat);
+  k_push_x<<<(unsigned)blocks_for(N), BS, 0, s>>>(P, v, xhat, lamhat, launch_gate());
   launch_constraints(P, v.x, v.g, s);
-  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 1);
+  if (P.m > 0) k_slack_from_g<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P, v, 1, launch_gate());
 }
 void launch_push_duals(const DevProblem& P, IpmVecs& v, double mu_w, hipStream_t s) {
-  k_push_duals<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, mu_w);
+  k_push_duals<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P, v, mu_w, launch_gate());
 }
 void launch_sum_sl(const DevProblem& P, IpmVecs& v, double* partials, hipStream_t s) {
   int g = red_grid(P.m > 0 ? P.m : 1);
-  k_sum_sl<<<g, BS, 0, s>>>(P, v, partials);
+  k_sum_sl<<<g, BS, 0, s>>>(P, v, partials, launch_gate());
   RedSpec spec{1, {RED_SUM}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
@@ -1753,60 +1818,60 @@ void launch_k_mul_free(const DevProblem& P, const double* jv, const double* hv, 
   launch_h_mul(P, hv, v, out, s);
   if (P.m > 0) {
     launch_j_mul(P, jv, v, tmp_m, s);
-    k_kfree_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, sig_s, tmp_m);
+    k_kfree_m<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, sig_s, tmp_m, launch_gate());
     launch_jt_mul(P, jv, tmp_m, tmp_n, s);
   } else {
     launch_fill_f64(tmp_n, P.n, 0.0, s);
   }
-  k_kfree_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, out, tmp_n, sig_x, dp, v, out);
+  k_kfree_n<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, out, tmp_n, sig_x, dp, v, out, launch_gate());
 }
 void launch_residual_norms(int64_t n, const double* rhs, const double* kx, const double* x, double* r,
                            double* partials, hipStream_t s) {
   int g = red_grid(n);
-  k_residual_norms<<<g, BS, 0, s>>>(n, rhs, kx, x, r, partials);
+  k_residual_norms<<<g, BS, 0, s>>>(n, rhs, kx, x, r, partials, launch_gate());
   RedSpec spec{3, {RED_MAX, RED_MAX, RED_MAX}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_dot(int64_t n, const double* a, const double* b, double* partials, hipStream_t s) {
   int g = red_grid(n);
-  k_dot<<<g, BS, 0, s>>>(n, a, b, partials);
+  k_dot<<<g, BS, 0, s>>>(n, a, b, partials, launch_gate());
   RedSpec spec{1, {RED_SUM}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_cg_step(int64_t n, double alpha, const double* p, const double* q, double* x, double* r,
                     double* partials, hipStream_t s) {
   int g = red_grid(n);
-  k_cg_step<<<g, BS, 0, s>>>(n, alpha, p, q, x, r, partials);
+  k_cg_step<<<g, BS, 0, s>>>(n, alpha, p, q, x, r, partials, launch_gate());
   RedSpec spec{2, {RED_MAX, RED_MAX}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_xpby(int64_t n, const double* z, double beta, double* p, hipStream_t s) {
-  k_xpby<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, z, beta, p);
+  k_xpby<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, z, beta, p, launch_gate());
 }
 void launch_dual_prep(const DevProblem& P, const double* hv, const double* sig_x, const double* sig_s,
                       double delta_p, double* dd, double* de, hipStream_t s) {
   const int64_t len = P.n > P.m ? P.n : P.m;
-  k_dual_prep<<<(unsigned)blocks_for(len), BS, 0, s>>>(P.n, P.m, hv, P.hdiag, sig_x, sig_s, delta_p, dd, de);
+  k_dual_prep<<<(unsigned)blocks_for(len), BS, 0, s>>>(P.n, P.m, hv, P.hdiag, sig_x, sig_s, delta_p, dd, de, launch_gate());
 }
 void launch_mul_vec(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
-  if (n > 0) k_mul_vec<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, a, b, out);
+  if (n > 0) k_mul_vec<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, a, b, out, launch_gate());
 }
 void launch_dual_finish(int64_t n, const double* d, const double* r, const double* w, double* out,
                         hipStream_t s) {
-  if (n > 0) k_dual_finish<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, r, w, out);
+  if (n > 0) k_dual_finish<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, r, w, out, launch_gate());
 }
 void launch_kdiag_max(const DevProblem& P, const double* jv, const double* sig_s, const double* dd,
                       double* partials, hipStream_t s) {
   int g = red_grid(P.n);
-  k_kdiag_max<<<g, BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, sig_s, dd, partials);
+  k_kdiag_max<<<g, BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, sig_s, dd, partials, launch_gate());
   RedSpec spec{1, {RED_MAX}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }
 void launch_add(int64_t n, double* x, const double* c, hipStream_t s) {
-  k_add<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, x, c);
+  k_add<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, x, c, launch_gate());
 }
 void launch_copy(int64_t n, double* d, const double* src, hipStream_t s) {
-  if (n > 0) k_copy<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, src);
+  if (n > 0) k_copy<<<(unsigned)blocks_for(n), BS, 0, s>>>(n, d, src, launch_gate());
 }
 
 }  // namespace pdipm

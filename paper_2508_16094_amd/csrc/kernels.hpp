@@ -38,6 +38,13 @@ struct DevKMap {
   const int64_t *tp, *pos;
 };
 
+// Gate of the kernels this host thread launches: null (every kernel runs),
+// or a device int that each kernel reads first, exiting when it is zero.
+// A batched solve captures several iterations in one graph and gates their
+// kernels by device flags, so iterations it does not need cost no work.
+void set_launch_gate(const int* gate);
+const int* launch_gate();
+
 // reductions: partial results per block, then one finalising block
 constexpr int RED_SUM = 0, RED_MAX = 1, RED_MIN = 2;
 constexpr int RED_BLOCKS = 512;

@@ -40,7 +40,8 @@ class ipm_options(ctypes.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("max_wall_time", _f64), ("delta_p", _f64),
                 ("delta_d", _f64), ("precision", _i32), ("ir_max", _i32), ("ir_tol", _f64),
                 ("nd_leaf", _i32), ("amalg_menu", _i32), ("print_level", _i32),
-                ("fp64_fallback", _i32), ("use_graphs", _i32), ("kkt_form", _i32), ("ordering", _i32)]
+                ("fp64_fallback", _i32), ("use_graphs", _i32), ("graph_iters", _i32), ("kkt_form", _i32),
+                ("ordering", _i32)]
 
 
 class kkt_symbolic_stats(ctypes.Structure):

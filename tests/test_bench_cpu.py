@@ -28,19 +28,20 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
 def test_traffic_record_applies_only_to_its_source_and_launch_mix():
     bm = _bench()
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    key = "k_gemm_f32@lp_block200"
+    key = "k_gemm_f32@lp_block200_dual"
     assert key in rec
     r = rec[key]
     alg = r["algorithmic_bytes_per_launch"]
     if r["gemm_source_sha256"] == bm.gemm_source_digest():
-        assert bm.traffic_of("k_gemm_f32", "lp_block200", alg) == r["bytes_per_launch"]
-        assert bm.traffic_of("k_gemm_f32", "lp_block200", alg * 1.004) == r["bytes_per_launch"]
+        assert bm.traffic_of("k_gemm_f32", "lp_block200_dual", alg) == r["bytes_per_launch"]
+        assert bm.traffic_of("k_gemm_f32", "lp_block200_dual", alg * 1.004) == r["bytes_per_launch"]
     else:
-        assert bm.traffic_of("k_gemm_f32", "lp_block200", alg) is None
+        assert bm.traffic_of("k_gemm_f32", "lp_block200_dual", alg) is None
     # another launch mix, another workload or kernel: nothing is reported
-    assert bm.traffic_of("k_gemm_f32", "lp_block200", alg * 1.01) is None
-    assert bm.traffic_of("k_gemm_f32", "lp_block50", alg) is None
-    assert bm.traffic_of("k_gemm_f64", "lp_block200", alg) is None
+    assert bm.traffic_of("k_gemm_f32", "lp_block200_dual", alg * 1.01) is None
+    assert bm.traffic_of("k_gemm_f32", "lp_block50_dual", alg) is None
+    assert bm.traffic_of("k_gemm_f64", "lp_block200_dual", alg) is None
+    assert bm.traffic_of("k_gemm_f32", "lp_block200_primal", alg) is None
 
 
 def test_traffic_record_is_consistent():

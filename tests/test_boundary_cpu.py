@@ -184,6 +184,10 @@ def test_dual_form_rejects_what_it_cannot_solve():
         L.BatchSolver([w.qp_instance(60, 2)], kkt_form=L.PDIPM_KKT_DUAL)
     with pytest.raises(L.PdipmError):
         L.IpmSolver(w.lp_small(), kkt_form=4)
+    for gi in (0, 1001):
+        with pytest.raises(L.PdipmError) as e:
+            L.BatchSolver([w.qp_instance(60, 2)], graph_iters=gi)
+        assert e.value.code == L.PDIPM_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("name", ["lp_small", "qp", "nlp_grid", "lp_block"])

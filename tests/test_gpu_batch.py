@@ -63,6 +63,8 @@ def test_batch_matches_oracle(precision):
     results, info = b.solve()
     print(info, flush=True)
     assert info["solved"] == len(ps)
+    # the whole solve is one replay of one captured graph of iterations
+    assert info["graph_launches"] == 1
     _check(ps, refs, results, b.solution())
 
 
@@ -142,3 +144,78 @@ def test_batch_matches_single_instance_path():
         rs = s.solve()
         assert rs["status"] == 0 and r["status"] == 0
         assert abs(rs["f"] - r["f"]) / max(1.0, abs(rs["f"])) <= 1e-6
+
+
+def test_batch_fp32_miss_repeats_the_iteration_in_fp64():
+    """A tolerance of 1e-10 puts the refinement target (1e-2 tol (1 +
+    ||grad f||)) out of reach of a few FP32-preconditioned steps: running
+    instances miss it, do not take that iteration's step, and repeat it with
+    FP64 factors; the results still meet the parity rule at the tighter
+    tolerance's reference."""
+    ps = _problems()[:8]
+    refs = _refs(ps)
+    b = L.BatchSolver(ps, precision=L.PDIPM_FP32, tol=1e-10, ir_max=1).bind()
+    results, info = b.solve()
+    print(info, flush=True)
+    assert info["refine_misses"] >= 1 and info["fp64_from"] >= 0
+    assert info["graph_launches"] >= 1
+    _check(ps, refs, results, b.solution())
+    for r in results:
+        assert max(r["P"], r["D"], r["C"]) <= 1e-10
+
+
+def _same(a, b):
+    """Result lists equal entry by entry, NaN equal to NaN."""
+    assert len(a) == len(b)
+    for ra, rb in zip(a, b):
+        assert ra.keys() == rb.keys()
+        for k in ra:
+            assert ra[k] == rb[k] or (np.isnan(ra[k]) and np.isnan(rb[k])), (k, ra, rb)
+
+
+@pytest.mark.parametrize("precision", [L.PDIPM_FP64, L.PDIPM_FP32])
+def test_batch_graph_holds_whole_iterations(precision):
+    """With three iterations per graph the batch replays it several times
+    (the FP32 batch, whose tolerance one refinement step of FP32 factors
+    cannot reach, switches to FP64 factors inside a replay); the result
+    equals the eager launches' bit for bit."""
+    ps = _problems()[:5]
+    kw = dict(tol=1e-6) if precision == L.PDIPM_FP64 else dict(tol=1e-10, ir_max=1)
+    b = L.BatchSolver(ps, precision=precision, graph_iters=3, **kw).bind()
+    results, info = b.solve()
+    e = L.BatchSolver(ps, precision=precision, use_graphs=0, **kw).bind()
+    eager, einfo = e.solve()
+    print(info, einfo, flush=True)
+    assert info["iterations"] == einfo["iterations"] > 3
+    assert info["graph_launches"] == -(-(info["iterations"] + 1) // 3)
+    assert info["fp64_from"] == einfo["fp64_from"]
+    if precision == L.PDIPM_FP32:
+        assert info["fp64_from"] >= 1
+    _same(results, eager)
+    sb, se = b.solution(), e.solution()
+    for a, c in zip(sb, se):
+        for k in a:
+            assert np.array_equal(a[k], c[k]), k
+    _check(ps, _refs(ps), results, sb)
+
+
+def test_batch_iterates_stay_finite_at_a_tight_tolerance():
+    """At tol 1e-12 late FP64 factors of some blocks meet non-positive
+    pivots (ended instances are still factored).  Every instance ends OK or
+    NUMERICAL; either way the returned iterate and its measures are finite
+    (an instance with a non-finite direction ends at its last iterate, and
+    an instance that takes no step keeps its point exactly)."""
+    ps = _problems()[:5]
+    b = L.BatchSolver(ps, precision=L.PDIPM_FP64, tol=1e-12).bind()
+    results, info = b.solve()
+    e = L.BatchSolver(ps, precision=L.PDIPM_FP64, tol=1e-12, use_graphs=0).bind()
+    eager, _ = e.solve()
+    print(info, results, flush=True)
+    _same(results, eager)
+    for p, r, sol in zip(ps, results, b.solution()):
+        assert r["status"] in (L.PDIPM_OK, L.PDIPM_ERR_NUMERICAL), r
+        assert np.isfinite([r["f"], r["P"], r["D"], r["C"]]).all(), r
+        for k, vec in sol.items():
+            assert np.isfinite(vec).all(), (p.name, k)
+        chk = checker.check(p, sol["x"], sol["s"], sol["lam"], sol["zl"], sol["zu"])
+        assert abs(chk["f"] - r["f"]) <= 1e-9 * max(1.0, abs(r["f"])), (chk, r)
