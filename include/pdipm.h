@@ -397,7 +397,11 @@ int ipm_batch_set_stream(ipm_batch* b, void* hip_stream);
 int ipm_batch_blockings(ipm_batch* b, int32_t* count, int32_t* small_h, int32_t* outer_blocks);
 int ipm_batch_set_blocking(ipm_batch* b, int32_t index);
 /* Times reps factorisations per candidate at the cold start point, keeps the
- * fastest; ms (NULL or count entries) receives each candidate's best time. */
+ * fastest; ms (NULL or count entries) receives each candidate's best time.
+ * The choice is remembered for the rest of the process per size bucket
+ * (precision, instance count, order, nnz(L) and largest front, each rounded
+ * down to a power of two): a batch created later in the same bucket starts
+ * with it (ipm_batch_info.blocking reports the blocking a solve used). */
 int ipm_batch_autotune(ipm_batch* b, int32_t reps, int32_t* chosen, double* ms);
 /* Solve every instance.  start: NULL (cold) or concatenated x (sum n_i) and
  * lambda (sum m_i), pushed into the interior per instance.  res: NULL or

@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <stdexcept>
@@ -42,13 +44,13 @@ size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
 // Largest plan arrays over the blocking candidates of a batch (the
 // workspace is laid out for all of them, so switching needs no new memory).
 struct PlanCaps {
-  size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0;
+  size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0, icomb = 0;
   int64_t inv = 0, part = 1;
   void add(const Plan& P) {
     gemm = std::max(gemm, bytes_of(P.gemm)); potrf = std::max(potrf, bytes_of(P.potrf));
     ext = std::max(ext, bytes_of(P.ext)); small = std::max(small, bytes_of(P.small));
     sdesc = std::max(sdesc, bytes_of(P.sdesc)); ssmall = std::max(ssmall, bytes_of(P.ssmall));
-    slarge = std::max(slarge, bytes_of(P.slarge));
+    slarge = std::max(slarge, bytes_of(P.slarge)); icomb = std::max(icomb, bytes_of(P.icomb));
     inv = std::max(inv, P.inv_elems); part = std::max(part, P.part_elems);
   }
 };
@@ -82,7 +84,7 @@ struct ipm_handle {
     size_t c, b, q4, xl, xu, jp, jc, ja, jw, jtp, jtr, jte, hp, hc, hq, hdiag, hsp, hsc, hss;
     size_t kmrow, kmc, kmh, kmtp, kmtk, kmta, kmtb, kmpos, ksp, ksc, kss, kval, kmkp, dscale;
     size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
-    size_t gemm64, potrf64, gemm32, potrf32, ext, small;
+    size_t gemm64, potrf64, gemm32, potrf32, ext, small, icomb64;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
     size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
     size_t vec[55];
@@ -151,6 +153,22 @@ int fail(ipm_handle* h, int code, const std::string& msg) {
       return fail((h), PDIPM_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// Autotuned blockings remembered for the rest of the process, per size
+// bucket of a batch: precision, instance count, order, nnz(L) and largest
+// front, each as its power-of-two exponent.  A batch created later in a
+// bucket starts with the blocking its last autotune chose.
+using TuneKey = std::array<int, 5>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+TuneKey tune_key(const ipm_handle* h) {
+  auto lg = [](double v) { return v < 1 ? 0 : (int)std::ilogb(v); };
+  const Symbolic& s = h->sym;
+  int64_t maxf = 0;
+  for (size_t k = 0; k + 1 < s.sn_start.size(); ++k) maxf = std::max<int64_t>(maxf, s.sn_rowptr[k + 1] - s.sn_rowptr[k]);
+  return TuneKey{h->opt.precision, lg(h->bcount), lg((double)s.n), lg((double)s.nnz_L), lg((double)maxf)};
+}
+
 void finish_analysis(ipm_handle* h) {
   if (h->bcount > 0) {
     // blocking candidates of the autotuner; the workspace fits each of them
@@ -163,8 +181,13 @@ void finish_analysis(ipm_handle* h) {
       build_plan(h->sym, 4, &t, b);
       h->cap32.add(t);
     }
-    build_plan(h->sym, 8, &h->plan64, h->bcand[0]);
-    build_plan(h->sym, 4, &h->plan32, h->bcand[0]);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned.find(tune_key(h));
+      h->bblocking = it == g_tuned.end() ? 0 : it->second;
+    }
+    build_plan(h->sym, 8, &h->plan64, h->bcand[h->bblocking]);
+    build_plan(h->sym, 4, &h->plan32, h->bcand[h->bblocking]);
     map_k_to_panels(h->sym, h->plan64, &h->km);
   } else {
     // the FP32 plan on a second host thread while the FP64 plan and the map
@@ -251,6 +274,7 @@ void layout(ipm_handle* h) {
     o.sdesc64 = r.take(c64.sdesc); o.ssmall64 = r.take(c64.ssmall);
     o.sinv64 = r.take(bytes_of(h->plan64.sinv));
     o.slarge64 = r.take(c64.slarge);
+    o.icomb64 = r.take(c64.icomb);
   }
   if (h->need32) {
     o.gemm32 = r.take(c32.gemm); o.potrf32 = r.take(c32.potrf);
@@ -319,7 +343,7 @@ int upload_plans(ipm_handle* h) {
   UP(ext, P.ext); UP(small, P.small);
   if (h->need64) {
     UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc); UP(sinv64, h->plan64.sinv);
-    UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge);
+    UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge); UP(icomb64, h->plan64.icomb);
   }
   if (h->need32) {
     UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc); UP(sinv32, h->plan32.sinv);
@@ -401,6 +425,7 @@ int bind_workspace(ipm_handle* h) {
     q.ssmall = at<int32_t>(h, prec == 0 ? o.ssmall64 : o.ssmall32);
     q.slarge = at<int32_t>(h, prec == 0 ? o.slarge64 : o.slarge32);
     q.sinv = at<int64_t>(h, prec == 0 ? o.sinv64 : o.sinv32);
+    q.icomb = prec == 0 ? at<InvCombDesc>(h, o.icomb64) : nullptr;
     q.sign = h->psign.empty() ? nullptr : at<signed char>(h, o.sign);
   }
   h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;
@@ -1261,6 +1286,8 @@ int batch_autotune(ipm_handle* h, int32_t* chosen, double* ms_out, int reps) {
   }
   if ((rc = set_blocking(h, besti))) return rc;
   if (chosen) *chosen = besti;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[tune_key(h)] = besti;
   return PDIPM_OK;
 }
 

@@ -536,14 +536,38 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       P.rel[e] = (int32_t)q;
     }
   }
-  // permanent storage of the inverses of the diagonal blocks (large fronts)
+  // permanent storage of the inverses of the diagonal blocks (large fronts):
+  // nb-column blocks for the factorisation's panel solves (finv), then, in
+  // FP64, the SOLVE_NB-column blocks of the triangular solves (sinv; the
+  // same blocks in FP32, where nb = SOLVE_NB)
   const int nb = P.nb;
-  P.sinv.assign(ns, -1);
+  std::vector<int64_t> finv(ns, -1);
   int64_t ioff = 0;
   for (int64_t k = 0; k < ns; ++k) {
     if (P.sh[k] <= P.small_h) continue;
-    P.sinv[k] = ioff;
+    finv[k] = ioff;
     ioff += (int64_t)((P.sw[k] + nb - 1) / nb) * nb * nb;
+  }
+  if (nb == SOLVE_NB) {
+    P.sinv = finv;
+  } else {
+    if (SOLVE_NB != 2 * nb) throw std::runtime_error("solve blocks must pair factor blocks");
+    P.sinv.assign(ns, -1);
+    for (int64_t k = 0; k < ns; ++k) {
+      if (finv[k] < 0) continue;
+      P.sinv[k] = ioff;
+      for (int32_t c0 = 0; c0 < P.sw[k]; c0 += SOLVE_NB) {
+        InvCombDesc d{};
+        d.bw = std::min(SOLVE_NB, P.sw[k] - c0);
+        d.x1_off = finv[k] + (int64_t)(c0 / nb) * nb * nb;
+        d.x2_off = d.bw > nb ? d.x1_off + (int64_t)nb * nb : -1;
+        d.ld = P.sld[k];
+        d.l21_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0 + nb;
+        d.out_off = ioff;
+        P.icomb.push_back(d);
+        ioff += (int64_t)SOLVE_NB * SOLVE_NB;
+      }
+    }
   }
   P.inv_elems = std::max<int64_t>(1, ioff);
   // launch schedule, level by level
@@ -615,7 +639,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
           int32_t bw = std::min(nb, P.sw[k] - c0);
           PotrfDesc d;
           d.d_off = P.spanel[k] + (int64_t)c0 * P.sld[k] + c0;
-          d.inv_off = P.sinv[k] + (int64_t)(c0 / nb) * nb * nb;
+          d.inv_off = finv[k] + (int64_t)(c0 / nb) * nb * nb;
           d.ld = P.sld[k];
           d.bw = bw;
           d.col0 = P.sfirst[k] + c0;
@@ -669,7 +693,11 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
       P.gemm_flops += gemm_desc_flops(g);
     }
   }
-  // ---- triangular solve schedule (same levels; large fronts blocked by nb)
+  if (!P.icomb.empty())
+    P.ops.push_back({OP_INV_COMBINE, 0, (int64_t)P.icomb.size(), (int64_t)P.icomb.size()});
+  // ---- triangular solve schedule (same levels; large fronts blocked by
+  // SOLVE_NB columns)
+  const int snb = SOLVE_NB;
   const int RB = 256;  // rows per forward work item
   for (int l = 0; l < P.nlevels; ++l) {
     std::vector<int32_t> large;
@@ -687,11 +715,11 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     P.fwd_ops.push_back({OP_FWD_GATHER, gb, (int64_t)P.slarge.size(), (int64_t)large.size()});
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
-    for (int32_t c0 = 0; c0 < maxw; c0 += nb) {
+    for (int32_t c0 = 0; c0 < maxw; c0 += snb) {
       int64_t db = (int64_t)P.sdesc.size();
       for (int32_t k : large) {
         if (P.sw[k] <= c0) continue;
-        int32_t bw = std::min(nb, P.sw[k] - c0);
+        int32_t bw = std::min(snb, P.sw[k] - c0);
         for (int32_t r0 = c0 + bw; r0 < P.sh[k]; r0 += RB) {
           SolveDesc d{};
           d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RB, P.sh[k]);
@@ -719,15 +747,15 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     if (large.empty()) continue;
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
-    const int32_t nsteps = (maxw + nb - 1) / nb;
+    const int32_t nsteps = (maxw + snb - 1) / snb;
     for (int32_t step = nsteps - 1; step >= 0; --step) {
-      const int32_t c0 = step * nb;
+      const int32_t c0 = step * snb;
       int64_t pb = (int64_t)P.sdesc.size();
       int64_t part = 0;
       std::vector<SolveDesc> diag;
       for (int32_t k : large) {
         if (P.sw[k] <= c0) continue;
-        int32_t bw = std::min(nb, P.sw[k] - c0);
+        int32_t bw = std::min(snb, P.sw[k] - c0);
         SolveDesc dd{};
         dd.sn = k; dd.c0 = c0; dd.bw = bw; dd.owner = 1; dd.part_off = part;
         int32_t np = 0;
@@ -735,7 +763,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
           SolveDesc d{};
           d.sn = k; d.c0 = c0; d.bw = bw; d.r0 = r0; d.r1 = std::min(r0 + RBB, P.sh[k]);
           d.part_off = part;
-          part += nb;
+          part += snb;
           ++np;
           P.sdesc.push_back(d);
         }

@@ -87,6 +87,19 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
   int32_t sn, t0, t1, pad;
 };
 
+// Column-block width of the blocked triangular solves, both precisions.
+// FP64 factorisations block by 64 columns; their solve inverses are formed
+// from pairs of 64 x 64 inverses after the factorisation:
+//   inv([L11 0; L21 L22]) = [X1 0; -X2 L21 X1  X2],  X1 = inv(L11), X2 = inv(L22).
+constexpr int SOLVE_NB = 128;
+
+struct InvCombDesc {       // one SOLVE_NB x SOLVE_NB solve inverse from two nb x nb ones
+  int64_t x1_off, x2_off;  // inverse-scratch offsets of X1 and X2 (x2_off < 0: bw <= nb)
+  int64_t l21_off;         // panel offset of L21 (rows c0 + nb .., columns c0 ..)
+  int64_t out_off;         // inverse-scratch offset of the result (ld SOLVE_NB)
+  int32_t ld, bw;          // panel leading dimension; columns of the block (<= SOLVE_NB)
+};
+
 // Blocked triangular-solve work item of supernode sn and column block
 // [c0, c0 + bw) over rows [r0, r1) below the block.  Forward: the owner
 // item also forms y of the next block.  Backward: partial products go to
@@ -106,6 +119,7 @@ struct SolveDesc {
 
 enum OpType {
   OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE,   // factorisation
+  OP_INV_COMBINE,                                                // solve inverses (FP64)
   OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_STEP,                      // forward solve
   OP_BWD_SMALL, OP_BWD_PART, OP_BWD_DIAG                         // backward solve
 };
@@ -136,8 +150,10 @@ struct Plan {
   std::vector<ExtAddDesc> ext;
   std::vector<int32_t> small;
   double update_bytes = 0;
-  // permanent inverses of the diagonal blocks of large supernodes
-  std::vector<int64_t> sinv;          // -1 for small supernodes
+  // permanent inverses of the SOLVE_NB-column diagonal blocks of large
+  // supernodes (the triangular solves' blocks; -1 for small supernodes)
+  std::vector<int64_t> sinv;
+  std::vector<InvCombDesc> icomb;     // FP64: their formation from 64-column inverses
   // triangular solves
   std::vector<Op> fwd_ops, bwd_ops;
   std::vector<SolveDesc> sdesc;

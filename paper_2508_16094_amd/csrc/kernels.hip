@@ -879,6 +879,68 @@ __global__ void k_permute_out(int64_t n, const int32_t* perm, const double* xp, 
   if (k < n) x[perm[k]] = d ? xp[k] * d[perm[k]] : xp[k];
 }
 
+// Solve inverses of SOLVE_NB-column diagonal blocks from the FP64
+// factorisation's 64-column ones (one workgroup per block):
+//   inv([L11 0; L21 L22]) = [X1 0; -X2 (L21 X1)  X2].
+// X1, X2 are lower triangular with zeros outside the block's columns, so
+// the products run over the triangles only and a partial block (bw <= 64:
+// no X2, or bw < 128: zero rows and columns) comes out zero-padded.
+__global__ void __launch_bounds__(256) k_inv_combine(DevPlan P, int64_t d0, const double* panel, double* inv,
+                                                     const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
+  constexpr int H = SOLVE_NB / 2, LD = H + 1, NT = 256, PER = H * H / NT;
+  __shared__ double X[H * LD], M[H * LD];
+  const InvCombDesc d = P.icomb[d0 + blockIdx.x];
+  const int tid = threadIdx.x, b2 = d.bw - H;
+  double* out = inv + d.out_off;
+  const double* X1 = inv + d.x1_off;
+  for (int idx = tid; idx < H * H; idx += NT) {
+    const int i = idx % H, j = idx / H;
+    X[i + j * LD] = X1[i + j * H];
+    M[i + j * LD] = i < b2 ? panel[d.l21_off + i + (int64_t)j * d.ld] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < H * H; idx += NT) {
+    const int i = idx % H, j = idx / H;
+    out[i + (int64_t)j * SOLVE_NB] = X[i + j * LD];
+    out[i + (int64_t)(j + H) * SOLVE_NB] = 0.0;
+  }
+  if (b2 <= 0) {
+    for (int idx = tid; idx < H * H; idx += NT) {
+      const int i = idx % H, j = idx / H;
+      out[(i + H) + (int64_t)j * SOLVE_NB] = 0.0;
+      out[(i + H) + (int64_t)(j + H) * SOLVE_NB] = 0.0;
+    }
+    return;
+  }
+  // T = L21 X1 (X1(k, j) = 0 for k < j)
+  double t[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + NT * q, i = idx % H, j = idx / H;
+    double acc = 0.0;
+    for (int k = j; k < H; ++k) acc += M[i + k * LD] * X[k + j * LD];
+    t[q] = acc;
+  }
+  __syncthreads();
+  const double* X2 = inv + d.x2_off;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + NT * q, i = idx % H, j = idx / H;
+    M[i + j * LD] = t[q];
+    X[i + j * LD] = X2[i + j * H];
+  }
+  __syncthreads();
+  // Y = -X2 T (X2(i, k) = 0 for k > i), and X2 itself
+  for (int idx = tid; idx < H * H; idx += NT) {
+    const int i = idx % H, j = idx / H;
+    double acc = 0.0;
+    for (int k = 0; k <= i; ++k) acc += X[i + k * LD] * M[k + j * LD];
+    out[(i + H) + (int64_t)j * SOLVE_NB] = -acc;
+    out[(i + H) + (int64_t)(j + H) * SOLVE_NB] = X[i + j * LD];
+  }
+}
+
 // Forward solve, small supernodes (h <= 64): one workgroup, vector in LDS.
 template <typename T>
 __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T* panel, const double* xp,
@@ -908,7 +970,7 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
 }
 
 // Inverse of a diagonal block (lower triangular, column-major, NB x NB
-// storage per block: NB = 128 in FP32, 64 in FP64) held in registers: wave w
+// storage per block, NB = SOLVE_NB) held in registers: wave w
 // keeps the columns j = w, w + NW, ... and every lane the rows lane (and
 // lane + 64).  The whole block is requested in one round of independent
 // loads (the gather kernel issues it before the vector it multiplies is
@@ -916,7 +978,7 @@ __global__ void __launch_bounds__(BS) k_fwd_small(DevPlan P, int64_t d0, const T
 // instead of one per column group.
 template <int NT, typename T>
 struct InvBlock {
-  static constexpr int NB = sizeof(T) == 4 ? 128 : 64, NW = NT / 64, JPW = NB / NW, RPL = NB / 64;
+  static constexpr int NB = SOLVE_NB, NW = NT / 64, JPW = NB / NW, RPL = NB / 64;
   T v[JPW][RPL];
   __device__ void load(const T* I) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1190,7 +1252,7 @@ template <typename T>
 __global__ void __launch_bounds__(SBS) k_bwd_diag(DevPlan P, int64_t d0, const T* inv, double* ys,
                                                 const double* part, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
-  constexpr int NB = sizeof(T) == 4 ? 128 : 64, CPW = 16, RPL = NB / 64;
+  constexpr int NB = SOLVE_NB, CPW = 16, RPL = NB / 64;
   constexpr int NG = SBS / NB, PU = 16;   // thread groups per column; partial loads per round
   __shared__ double z[NB], zp[NG * NB];
   const SolveDesc d = P.sdesc[d0 + blockIdx.x];
@@ -1671,6 +1733,9 @@ void launch_factor_op(const Op& op, const DevPlan& P, T* panel, T* ubuf, T* inv,
       }
       break;
     }
+    case OP_INV_COMBINE:
+      if constexpr (sizeof(T) == 8) k_inv_combine<<<g, 256, 0, s>>>(P, op.begin, panel, inv, launch_gate());
+      break;
   }
 }
 template void launch_factor_op<double>(const Op&, const DevPlan&, double*, double*, double*, int*, hipStream_t);

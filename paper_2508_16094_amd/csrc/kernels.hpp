@@ -25,6 +25,7 @@ struct DevPlan {
   const int32_t *sfirst, *sw, *sh, *sld, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
   const int64_t *spanel, *su, *srow, *suv, *sinv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
+  const InvCombDesc* icomb;
   const SolveDesc* sdesc; const int32_t *ssmall, *slarge;
   // pivot signs of a signed factorisation P'AP = L S L' (S = diag(sign),
   // permuted numbering; Section 2, SQD matrices); null: Cholesky, S = I

@@ -105,6 +105,11 @@ def test_batch_autotune_and_blockings():
     results, info = b.solve()
     assert info["blocking"] == other
     _check(ps, refs, results, b.solution())
+    # the tuned choice is remembered for batches of the same size bucket
+    b2 = L.BatchSolver(ps, precision=L.PDIPM_FP32).bind()
+    results, info = b2.solve()
+    assert info["blocking"] == chosen
+    _check(ps, refs, results, b2.solution())
 
 
 @pytest.mark.parametrize("precision", [L.PDIPM_FP64, L.PDIPM_FP32])
