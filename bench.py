@@ -382,6 +382,8 @@ def main():
                     help="skip the FP64 solve on the same handle (reported next to the FP32 form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--print-level", type=int, default=None,
+                    help="solver log on stderr (0 none, 1 per iteration, 2 per solve, 3 per refinement)")
     ap.add_argument("--count", type=int, default=4096, help="qp_batch: number of instances")
     ap.add_argument("--loop-sample", type=int, default=16, help="qp_batch: instances timed one at a time")
     ap.add_argument("--n-train", type=int, default=4096, help="warm: training instances")
@@ -428,7 +430,8 @@ def main():
     # refinement cannot reach the accuracy the iteration needs; the FP64
     # space also serves the FP64 comparison solve on the same handle
     form = FORMS[args.form]
-    s = L.IpmSolver(p, precision=prec, fp64_fallback=1, print_level=1 if args.verbose else 0, kkt_form=form)
+    s = L.IpmSolver(p, precision=prec, fp64_fallback=1, kkt_form=form,
+                    print_level=args.print_level if args.print_level is not None else (1 if args.verbose else 0))
     st = s.stats()
     chosen = FORM_NAMES[st["kkt_form"]]
     t_setup = time.time() - t

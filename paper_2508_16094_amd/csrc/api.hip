@@ -45,12 +45,15 @@ size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
 // workspace is laid out for all of them, so switching needs no new memory).
 struct PlanCaps {
   size_t gemm = 0, potrf = 0, ext = 0, small = 0, sdesc = 0, ssmall = 0, slarge = 0, icomb = 0;
+  size_t gitem = 0, grow = 0, gptr = 0, gidx = 0;
   int64_t inv = 0, part = 1;
   void add(const Plan& P) {
     gemm = std::max(gemm, bytes_of(P.gemm)); potrf = std::max(potrf, bytes_of(P.potrf));
     ext = std::max(ext, bytes_of(P.ext)); small = std::max(small, bytes_of(P.small));
     sdesc = std::max(sdesc, bytes_of(P.sdesc)); ssmall = std::max(ssmall, bytes_of(P.ssmall));
     slarge = std::max(slarge, bytes_of(P.slarge)); icomb = std::max(icomb, bytes_of(P.icomb));
+    gitem = std::max(gitem, bytes_of(P.gitem)); grow = std::max(grow, bytes_of(P.grow));
+    gptr = std::max(gptr, bytes_of(P.gptr)); gidx = std::max(gidx, bytes_of(P.gidx));
     inv = std::max(inv, P.inv_elems); part = std::max(part, P.part_elems);
   }
 };
@@ -86,6 +89,7 @@ struct ipm_handle {
     size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small, icomb64;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
+    size_t gitem[2], grow[2], gptr[2], gidx[2];   // forward gather map (FP64, FP32 plan)
     size_t panel, ubuf, inv, bad, partials, xperm, uvec, ysol, part, sinv64, sinv32;
     size_t vec[55];
     size_t sign;
@@ -275,12 +279,16 @@ void layout(ipm_handle* h) {
     o.sinv64 = r.take(bytes_of(h->plan64.sinv));
     o.slarge64 = r.take(c64.slarge);
     o.icomb64 = r.take(c64.icomb);
+    o.gitem[0] = r.take(c64.gitem); o.grow[0] = r.take(c64.grow);
+    o.gptr[0] = r.take(c64.gptr); o.gidx[0] = r.take(c64.gidx);
   }
   if (h->need32) {
     o.gemm32 = r.take(c32.gemm); o.potrf32 = r.take(c32.potrf);
     o.sdesc32 = r.take(c32.sdesc); o.ssmall32 = r.take(c32.ssmall);
     o.sinv32 = r.take(bytes_of(h->plan32.sinv));
     o.slarge32 = r.take(c32.slarge);
+    o.gitem[1] = r.take(c32.gitem); o.grow[1] = r.take(c32.grow);
+    o.gptr[1] = r.take(c32.gptr); o.gidx[1] = r.take(c32.gidx);
   }
   const size_t es = h->need64 ? 8 : 4;
   o.panel = r.take((size_t)P.panel_elems * es);
@@ -344,10 +352,14 @@ int upload_plans(ipm_handle* h) {
   if (h->need64) {
     UP(gemm64, h->plan64.gemm); UP(potrf64, h->plan64.potrf); UP(sdesc64, h->plan64.sdesc); UP(sinv64, h->plan64.sinv);
     UP(ssmall64, h->plan64.ssmall); UP(slarge64, h->plan64.slarge); UP(icomb64, h->plan64.icomb);
+    UP(gitem[0], h->plan64.gitem); UP(grow[0], h->plan64.grow); UP(gptr[0], h->plan64.gptr);
+    UP(gidx[0], h->plan64.gidx);
   }
   if (h->need32) {
     UP(gemm32, h->plan32.gemm); UP(potrf32, h->plan32.potrf); UP(sdesc32, h->plan32.sdesc); UP(sinv32, h->plan32.sinv);
     UP(ssmall32, h->plan32.ssmall); UP(slarge32, h->plan32.slarge);
+    UP(gitem[1], h->plan32.gitem); UP(grow[1], h->plan32.grow); UP(gptr[1], h->plan32.gptr);
+    UP(gidx[1], h->plan32.gidx);
   }
   return PDIPM_OK;
 }
@@ -426,6 +438,8 @@ int bind_workspace(ipm_handle* h) {
     q.slarge = at<int32_t>(h, prec == 0 ? o.slarge64 : o.slarge32);
     q.sinv = at<int64_t>(h, prec == 0 ? o.sinv64 : o.sinv32);
     q.icomb = prec == 0 ? at<InvCombDesc>(h, o.icomb64) : nullptr;
+    q.gitem = at<GatherItem>(h, o.gitem[prec]); q.grow = at<int64_t>(h, o.grow[prec]);
+    q.gptr = at<int64_t>(h, o.gptr[prec]); q.gidx = at<int64_t>(h, o.gidx[prec]);
     q.sign = h->psign.empty() ? nullptr : at<signed char>(h, o.sign);
   }
   h->panel = h->ws + o.panel; h->ubuf = h->ws + o.ubuf; h->inv = h->ws + o.inv;

@@ -695,10 +695,35 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   }
   if (!P.icomb.empty())
     P.ops.push_back({OP_INV_COMBINE, 0, (int64_t)P.icomb.size(), (int64_t)P.icomb.size()});
+  // ---- gather map of the forward solve: for each front row of a large
+  // supernode, its children's update-vector entries in child order
+  P.grow.assign(ns, -1);
+  for (int64_t k = 0; k < ns; ++k) {
+    if (P.sh[k] <= P.small_h) continue;
+    const int64_t base = (int64_t)P.gptr.size();
+    P.grow[k] = base;
+    P.gptr.resize(base + P.sh[k] + 1, 0);
+    int64_t* rp = P.gptr.data() + base;
+    for (int32_t q = P.child_ptr[k]; q < P.child_ptr[k + 1]; ++q) {
+      const int32_t c = P.child[q];
+      for (int64_t e = P.srow[c] + P.sw[c]; e < P.srow[c + 1]; ++e) rp[P.rel[e] + 1]++;
+    }
+    rp[0] = (int64_t)P.gidx.size();
+    for (int32_t r = 0; r < P.sh[k]; ++r) rp[r + 1] += rp[r];
+    P.gidx.resize(rp[P.sh[k]]);
+    std::vector<int64_t> pos(rp, rp + P.sh[k]);
+    for (int32_t q = P.child_ptr[k]; q < P.child_ptr[k + 1]; ++q) {
+      const int32_t c = P.child[q];
+      for (int64_t e = P.srow[c] + P.sw[c]; e < P.srow[c + 1]; ++e)
+        P.gidx[pos[P.rel[e]]++] = P.suv[c] + (e - P.srow[c] - P.sw[c]);
+    }
+  }
+  if (P.gptr.empty()) P.gptr.push_back(0);
+  if (P.gidx.empty()) P.gidx.push_back(0);
   // ---- triangular solve schedule (same levels; large fronts blocked by
   // SOLVE_NB columns)
   const int snb = SOLVE_NB;
-  const int RB = 256;  // rows per forward work item
+  const int RB = 128;  // rows per forward work item
   for (int l = 0; l < P.nlevels; ++l) {
     std::vector<int32_t> large;
     int64_t sb = (int64_t)P.ssmall.size();
@@ -712,7 +737,14 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
     if (large.empty()) continue;
     int64_t gb = (int64_t)P.slarge.size();
     for (int32_t k : large) P.slarge.push_back(k);
-    P.fwd_ops.push_back({OP_FWD_GATHER, gb, (int64_t)P.slarge.size(), (int64_t)large.size()});
+    // children's update vectors into the fronts (one row per thread), then
+    // y of each front's first column block
+    const int64_t ib = (int64_t)P.gitem.size();
+    for (int32_t k : large)
+      for (int32_t r0 = 0; r0 < P.sh[k]; r0 += GATHER_ROWS)
+        P.gitem.push_back({k, r0, std::min(r0 + GATHER_ROWS, P.sh[k]), 0});
+    P.fwd_ops.push_back({OP_FWD_GATHER, ib, (int64_t)P.gitem.size(), (int64_t)P.gitem.size() - ib});
+    P.fwd_ops.push_back({OP_FWD_FIRST, gb, (int64_t)P.slarge.size(), (int64_t)large.size()});
     int32_t maxw = 0;
     for (int32_t k : large) maxw = std::max(maxw, P.sw[k]);
     for (int32_t c0 = 0; c0 < maxw; c0 += snb) {
@@ -733,7 +765,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   }
   // backward: levels from the root down; column blocks from the last one:
   // partial products over row ranges below the block, then the block solve
-  const int RBB = 256;  // rows per backward partial item
+  const int RBB = 128;  // rows per backward partial item
   for (int l = P.nlevels - 1; l >= 0; --l) {
     std::vector<int32_t> large;
     int64_t sb = (int64_t)P.ssmall.size();

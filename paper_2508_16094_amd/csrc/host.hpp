@@ -53,9 +53,10 @@ struct KMap {
 constexpr int SMALL_H_MAX = 64;
 
 // Square tile edge of the Schur-update / panel-solve GEMM kernels.  FP64
-// 128 x 128 tiles (KC 16) ran the rank-512 updates 3% faster than 64 x 64
-// but wasted half of every tile of the 64-column panel solves and inner
-// updates: no net gain, so FP64 keeps 64 x 64.
+// 128 x 128 tiles ran the largest rank-512 updates up to 4% faster than
+// 64 x 64 but the 4096-row ones 20% slower and wasted half of every tile of
+// the 64-column panel solves and inner updates (the block-angular LP's
+// solve took 4% longer), so FP64 keeps 64 x 64.
 constexpr int GEMM_TILE_F32 = 128;
 constexpr int GEMM_TILE_F64 = 64;
 
@@ -92,6 +93,8 @@ struct ExtAddDesc {        // parent front, target front columns [t0, t1)
 // from pairs of 64 x 64 inverses after the factorisation:
 //   inv([L11 0; L21 L22]) = [X1 0; -X2 L21 X1  X2],  X1 = inv(L11), X2 = inv(L22).
 constexpr int SOLVE_NB = 128;
+// Front rows per forward gather item (one per thread of its workgroup).
+constexpr int GATHER_ROWS = 256;
 
 struct InvCombDesc {       // one SOLVE_NB x SOLVE_NB solve inverse from two nb x nb ones
   int64_t x1_off, x2_off;  // inverse-scratch offsets of X1 and X2 (x2_off < 0: bw <= nb)
@@ -117,10 +120,16 @@ struct SolveDesc {
   int32_t first, ld;       // first column, panel leading dimension
 };
 
+// Forward solve: rows [r0, r1) of the front of large supernode sn collect
+// their children's update-vector entries.
+struct GatherItem {
+  int32_t sn, r0, r1, pad;
+};
+
 enum OpType {
   OP_EXTEND_ADD = 0, OP_SMALL, OP_POTRF, OP_TRSM, OP_UPDATE,   // factorisation
   OP_INV_COMBINE,                                                // solve inverses (FP64)
-  OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_STEP,                      // forward solve
+  OP_FWD_SMALL, OP_FWD_GATHER, OP_FWD_FIRST, OP_FWD_STEP,        // forward solve
   OP_BWD_SMALL, OP_BWD_PART, OP_BWD_DIAG                         // backward solve
 };
 
@@ -158,6 +167,11 @@ struct Plan {
   std::vector<Op> fwd_ops, bwd_ops;
   std::vector<SolveDesc> sdesc;
   std::vector<int32_t> ssmall, slarge; // supernode lists used by the solve ops
+  // forward gather of large supernodes: per front row, the update-vector
+  // offsets of the children's entries for that row in child order (rows of
+  // supernode k at gptr[grow[k] ..], -1 for small supernodes)
+  std::vector<GatherItem> gitem;
+  std::vector<int64_t> grow, gptr, gidx;
   int64_t part_elems = 1;              // backward partial sums (max per step)
   // algorithmic work of the Schur-update / panel-solve GEMM launches of one
   // factorisation (useful multiply-add flops, triangles not double counted)

@@ -695,10 +695,12 @@ __device__ inline double2u load2(const double* p, int valid) {
   return v;
 }
 
-// C (-)= A * B^T, FP64 MFMA 16x16x4.  TM x TM tile per workgroup of eight
-// waves, each a (16 BX) x (16 BY) strip of BX x BY MFMA blocks; K chunks of
-// 32 (16 for 128 x 128 tiles, to fit two workgroups per CU) staged through
-// LDS with the next chunk prefetched into registers.
+// C (-)= A * B^T, FP64 MFMA 16x16x4.  64 x 64 tile per workgroup of eight
+// waves, each a 32 x 16 strip of 2 x 1 MFMA blocks; K chunks of 16 staged
+// through LDS with the next chunk prefetched into registers (one 16-byte
+// load per operand and thread).  Against 16 x 32 strips and 32-deep chunks
+// this ran the rank-512 updates 3-6% faster (55 -> 58.5 TFLOP/s on an
+// 8192-row lower update).
 // SG: signed factorisation (L S L'): updates subtract A S B' (the sign of
 // inner index k, at permuted column kcol + k, applied to A), the panel solve
 // scales output column j by the sign at kcol + j.
@@ -707,10 +709,11 @@ template <bool SG>
 __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, double* panel,
                                                    double* ubuf, const double* inv, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
-  constexpr int TM = GEMM_TILE_F64, BX = TM == 128 ? 4 : 1, BY = 2;
+  constexpr int TM = GEMM_TILE_F64, BX = 2, BY = 1;
   constexpr int WX = TM / (16 * BX);                       // waves along rows
   static_assert(WX * (TM / (16 * BY)) == BS64 / 64, "eight waves per tile");
-  constexpr int KC = TM == 128 ? 16 : 32, LDS_LD = TM + 2, TPR = TM / 2, KS = BS64 / TPR, PER = KC / KS;
+  constexpr int KC = 16, LDS_LD = TM + 2, TPR = TM / 2, KS = BS64 / TPR, PER = KC / KS;
+  static_assert(PER >= 1 && PER * KS == KC, "whole rows of the chunk per load round");
   __shared__ double As[KC * LDS_LD];
   __shared__ double Bs[KC * LDS_LD];
   const int64_t bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -787,14 +790,15 @@ __global__ void __launch_bounds__(BS64) k_gemm_f64(DevPlan P, int64_t d0, int64_
 
 // C (-)= A * B^T, FP32 MFMA 32x32x2 with FP32 accumulation.  128x128 tile
 // per workgroup of eight waves, each a 64x32 strip (2x1 MFMA blocks); K is
-// staged through LDS in chunks of 32 with the next chunk prefetched into
-// registers.
+// staged through LDS in chunks of 16 with the next chunk prefetched into
+// registers (chunks of 32 ran the large lower updates 2-4% slower).
 constexpr int BS32 = 512;  // threads of the FP32 GEMM (8 waves)
 template <bool SG>
 __global__ void __launch_bounds__(BS32) k_gemm_f32(DevPlan P, int64_t d0, int64_t d1, int64_t ntiles, float* panel,
                                                    float* ubuf, const float* inv, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
-  constexpr int TM = GEMM_TILE_F32, KC = 32, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 8 per operand
+  constexpr int TM = GEMM_TILE_F32, KC = 16, LDS_LD = TM + 4, PER = (TM * KC) / BS32;  // 4 per operand
+  static_assert(PER % 4 == 0 && KC % 16 == 0, "16-byte loads at k offsets kb + 16 r");
   static_assert(TM == 128, "the FP32 wave layout assumes 128 x 128 tiles");
   __shared__ float As[KC * LDS_LD];
   __shared__ float Bs[KC * LDS_LD];
@@ -1018,33 +1022,42 @@ struct InvBlock {
     }
   }
 };
-// Forward solve, large supernodes: collect the children's update vectors,
-// then y for the first column block.
+// Forward solve, large supernodes: each front row sums its children's
+// update-vector entries (the plan's gather map lists them in child order,
+// so the sum is deterministic) into x (own columns) or into the front's
+// update vector (rows below).  One thread per row; rows of many fronts at
+// once, where one workgroup per front adding child after child serialised
+// the 200 children of a separator.
+__global__ void __launch_bounds__(GATHER_ROWS) k_fwd_gather(DevPlan P, int64_t d0, double* xp, double* uvec,
+                                                           const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
+  const GatherItem g = P.gitem[d0 + blockIdx.x];
+  const int32_t S = g.sn;
+  const int w = P.sw[S], f = P.sfirst[S];
+  const int64_t uo = P.suv[S];
+  const int64_t* rp = P.gptr + P.grow[S];
+  const int r = g.r0 + (int)threadIdx.x;
+  if (r >= g.r1) return;
+  double s = 0.0;
+  const int64_t k1 = rp[r + 1];
+#pragma unroll 4
+  for (int64_t k = rp[r]; k < k1; ++k) s += uvec[P.gidx[k]];
+  if (r < w) xp[f + r] += s;
+  else uvec[uo + r - w] = s;
+}
+
+// Forward solve, large supernodes: y of the first column block from the
+// gathered right-hand side.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_fwd_gather(DevPlan P, int64_t d0, const T* inv, double* xp, double* ys,
-                                                  double* uvec, const int* gate) {
+__global__ void __launch_bounds__(BS) k_fwd_first(DevPlan P, int64_t d0, const T* inv, const double* xp, double* ys,
+                                                 const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
   typedef InvBlock<BS, T> IB;
   __shared__ double tb[IB::NB], red[IB::NW * IB::NB];
   const int32_t S = P.slarge[d0 + blockIdx.x];
-  const int h = P.sh[S], w = P.sw[S], f = P.sfirst[S];
-  const int64_t uo = P.suv[S];
+  const int w = P.sw[S], f = P.sfirst[S];
   IB ib;
   ib.load(inv + P.sinv[S]);
-  for (int i = threadIdx.x; i < h - w; i += BS) uvec[uo + i] = 0.0;
-  __syncthreads();
-  for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
-    const int32_t c = P.child[q];
-    const int hu = P.sh[c] - P.sw[c];
-    const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
-    const double* uc = uvec + P.suv[c];
-    for (int i = threadIdx.x; i < hu; i += BS) {
-      const int r = rc[i];
-      if (r < w) xp[f + r] += uc[i];
-      else uvec[uo + r - w] += uc[i];
-    }
-    __syncthreads();
-  }
   const int bw = w < IB::NB ? w : IB::NB;
   if ((int)threadIdx.x < bw) tb[threadIdx.x] = xp[f + threadIdx.x];
   __syncthreads();
@@ -1775,7 +1788,8 @@ void launch_solve_op(const Op& op, const DevPlan& P, const T* panel, const T* in
   const unsigned g = (unsigned)op.grid;
   switch (op.type) {
     case OP_FWD_SMALL: k_fwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, xp, ys, uvec, launch_gate()); break;
-    case OP_FWD_GATHER: k_fwd_gather<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, uvec, launch_gate()); break;
+    case OP_FWD_GATHER: k_fwd_gather<<<g, GATHER_ROWS, 0, s>>>(P, op.begin, xp, uvec, launch_gate()); break;
+    case OP_FWD_FIRST: k_fwd_first<T><<<g, BS, 0, s>>>(P, op.begin, inv, xp, ys, launch_gate()); break;
     case OP_FWD_STEP: k_fwd_step<T><<<g, SBS, 0, s>>>(P, op.begin, panel, inv, xp, ys, uvec, launch_gate()); break;
     case OP_BWD_SMALL: k_bwd_small<T><<<g, BS, 0, s>>>(P, op.begin, panel, ys, launch_gate()); break;
     case OP_BWD_PART: k_bwd_part<T><<<g, SBS, 0, s>>>(P, op.begin, panel, ys, part, launch_gate()); break;

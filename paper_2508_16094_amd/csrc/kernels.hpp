@@ -26,6 +26,7 @@ struct DevPlan {
   const int64_t *spanel, *su, *srow, *suv, *sinv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
   const InvCombDesc* icomb;
+  const GatherItem* gitem; const int64_t *grow, *gptr, *gidx;
   const SolveDesc* sdesc; const int32_t *ssmall, *slarge;
   // pivot signs of a signed factorisation P'AP = L S L' (S = diag(sign),
   // permuted numbering; Section 2, SQD matrices); null: Cholesky, S = I
