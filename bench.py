@@ -57,7 +57,7 @@ def bench_batch(args, log):
     ps = w.qp_batch(args.count)
     sizes = np.array([p.n for p in ps])
     log(f"[bench] generated {len(ps)} QPs (sum n = {sizes.sum()}) in {time.time() - t:.1f}s")
-    prec = L.PDIPM_FP32 if args.precision == "fp32" else L.PDIPM_FP64
+    prec = L.PDIPM_FP64 if args.precision == "fp64" else L.PDIPM_FP32
     t = time.time()
     b = L.BatchSolver(ps, precision=prec, print_level=1 if args.verbose else 0)
     st = b.stats()
@@ -368,7 +368,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lp_block")
     ap.add_argument("--nblocks", type=int, default=200)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "auto"],
+                    help="factor precision; auto: the library keeps FP32 factors only where its cost model "
+                         "predicts they pay (batches: fp32)")
     ap.add_argument("--form", default="auto", choices=["auto", "primal", "dual", "augmented"],
                     help="KKT system factored each iteration: auto (the condensed system with fewer "
                          "factorisation flops), the primal condensed K (n x n), the dual condensed "
@@ -424,7 +426,7 @@ def main():
     t = time.time()
     p, name = make_problem(args)
     log(f"[bench] generated {name} in {time.time() - t:.1f}s")
-    prec = L.PDIPM_FP32 if args.precision == "fp32" else L.PDIPM_FP64
+    prec = {"fp32": L.PDIPM_FP32, "fp64": L.PDIPM_FP64, "auto": L.PDIPM_PRECISION_AUTO}[args.precision]
     t = time.time()
     # FP32 form: FP64 factors take over for the rest of a solve once FP32
     # refinement cannot reach the accuracy the iteration needs; the FP64
@@ -434,6 +436,7 @@ def main():
                     print_level=args.print_level if args.print_level is not None else (1 if args.verbose else 0))
     st = s.stats()
     chosen = FORM_NAMES[st["kkt_form"]]
+    prec = st["precision"]   # the automatic choice resolved
     t_setup = time.time() - t
     log(f"[bench] analysed in {t_setup:.1f}s: {chosen} system, order {st['n']}, nnz(L)={st['nnz_L']:.4g} "
         f"flops={st['flops']:.4g} "
@@ -508,7 +511,7 @@ def main():
         "dtype": "f32" if prec == L.PDIPM_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": name, "form": "fp32 factor + fp64 refinement" if prec == L.PDIPM_FP32 else "fp64",
-                   "kkt_system": FORM_TEXT[chosen], "kkt_choice": args.form,
+                   "kkt_system": FORM_TEXT[chosen], "kkt_choice": args.form, "precision_choice": args.precision,
                    "tol": 1e-6, "parallelism": "single GPU"},
         "status": last["status"], "iterations": last["iterations"], "f": last["f"],
         "fp64_refactors": last["fp64_refactors"], "refinement_steps": last["ir_steps"],

@@ -52,6 +52,7 @@ extern "C" {
 
 #define PDIPM_FP64 0              /* factor and solve in FP64 */
 #define PDIPM_FP32 1              /* FP32 factor + FP64 iterative refinement */
+#define PDIPM_PRECISION_AUTO 2    /* ipm_create: FP32 or FP64 factors, chosen once */
 
 #define PDIPM_HOST 0
 #define PDIPM_DEVICE 1
@@ -92,7 +93,17 @@ typedef struct ipm_options {
   double max_wall_time;  /* seconds, default 900 */
   double delta_p;        /* primal regularisation, default 1e-8 */
   double delta_d;        /* dual regularisation, default 1e-8 */
-  int32_t precision;     /* PDIPM_FP64 or PDIPM_FP32 (workspace sized for it) */
+  int32_t precision;     /* PDIPM_FP64 or PDIPM_FP32 (workspace sized for it).
+                            PDIPM_PRECISION_AUTO (ipm_create only): space for
+                            both, and ipm_create keeps FP32 factors with FP64
+                            refinement when the factorisation time they save,
+                            sum_j c_j^2 at 100 against 50 TFLOP/s, exceeds two
+                            FP32 triangular solves per iteration (2 nnz(L) 4
+                            bytes at 3 TB/s plus 6 us per launch), else FP64
+                            factors: on small or latency-bound systems FP32
+                            factors save nothing and refinement costs extra.
+                            From counts only, so the choice is deterministic;
+                            kkt_analyze reports it. */
   int32_t ir_max;        /* refinement steps per solve, default 10 */
   double ir_tol;         /* backward-error target of refinement, 1e-14 */
   int32_t nd_leaf;       /* minimum-degree leaf size of the ordering, 64 */
@@ -161,6 +172,8 @@ typedef struct kkt_symbolic_stats {
   double flops;          /* sum_j (c_j^2 - 1), the factorisation's work */
   double update_bytes;   /* bytes of front update matrices (per precision) */
   int32_t kkt_form;      /* the system factored (PDIPM_KKT_*; -1 standalone) */
+  int32_t precision;     /* factors a solve starts with: PDIPM_FP64 or
+                            PDIPM_FP32 (the automatic choice resolved) */
 } kkt_symbolic_stats;
 
 typedef struct kkt_factor_info {

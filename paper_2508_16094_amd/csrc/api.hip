@@ -1393,9 +1393,15 @@ static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** ou
     delete h;
     return fail(nullptr, PDIPM_ERR_INVALID_ARG, "ordering must be PDIPM_ORDER_LEVELS or PDIPM_ORDER_MULTILEVEL");
   }
+  if (h->opt.precision == PDIPM_PRECISION_AUTO && h->standalone) {
+    delete h;
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "kkt_factor takes its precision per call: no PDIPM_PRECISION_AUTO");
+  }
+  const bool auto_prec = h->opt.precision == PDIPM_PRECISION_AUTO;
   try {
+    if (auto_prec) h->opt.fp64_fallback = 1;
     h->need64 = h->opt.precision == PDIPM_FP64 || h->opt.fp64_fallback;
-    h->need32 = h->opt.precision == PDIPM_FP32;
+    h->need32 = h->opt.precision == PDIPM_FP32 || auto_prec;
     if (!h->sym_ready) analyze(h->graph, h->opt.nd_leaf, h->opt.amalg_menu, &h->sym, h->opt.ordering);
     create_lap("symbolic analysis");
     if (h->aug) {
@@ -1405,6 +1411,12 @@ static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** ou
     }
     finish_analysis(h);
     create_lap("plans and K map");
+    if (auto_prec) {
+      // FP32 factors pay when the factorisation time they save exceeds the
+      // two extra refinement solves an iteration needs at least
+      const CostModel cm = cost_model(h);
+      h->opt.precision = cm.fac64 - cm.fac32 > 2.0 * cm.step32 ? PDIPM_FP32 : PDIPM_FP64;
+    }
     layout(h);
     create_lap("workspace layout");
     hipGetDevice(&h->device);
@@ -1424,9 +1436,9 @@ int ipm_create(const ipm_problem_desc* prob, const ipm_options* opts, ipm_handle
   ipm_handle* h = new (std::nothrow) ipm_handle();
   if (!h) return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
   if (opts) h->opt = *opts; else ipm_default_options(&h->opt);
-  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32) {
+  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32 && h->opt.precision != PDIPM_PRECISION_AUTO) {
     delete h;
-    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64, PDIPM_FP32 or PDIPM_PRECISION_AUTO");
   }
   if (h->opt.kkt_form != PDIPM_KKT_PRIMAL && h->opt.kkt_form != PDIPM_KKT_DUAL &&
       h->opt.kkt_form != PDIPM_KKT_AUGMENTED && h->opt.kkt_form != PDIPM_KKT_AUTO) {
@@ -1564,6 +1576,7 @@ int kkt_analyze(ipm_handle* h, kkt_symbolic_stats* s) {
   s->flops = h->sym.flops;
   s->update_bytes = (double)h->plan64.u_elems * (h->need64 ? 8 : 4);
   s->kkt_form = h->standalone ? -1 : (h->aug ? PDIPM_KKT_AUGMENTED : (h->dual ? PDIPM_KKT_DUAL : PDIPM_KKT_PRIMAL));
+  s->precision = h->opt.precision;
   return PDIPM_OK;
 }
 

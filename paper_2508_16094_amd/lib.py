@@ -16,7 +16,7 @@ SO_PATH = os.path.join(HERE, "libpdipm.so")
 PDIPM_OK, PDIPM_MAX_ITER, PDIPM_TIME_LIMIT, PDIPM_STALLED = 0, 1, 2, 3
 PDIPM_ERR_INVALID_ARG, PDIPM_ERR_OUT_OF_MEMORY, PDIPM_ERR_NOT_PD = -1, -2, -3
 PDIPM_ERR_NUMERICAL, PDIPM_ERR_DEVICE, PDIPM_ERR_NOT_ANALYZED = -4, -5, -6
-PDIPM_FP64, PDIPM_FP32 = 0, 1
+PDIPM_FP64, PDIPM_FP32, PDIPM_PRECISION_AUTO = 0, 1, 2
 PDIPM_HOST, PDIPM_DEVICE = 0, 1
 PDIPM_KKT_PRIMAL, PDIPM_KKT_DUAL, PDIPM_KKT_AUGMENTED, PDIPM_KKT_AUTO = 0, 1, 2, 3
 PDIPM_ORDER_LEVELS, PDIPM_ORDER_MULTILEVEL = 0, 1
@@ -47,7 +47,7 @@ class ipm_options(ctypes.Structure):
 class kkt_symbolic_stats(ctypes.Structure):
     _fields_ = [("n", _i64), ("nnz_K", _i64), ("nnz_L", _i64), ("nnz_L_stored", _i64),
                 ("n_super", _i64), ("max_front", _i64), ("n_levels", _i64), ("n_triples", _i64),
-                ("flops", _f64), ("update_bytes", _f64), ("kkt_form", _i32)]
+                ("flops", _f64), ("update_bytes", _f64), ("kkt_form", _i32), ("precision", _i32)]
 
 
 class kkt_factor_info(ctypes.Structure):

@@ -288,3 +288,31 @@ def test_automatic_form_keeps_the_cheaper_condensed_system(name):
         assert np.array_equal(a[k], b[k]), k
     if name == "lp_block":
         assert st["kkt_form"] == L.PDIPM_KKT_DUAL
+
+
+def test_automatic_precision_follows_the_cost_model():
+    """PDIPM_PRECISION_AUTO resolves at create, from counts only: FP64
+    factors where FP32 ones would save less factorisation time than two
+    extra triangular solves cost (a 500-column LP, a 1,440-point grid NLP),
+    FP32 factors where the factorisation dominates (a 20-block
+    block-angular LP, 1.3e12 flops); explicit precisions report themselves."""
+    cases = [(w.lp_small(), L.PDIPM_FP64), (w.nlp_grid(40, 36), L.PDIPM_FP64),
+             (w.lp_block(nblocks=20), L.PDIPM_FP32)]
+    for p, want in cases:
+        got = [L.IpmSolver(p, precision=L.PDIPM_PRECISION_AUTO).stats()["precision"] for _ in range(2)]
+        assert got == [want, want], (p.name, got)
+    p = w.lp_small()
+    for prec in (L.PDIPM_FP64, L.PDIPM_FP32):
+        assert L.IpmSolver(p, precision=prec).stats()["precision"] == prec
+    # the automatic choice keeps space for both factor precisions
+    s = L.IpmSolver(p, precision=L.PDIPM_PRECISION_AUTO)
+    assert s.workspace_bytes() >= L.IpmSolver(p, precision=L.PDIPM_FP32).workspace_bytes()
+    # batches and the standalone KKT handle take an explicit precision
+    with pytest.raises(L.PdipmError):
+        L.BatchSolver([w.qp_instance(60, 2)], precision=L.PDIPM_PRECISION_AUTO)
+    K = sp.random(30, 30, density=0.2, random_state=1) + 30 * sp.eye(30)
+    lo = sp.tril(K + K.T, format="csr")
+    with pytest.raises(L.PdipmError):
+        L.KktSolver(30, lo.indptr, lo.indices, L.default_options(precision=L.PDIPM_PRECISION_AUTO))
+    with pytest.raises(L.PdipmError):
+        L.IpmSolver(p, precision=3)

@@ -117,3 +117,20 @@ def test_set_precision_checks_the_workspace():
     assert r32["status"] == 0 and r64["status"] == 0
     assert r64["fp64_refactors"] == 0
     assert abs(r32["f"] - r64["f"]) <= 1e-6 * max(1.0, abs(r64["f"]))
+
+
+def test_automatic_precision_solves_to_parity():
+    """PDIPM_PRECISION_AUTO on a latency-bound LP resolves to FP64 factors
+    and solves it like the FP64 form (same iterates bit for bit), within the
+    parity bar of the oracle."""
+    p = w.lp_small()
+    ref = oipm.solve(p, tol=1e-9)
+    sa = L.IpmSolver(p, precision=L.PDIPM_PRECISION_AUTO).bind()
+    assert sa.stats()["precision"] == L.PDIPM_FP64
+    ra = sa.solve()
+    r64 = L.IpmSolver(p, precision=L.PDIPM_FP64).bind().solve()
+    print(ra, r64, flush=True)
+    assert ra["status"] == 0 and ra["fp64_refactors"] == 0
+    for k in ("iterations", "f", "P", "D", "C"):
+        assert ra[k] == r64[k], k
+    assert abs(ra["f"] - ref["f"]) <= 1e-6 * max(1.0, abs(ref["f"]))
