@@ -92,7 +92,19 @@ def bench_batch(args, log):
         loop_t.append(time.time() - t1)
     loop_est = float(np.mean(loop_t)) * len(ps)
     fac_tf = st["flops"] / (ms[chosen] * 1e-3) / 1e12
-    peak = PEAK[args.precision]
+    peak = PEAK["fp32" if prec == L.PDIPM_FP32 else "fp64"]
+    # the same batch with the other factor precision
+    other = L.PDIPM_FP64 if prec == L.PDIPM_FP32 else L.PDIPM_FP32
+    b2 = L.BatchSolver(ps, precision=other).bind()
+    b2.autotune(reps=1)
+    b2.solve()
+    torch.cuda.synchronize()
+    t2 = time.time()
+    res2, info2 = b2.solve()
+    torch.cuda.synchronize()
+    t_other = time.time() - t2
+    del b2
+    log(f"[bench] other precision: {info2}")
     out = {
         "metric": "IPM solves/s + KKT factor TFLOP/s, GB/s; mixed/batched/warm vs FP64 at 1e-6 tol",
         "value": len(ps) * args.steps / elapsed,
@@ -107,6 +119,11 @@ def bench_batch(args, log):
                    "tol": 1e-6, "parallelism": "single GPU"},
         "solved": ok, "iterations_max": int(iters.max()), "iterations_mean": float(iters.mean()),
         "batch_info": info,
+        "other_precision": {"dtype": "f64" if other == L.PDIPM_FP64 else "f32",
+                            "solves_per_s": len(ps) / t_other,
+                            "solved": sum(r["status"] == 0 for r in res2),
+                            "iterations_max": int(max(r["iterations"] for r in res2)),
+                            "fp64_from": info2["fp64_from"]},
         "loop_fp64_single_path": {"sample": len(sample), "mean_s": float(np.mean(loop_t)),
                                   "estimated_total_s": loop_est,
                                   "batched_speedup": loop_est / (elapsed / args.steps)},
