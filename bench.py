@@ -57,10 +57,11 @@ def bench_batch(args, log):
     ps = w.qp_batch(args.count)
     sizes = np.array([p.n for p in ps])
     log(f"[bench] generated {len(ps)} QPs (sum n = {sizes.sum()}) in {time.time() - t:.1f}s")
-    prec = L.PDIPM_FP64 if args.precision == "fp64" else L.PDIPM_FP32
+    prec = {"fp32": L.PDIPM_FP32, "fp64": L.PDIPM_FP64, "auto": L.PDIPM_PRECISION_AUTO}[args.precision]
     t = time.time()
     b = L.BatchSolver(ps, precision=prec, print_level=1 if args.verbose else 0)
     st = b.stats()
+    prec = st["precision"]   # the automatic choice resolved
     log(f"[bench] analysed in {time.time() - t:.1f}s: nnz(L)={st['nnz_L']:.4g} flops={st['flops']:.4g} "
         f"supernodes={st['n_super']} levels={st['n_levels']} workspace={b.workspace_bytes() / 1e9:.2f} GB")
     b.bind()
@@ -387,7 +388,7 @@ def main():
     ap.add_argument("--nblocks", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "auto"],
                     help="factor precision; auto: the library keeps FP32 factors only where its cost model "
-                         "predicts they pay (batches: fp32)")
+                         "predicts they pay")
     ap.add_argument("--form", default="auto", choices=["auto", "primal", "dual", "augmented"],
                     help="KKT system factored each iteration: auto (the condensed system with fewer "
                          "factorisation flops), the primal condensed K (n x n), the dual condensed "

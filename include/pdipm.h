@@ -94,12 +94,15 @@ typedef struct ipm_options {
   double delta_p;        /* primal regularisation, default 1e-8 */
   double delta_d;        /* dual regularisation, default 1e-8 */
   int32_t precision;     /* PDIPM_FP64 or PDIPM_FP32 (workspace sized for it).
-                            PDIPM_PRECISION_AUTO (ipm_create only): space for
-                            both, and ipm_create keeps FP32 factors with FP64
+                            PDIPM_PRECISION_AUTO (ipm_create and
+                            ipm_batch_create): space for both, and the create
+                            call keeps FP32 factors with FP64
                             refinement when the factorisation time they save,
-                            sum_j c_j^2 at 100 against 50 TFLOP/s, exceeds two
-                            FP32 triangular solves per iteration (2 nnz(L) 4
-                            bytes at 3 TB/s plus 6 us per launch), else FP64
+                            sum_j c_j^2 at 100 against 50 TFLOP/s, exceeds the
+                            extra FP32 triangular solves per iteration (2 nnz(L)
+                            4 bytes at 3 TB/s plus 6 us per launch each; two for
+                            a single instance, 2 (min(ir_max, 3) - 1) for a
+                            batch, whose refinement is fixed), else FP64
                             factors: on small or latency-bound systems FP32
                             factors save nothing and refinement costs extra.
                             From counts only, so the choice is deterministic;

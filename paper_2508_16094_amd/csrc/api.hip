@@ -1413,9 +1413,13 @@ static int finish_create(ipm_handle* h, const ipm_options* opts, ipm_handle** ou
     create_lap("plans and K map");
     if (auto_prec) {
       // FP32 factors pay when the factorisation time they save exceeds the
-      // two extra refinement solves an iteration needs at least
+      // extra refinement solves an iteration needs: at least one per
+      // direction for a single instance; for a batch, whose FP32 directions
+      // take a fixed min(ir_max, 3) refinement steps against one with FP64
+      // factors, that difference per direction
       const CostModel cm = cost_model(h);
-      h->opt.precision = cm.fac64 - cm.fac32 > 2.0 * cm.step32 ? PDIPM_FP32 : PDIPM_FP64;
+      const double extra = h->bcount > 0 ? 2.0 * std::max(1, std::min(h->opt.ir_max, 3) - 1) : 2.0;
+      h->opt.precision = cm.fac64 - cm.fac32 > extra * cm.step32 ? PDIPM_FP32 : PDIPM_FP64;
     }
     layout(h);
     create_lap("workspace layout");
@@ -1898,9 +1902,9 @@ int ipm_batch_create(int32_t count, const ipm_problem_desc* probs, const ipm_opt
   ipm_handle* h = new (std::nothrow) ipm_handle();
   if (!h) return fail(nullptr, PDIPM_ERR_OUT_OF_MEMORY, "host allocation failed");
   if (opts) h->opt = *opts; else ipm_default_options(&h->opt);
-  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32) {
+  if (h->opt.precision != PDIPM_FP64 && h->opt.precision != PDIPM_FP32 && h->opt.precision != PDIPM_PRECISION_AUTO) {
     delete h;
-    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64 or PDIPM_FP32");
+    return fail(nullptr, PDIPM_ERR_INVALID_ARG, "precision must be PDIPM_FP64, PDIPM_FP32 or PDIPM_PRECISION_AUTO");
   }
   if (h->opt.kkt_form != PDIPM_KKT_PRIMAL) {
     delete h;

@@ -409,6 +409,19 @@ __device__ inline double lane_bcast(double v, int src) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1 / sqrt(x) for x > 0: the hardware estimate refined by Newton's iteration
+// y <- y (3 - x y^2) / 2 (once in FP32, twice in FP64), cheaper on the
+// factor's dependent chain than a square root and a division.
+__device__ inline float rsqrt_newton(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return y * (1.5f - 0.5f * x * y * y);
+}
+__device__ inline double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+
 // Cholesky factor and inverse of one nb x nb diagonal block (bw <= nb
 // columns used; the rest is padded with the identity), blocked by panels of
 // PB columns in LDS:
@@ -484,7 +497,7 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
           if (lane == 0 && c0 + k < bw) atomicMin(bad, d.col0 + c0 + k);
           dk = (T)1;
         }
-        const T piv = sqrt(dk), rp = (T)1 / piv;
+        const T rp = rsqrt_newton(dk), piv = dk * rp;
         if (lane == 0) rdiag[c0 + k] = rp;
         const T rs = SG ? sk * rp : rp;
 #pragma unroll

@@ -307,9 +307,10 @@ def test_automatic_precision_follows_the_cost_model():
     # the automatic choice keeps space for both factor precisions
     s = L.IpmSolver(p, precision=L.PDIPM_PRECISION_AUTO)
     assert s.workspace_bytes() >= L.IpmSolver(p, precision=L.PDIPM_FP32).workspace_bytes()
-    # batches and the standalone KKT handle take an explicit precision
-    with pytest.raises(L.PdipmError):
-        L.BatchSolver([w.qp_instance(60, 2)], precision=L.PDIPM_PRECISION_AUTO)
+    # a batch of small QPs resolves to FP64 factors as well; the standalone
+    # KKT handle takes an explicit precision
+    b = L.BatchSolver([w.qp_instance(60 + 10 * i, 2 + i) for i in range(8)], precision=L.PDIPM_PRECISION_AUTO)
+    assert b.stats()["precision"] == L.PDIPM_FP64
     K = sp.random(30, 30, density=0.2, random_state=1) + 30 * sp.eye(30)
     lo = sp.tril(K + K.T, format="csr")
     with pytest.raises(L.PdipmError):

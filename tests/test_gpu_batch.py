@@ -224,3 +224,16 @@ def test_batch_iterates_stay_finite_at_a_tight_tolerance():
             assert np.isfinite(vec).all(), (p.name, k)
         chk = checker.check(p, sol["x"], sol["s"], sol["lam"], sol["zl"], sol["zu"])
         assert abs(chk["f"] - r["f"]) <= 1e-9 * max(1.0, abs(r["f"])), (chk, r)
+
+
+def test_batch_automatic_precision():
+    """PDIPM_PRECISION_AUTO on a batch of small QPs resolves to FP64 factors
+    (FP32 ones would save less than their refinement costs) and solves to the
+    parity bar."""
+    ps = _problems()
+    refs = _refs(ps)
+    b = L.BatchSolver(ps, precision=L.PDIPM_PRECISION_AUTO).bind()
+    assert b.stats()["precision"] == L.PDIPM_FP64
+    results, info = b.solve()
+    assert info["fp64_from"] == -1 and info["solved"] == len(ps)
+    _check(ps, refs, results, b.solution())
