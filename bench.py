@@ -261,12 +261,14 @@ def bench_copy(args, log):
 GEMM_SOURCE_REGIONS = (("kernels.hip", "constexpr int TG = 8;", "// C (-)= A * B^T, FP64 MFMA"),
                        ("kernels.hip", "// C (-)= A * B^T, FP32 MFMA",
                         "// --------------------------------------------------- triangular solves"),
-                       ("host.cpp", "P.sld[k] =", "P.srow[k] = s.sn_rowptr[k];"))
+                       ("host.cpp", "P.sld[k] =", "P.srow[k] = s.sn_rowptr[k];"),
+                       ("host.cpp", "int64_t off = 0, uoff = 0, uvoff = 0;", "P.suv[k] = uvoff;"))
 
 
 def gemm_source_digest():
     """sha256 over the source regions that decide the GEMM's memory traffic:
-    tile mapping and load helpers, the FP32 kernel, the panel layout."""
+    tile mapping and load helpers, the FP32 kernel, the panel and
+    update-matrix layout."""
     import hashlib
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2508_16094_amd", "csrc")
     parts = []
@@ -279,7 +281,7 @@ def gemm_source_digest():
 def traffic_of(kernel, workload, alg_bytes_per_launch):
     """HBM bytes per launch of kernel on workload measured with hardware
     counters (profiles/traffic.json), or None when the GEMM source (tile
-    mapping, load helpers, FP32 kernel, panel layout) changed since the
+    mapping, load helpers, FP32 kernel, panel and update-matrix layout) changed since the
     counters were taken,
     or when the launch mix did (the algorithmic bytes per launch differ from
     the recorded ones by more than 0.5%)."""

@@ -369,21 +369,27 @@ void ipm_destroy(ipm_handle* h);
  * problem, so symbolic analysis, assembly, factorisation and the triangular
  * solves run once over all of them (each level of the elimination forest is
  * one launch across instances), while step lengths, centring and
- * termination are per instance.  An iteration is two replays of captured
- * HIP graphs (termination measures; Newton step); the host only reads the
- * count of running instances between them.  FP32 form: FP32 factor, a fixed
- * number min(ir_max, 3) of FP64 refinement steps per solve, and FP64 factors
- * for all instances from the first iteration in which a running instance
- * misses its refinement target 1e-2 tol (1 + ||grad f||) (when fp64_fallback).
- * Instances must have W empty and q4 NULL (LP or QP).
+ * termination are per instance.  The whole solve is one captured HIP graph
+ * of graph_iters iterations (with use_graphs; default 20): a control kernel
+ * sets device flags from the termination measures, every other kernel of
+ * the graph reads its gate flag first, and the host replays the graph until
+ * every instance has ended, reading the flags once per replay.  FP32 form:
+ * FP32 factor and a fixed number min(ir_max, 3) of FP64 refinement steps
+ * per solve; an instance whose direction misses its refinement target
+ * 1e-2 tol (1 + ||grad f||) does not take it but repeats the iteration with
+ * FP64 factors, which every instance uses from then on (when
+ * fp64_fallback).  An instance whose direction is not finite ends with
+ * PDIPM_ERR_NUMERICAL at its current iterate.  Instances must have W empty
+ * and q4 NULL (LP or QP).
  * ------------------------------------------------------------------------- */
 typedef struct ipm_batch ipm_batch;
 
 typedef struct ipm_batch_info {
   int32_t iterations;      /* Newton iterations run (the slowest instance) */
   int32_t solved;          /* instances that reached status PDIPM_OK */
-  int32_t graph_launches;  /* HIP graph replays */
-  int32_t fp64_from;       /* iteration from which FP64 factors were used, -1 never */
+  int32_t graph_launches;  /* HIP graph replays (graph_iters iterations each) */
+  int32_t fp64_from;       /* iteration from which FP64 factors were used (FP32
+                              form), -1 never */
   int32_t factor_failures; /* factorisations that met a non-positive pivot */
   int32_t refine_misses;   /* iterations in which an instance missed its target */
   int32_t blocking;        /* blocking candidate used */

@@ -86,7 +86,7 @@ struct ipm_handle {
   struct Off {
     size_t c, b, q4, xl, xu, jp, jc, ja, jw, jtp, jtr, jte, hp, hc, hq, hdiag, hsp, hsc, hss;
     size_t kmrow, kmc, kmh, kmtp, kmtk, kmta, kmtb, kmpos, ksp, ksc, kss, kval, kmkp, dscale;
-    size_t sfirst, sw, sh, sld, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
+    size_t sfirst, sw, sh, sld, sldu, cptr, child, rel, lsn, snrows, perm, spanel, su, srow, suv;
     size_t gemm64, potrf64, gemm32, potrf32, ext, small, icomb64;
     size_t sdesc64, sdesc32, ssmall64, ssmall32, slarge64, slarge32;
     size_t gitem[2], grow[2], gptr[2], gidx[2];   // forward gather map (FP64, FP32 plan)
@@ -262,7 +262,7 @@ void layout(ipm_handle* h) {
   o.dscale = r.take(n * 8);
   const Plan& P = h->plan64;
   o.sfirst = r.take(bytes_of(P.sfirst)); o.sw = r.take(bytes_of(P.sw)); o.sh = r.take(bytes_of(P.sh));
-  o.sld = r.take(bytes_of(P.sld));
+  o.sld = r.take(bytes_of(P.sld)); o.sldu = r.take(bytes_of(P.sldu));
   o.cptr = r.take(bytes_of(P.child_ptr)); o.child = r.take(bytes_of(P.child)); o.rel = r.take(bytes_of(P.rel));
   o.lsn = r.take(bytes_of(P.level_sn)); o.snrows = r.take(bytes_of(h->sym.sn_rows));
   o.perm = r.take(bytes_of(h->sym.perm)); o.spanel = r.take(bytes_of(P.spanel)); o.su = r.take(bytes_of(P.su));
@@ -377,7 +377,7 @@ int bind_workspace(ipm_handle* h) {
   }
   UP(kmrow, h->km.krow); UP(kmc, h->km.kc); UP(kmpos, h->km.pos); UP(kmkp, h->km.kp);
   const Plan& P = h->plan64;
-  UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(sld, P.sld); UP(cptr, P.child_ptr); UP(child, P.child);
+  UP(sfirst, P.sfirst); UP(sw, P.sw); UP(sh, P.sh); UP(sld, P.sld); UP(sldu, P.sldu); UP(cptr, P.child_ptr); UP(child, P.child);
   UP(rel, P.rel); UP(lsn, P.level_sn); UP(snrows, h->sym.sn_rows); UP(perm, h->sym.perm);
   UP(spanel, P.spanel); UP(su, P.su); UP(srow, P.srow); UP(suv, P.suv);
   if (!h->psign.empty()) UP(sign, h->psign);
@@ -426,7 +426,7 @@ int bind_workspace(ipm_handle* h) {
     const Plan& PP = prec == 0 ? h->plan64 : h->plan32;
     q.ns = PP.ns; q.n = PP.n; q.nb = PP.nb; q.small_h = PP.small_h;
     q.sfirst = at<int32_t>(h, o.sfirst); q.sw = at<int32_t>(h, o.sw); q.sh = at<int32_t>(h, o.sh);
-    q.sld = at<int32_t>(h, o.sld);
+    q.sld = at<int32_t>(h, o.sld); q.sldu = at<int32_t>(h, o.sldu);
     q.child_ptr = at<int32_t>(h, o.cptr); q.child = at<int32_t>(h, o.child); q.rel = at<int32_t>(h, o.rel);
     q.level_sn = at<int32_t>(h, o.lsn); q.sn_rows = at<int32_t>(h, o.snrows); q.perm = at<int32_t>(h, o.perm);
     q.spanel = at<int64_t>(h, o.spanel); q.su = at<int64_t>(h, o.su); q.srow = at<int64_t>(h, o.srow);

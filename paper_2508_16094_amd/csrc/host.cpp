@@ -482,12 +482,20 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
   }
   P.srow[ns] = s.sn_rowptr[ns];
   int64_t off = 0, uoff = 0, uvoff = 0;
+  P.sldu.resize(ns);
   for (int64_t k = 0; k < ns; ++k) {
+    // the panels of fronts taller than the small-front limit and the update
+    // matrices with more than that many rows start on 32-element boundaries
+    // and keep their columns there (leading dimensions multiples of 32);
+    // rules of h and h - w alone, so the layout serves every blocking
+    if (P.sh[k] > SMALL_H_MAX) off = (off + 31) & ~(int64_t)31;
     P.spanel[k] = off;
     off += (int64_t)P.sld[k] * P.sw[k];
     int64_t hu = P.sh[k] - P.sw[k];
+    P.sldu[k] = (int32_t)(hu > SMALL_H_MAX ? (hu + 31) & ~31 : hu);
+    if (hu > SMALL_H_MAX) uoff = (uoff + 31) & ~(int64_t)31;
     P.su[k] = uoff;
-    uoff += hu * hu;
+    uoff += hu * P.sldu[k];
     P.suv[k] = uvoff;
     uvoff += hu;
     P.max_front = std::max<int64_t>(P.max_front, P.sh[k]);
@@ -673,7 +681,7 @@ void build_plan(const Symbolic& s, int esize, Plan* pl, const Blocking& blk) {
                    P.spanel[k] + (int64_t)o0 * ld + o1, ld, ld, ld, h - o1, w - o1, K, 0, 0, 0, 1,
                    P.sfirst[k] + o0, tiles);
         if (h - w > 0)
-          add_gemm(P.su[k], P.spanel[k] + (int64_t)o0 * ld + w, P.spanel[k] + (int64_t)o0 * ld + w, h - w, ld,
+          add_gemm(P.su[k], P.spanel[k] + (int64_t)o0 * ld + w, P.spanel[k] + (int64_t)o0 * ld + w, P.sldu[k], ld,
                    ld, h - w, h - w, K, 1, 0, 0, 1, P.sfirst[k] + o0, tiles);
       }
       if (tiles) P.ops.push_back({OP_UPDATE, gb, (int64_t)P.gemm.size(), tiles});

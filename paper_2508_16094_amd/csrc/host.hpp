@@ -145,6 +145,7 @@ struct Plan {
   int small_h = 64;        // fronts with h <= small_h use the one-workgroup path
   int esize = 8;           // bytes per panel element (8 FP64, 4 FP32)
   std::vector<int32_t> sfirst, sw, sh, sld, sparent, slevel;  // sld: panel leading dim (h rounded up to 4)
+  std::vector<int32_t> sldu;          // update-matrix leading dim (h - w, rounded up to 32 above 64)
   std::vector<int64_t> spanel, su, srow, suv;  // panel / U / row / update-vector offsets
   std::vector<int32_t> child_ptr, child;
   std::vector<int32_t> rel;           // parallel to sn_rows: row position in the parent

@@ -321,9 +321,10 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
     const int hu = P.sh[c] - P.sw[c];
     const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
     const T* U = ubuf + P.su[c];
+    const int ldu = P.sldu[c];
     for (int idx = threadIdx.x; idx < hu * hu; idx += BS) {
       int i = idx % hu, j = idx / hu;
-      if (i >= j) F[rc[i] + rc[j] * LD] += U[i + (int64_t)j * hu];
+      if (i >= j) F[rc[i] + rc[j] * LD] += U[i + (int64_t)j * ldu];
     }
     __syncthreads();
   }
@@ -354,11 +355,11 @@ __global__ void __launch_bounds__(BS) k_small_front(DevPlan P, int64_t d0, T* pa
     int i = idx % h, j = idx / h;
     if (i >= j) panel[poff + i + (int64_t)j * ld] = F[i + j * LD];
   }
-  const int hu = h - w;
+  const int hu = h - w, ldu = P.sldu[S];
   T* U = ubuf + P.su[S];
   for (int idx = threadIdx.x; idx < hu * hu; idx += BS) {
     int i = idx % hu, j = idx / hu;
-    if (i >= j) U[i + (int64_t)j * hu] = F[(w + i) + (w + j) * LD];
+    if (i >= j) U[i + (int64_t)j * ldu] = F[(w + i) + (w + j) * LD];
   }
 }
 
@@ -373,12 +374,13 @@ __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* pan
   const int hP = P.sh[S], wP = P.sw[S], ldP = P.sld[S];
   T* pan = panel + P.spanel[S];
   T* UP = ubuf + P.su[S];
-  const int64_t ldu = hP - wP;
+  const int64_t ldu = P.sldu[S];
   for (int32_t q = P.child_ptr[S]; q < P.child_ptr[S + 1]; ++q) {
     const int32_t c = P.child[q];
     const int hu = P.sh[c] - P.sw[c];
     const int32_t* rc = P.rel + P.srow[c] + P.sw[c];
     const T* U = ubuf + P.su[c];
+    const int64_t lduc = P.sldu[c];
     int lo = 0, hi = hu;
     while (lo < hi) { int mid = (lo + hi) >> 1; if (rc[mid] < d.t0) lo = mid + 1; else hi = mid; }
     int jlo = lo;
@@ -389,7 +391,7 @@ __global__ void __launch_bounds__(BS) k_extend_add(DevPlan P, int64_t d0, T* pan
       const int tj = rc[j];
       for (int i = j + threadIdx.x; i < hu; i += BS) {
         const int ti = rc[i];
-        const T v = U[i + (int64_t)j * hu];
+        const T v = U[i + (int64_t)j * lduc];
         if (tj < wP) pan[ti + (int64_t)tj * ldP] += v;
         else UP[(ti - wP) + (int64_t)(tj - wP) * ldu] += v;
       }

@@ -22,7 +22,7 @@ struct DevProblem {
 struct DevPlan {
   int64_t ns, n;
   int nb, small_h;
-  const int32_t *sfirst, *sw, *sh, *sld, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
+  const int32_t *sfirst, *sw, *sh, *sld, *sldu, *child_ptr, *child, *rel, *level_sn, *sn_rows, *perm;
   const int64_t *spanel, *su, *srow, *suv, *sinv;
   const GemmDesc* gemm; const PotrfDesc* potrf; const ExtAddDesc* ext; const int32_t* small;
   const InvCombDesc* icomb;
