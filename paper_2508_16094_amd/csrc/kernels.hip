@@ -793,11 +793,23 @@ __device__ inline int64_t xcd_tile(int64_t bid, int64_t grid) {
   return (bid & 7) * per + (bid >> 3);
 }
 
+// Descriptor of tile bid: the last of d0 .. d1-1 whose first tile is at or
+// before bid.  Each wave searches by 64-way splits, one load per lane and
+// round (two rounds for up to 4096 descriptors; a binary search was a chain
+// of log2(d1 - d0) dependent loads at the start of every tile).  Every wave
+// finds the same descriptor.
 __device__ inline int64_t find_desc(const GemmDesc* g, int64_t d0, int64_t d1, int64_t bid) {
-  int64_t lo = d0, hi = d1 - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (g[mid].tile_begin <= bid) lo = mid; else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int64_t lo = d0, n = d1 - d0;
+  while (n > 1) {
+    const int64_t step = (n + 63) >> 6;
+    const int64_t idx = lo + (int64_t)lane * step;
+    // lanes whose split point starts at or before bid form a prefix; lane 0's
+    // (lo) always does
+    const bool ok = idx < lo + n && g[idx].tile_begin <= bid;
+    const int last = 63 - __builtin_clzll((unsigned long long)__ballot(ok));
+    lo += (int64_t)last * step;
+    n = n - (int64_t)last * step < step ? n - (int64_t)last * step : step;
   }
   return lo;
 }
