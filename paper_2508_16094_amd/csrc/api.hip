@@ -308,11 +308,11 @@ void layout(ipm_handle* h) {
   const int64_t jn = std::max<int64_t>((int64_t)p.jc.size(), 1), hn = std::max<int64_t>((int64_t)p.hc.size(), 1);
   const int64_t sizes[] = {
       nv, mv, mv, nv, nv,          // 0 x, 1 s, 2 lam, 3 zl, 4 zu
-      nv, nv, mv, jn, hn,          // 5 gf, 6 qx, 7 g, 8 jv, 9 hv
+      nv, nv, mv, 2 * jn, hn,      // 5 gf, 6 qx, 7 g, 8 jv (row order, then transposed), 9 hv
       nv, mv, mv, nv,              // 10 rd, 11 rp, 12 sig_s, 13 sig_x
       nv, mv, nv, mv,              // 14 tmp_n, 15 tmp_m, 16 tmp_n2, 17 tmp_m2
       nv, mv, mv, nv, nv,          // 18..22 trial x, s, lam, zl, zu
-      nv, nv, mv, jn, nv, mv,      // 23 gf, 24 qx, 25 g, 26 jv, 27 rd, 28 rp
+      nv, nv, mv, 2 * jn, nv, mv,  // 23 gf, 24 qx, 25 g, 26 jv (as 8), 27 rd, 28 rp
       nv, mv, mv, nv, nv,          // 29..33 affine dx, ds, dlam, dzl, dzu
       nv, mv, mv, nv, nv,          // 34..38 dx, ds, dlam, dzl, dzu
       mv, nv, nv, nv,              // 39 ts, 40 tl, 41 tu, 42 rhs
@@ -843,9 +843,9 @@ int run_ipm(ipm_handle* h, const ipm_start* st, ipm_result* res) {
   auto ms_since = [&](clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); };
   // constant derivatives for LP/QP
   if (kind != KIND_NLP) {
-    launch_copy(P.nnz_j, v.jv, P.ja, h->stream);
+    launch_jv_copy(P, v.jv, h->stream);
     launch_copy(P.nnz_h, v.hv, P.hq, h->stream);
-    launch_copy(P.nnz_j, h->tv.jv, P.ja, h->stream);
+    launch_jv_copy(P, h->tv.jv, h->stream);
   }
   if (st) {
     const hipMemcpyKind kd = st->memspace == PDIPM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1164,7 +1164,7 @@ int ensure_stream(ipm_handle* h) {
 int batch_start(ipm_handle* h, const ipm_start* st) {
   const DevProblem& P = h->dp;
   IpmVecs& v = h->v;
-  launch_copy(P.nnz_j, v.jv, P.ja, h->stream);
+  launch_jv_copy(P, v.jv, h->stream);
   launch_copy(P.nnz_h, v.hv, P.hq, h->stream);
   launch_batch_init(h->bd, h->opt.precision == PDIPM_FP64 ? 1 : 0, h->stream);
   if (st) {

@@ -131,24 +131,40 @@ __global__ void k_hess_eval(int64_t n, const int64_t* hp, const int64_t* hdiag, 
   hv[hdiag[i]] += (q4 ? 3.0 * q4[i] * xi * xi : 0.0) + 2.0 * wl;
 }
 
-__global__ void k_jt_mul(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
-                         const double* jv, const double* y, double* out, const int* gate) {
+// Column-major copy of J's values (the second half of every J value array):
+// jvt[q] = jv[jte[q]] in the transpose's order, so that products with J'
+// read the values contiguously instead of gathering them.
+__global__ void k_jv_transpose(int64_t nnz, const int32_t* jte, const double* jv, double* jvt, const int* gate) {
+  if (gate && *gate == 0) return;   // gated launch whose gate is closed
+  int64_t q = blockIdx.x * (int64_t)BS + threadIdx.x;
+  if (q < nnz) jvt[q] = jv[jte[q]];
+}
+
+// J' y: one thread per column over the column-major values.
+__global__ void k_jt_mul(int64_t n, const int64_t* jtp, const int32_t* jtr, const double* jvt,
+                         const double* y, double* out, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
   int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
-  for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) acc += jv[jte[q]] * y[jtr[q]];
+  for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) acc += jvt[q] * y[jtr[q]];
   out[i] = acc;
 }
 
+// J v: JROW lanes per row stride over its entries (coalesced), then a fixed
+// butterfly sums the lanes.
+constexpr int JROW = 8;
 __global__ void k_j_mul(int64_t m, const int64_t* jp, const int32_t* jc, const double* jv,
                         const double* v, double* out, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
-  int64_t k = blockIdx.x * (int64_t)BS + threadIdx.x;
-  if (k >= m) return;
+  const int64_t k = blockIdx.x * (int64_t)(BS / JROW) + threadIdx.x / JROW;
+  const int g = threadIdx.x % JROW;
   double acc = 0.0;
-  for (int64_t e = jp[k]; e < jp[k + 1]; ++e) acc += jv[e] * v[jc[e]];
-  out[k] = acc;
+  if (k < m)
+    for (int64_t e = jp[k] + g; e < jp[k + 1]; e += JROW) acc += jv[e] * v[jc[e]];
+#pragma unroll
+  for (int o = JROW / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (k < m && g == 0) out[k] = acc;
 }
 
 __global__ void k_h_mul(int64_t n, const int64_t* hsp, const int32_t* hsc, const int32_t* hss,
@@ -283,15 +299,15 @@ __global__ void k_dual_finish(int64_t n, const double* d, const double* r, const
 
 // max_i K_ii with K_ii = 1/D_i + sum_k Sigma_s[k] J_ki^2 (the norm estimate
 // of K used by the backward error when K itself is never formed)
-__global__ void k_kdiag_max(int64_t n, const int64_t* jtp, const int32_t* jtr, const int32_t* jte,
-                            const double* jv, const double* sig_s, const double* dd, double* partials, const int* gate) {
+__global__ void k_kdiag_max(int64_t n, const int64_t* jtp, const int32_t* jtr, const double* jvt,
+                            const double* sig_s, const double* dd, double* partials, const int* gate) {
   if (gate && *gate == 0) return;   // gated launch whose gate is closed
   RedSpec spec{1, {RED_MAX}};
   double a[1] = {0.0};
   for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
     double k = 1.0 / dd[i];
     for (int64_t q = jtp[i]; q < jtp[i + 1]; ++q) {
-      const double j = jv[jte[q]];
+      const double j = jvt[q];
       k += sig_s[jtr[q]] * j * j;
     }
     a[0] = fmax(a[0], k);
@@ -1813,9 +1829,15 @@ void launch_finalize(const double* partials, int nblocks, RedSpec spec, double* 
   k_finalize<<<1, BS, 0, s>>>(partials, nblocks, spec, out, launch_gate());
 }
 
+void launch_jv_copy(const DevProblem& P, double* jv, hipStream_t s) {
+  if (P.nnz_j == 0) return;
+  launch_copy(P.nnz_j, jv, P.ja, s);
+  k_jv_transpose<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.jte, jv, jv + P.nnz_j, launch_gate());
+}
 void launch_jac_eval(const DevProblem& P, const double* x, double* jv, hipStream_t s) {
   if (P.nnz_j == 0) return;
   k_jac_eval<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.ja, P.jw, P.jc, x, jv, launch_gate());
+  k_jv_transpose<<<(unsigned)blocks_for(P.nnz_j), BS, 0, s>>>(P.nnz_j, P.jte, jv, jv + P.nnz_j, launch_gate());
 }
 void launch_constraints(const DevProblem& P, const double* x, double* g, hipStream_t s) {
   if (P.m == 0) return;
@@ -1829,11 +1851,12 @@ void launch_hess_eval(const DevProblem& P, const double* x, const double* lam, d
                                                         P.jw, x, lam, hv, launch_gate());
 }
 void launch_jt_mul(const DevProblem& P, const double* jv, const double* y, double* out, hipStream_t s) {
-  k_jt_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, y, out, launch_gate());
+  k_jt_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.jtp, P.jtr, jv + P.nnz_j, y, out, launch_gate());
 }
 void launch_j_mul(const DevProblem& P, const double* jv, const double* v, double* out, hipStream_t s) {
   if (P.m == 0) return;
-  k_j_mul<<<(unsigned)blocks_for(P.m), BS, 0, s>>>(P.m, P.jp, P.jc, jv, v, out, launch_gate());
+  const int64_t g = (P.m + BS / JROW - 1) / (BS / JROW);
+  if (g > 0) k_j_mul<<<(unsigned)g, BS, 0, s>>>(P.m, P.jp, P.jc, jv, v, out, launch_gate());
 }
 void launch_h_mul(const DevProblem& P, const double* hv, const double* v, double* out, hipStream_t s) {
   k_h_mul<<<(unsigned)blocks_for(P.n), BS, 0, s>>>(P.n, P.hsp, P.hsc, P.hss, hv, v, out, launch_gate());
@@ -2087,7 +2110,7 @@ void launch_dual_finish(int64_t n, const double* d, const double* r, const doubl
 void launch_kdiag_max(const DevProblem& P, const double* jv, const double* sig_s, const double* dd,
                       double* partials, hipStream_t s) {
   int g = red_grid(P.n);
-  k_kdiag_max<<<g, BS, 0, s>>>(P.n, P.jtp, P.jtr, P.jte, jv, sig_s, dd, partials, launch_gate());
+  k_kdiag_max<<<g, BS, 0, s>>>(P.n, P.jtp, P.jtr, jv + P.nnz_j, sig_s, dd, partials, launch_gate());
   RedSpec spec{1, {RED_MAX}};
   launch_finalize(partials, g, spec, partials + 8 * RED_BLOCKS, s);
 }

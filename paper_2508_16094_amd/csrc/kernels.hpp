@@ -56,8 +56,12 @@ void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 void launch_fill_bytes0(void* p, int64_t bytes, hipStream_t s);  // zero via kernel
 void launch_finalize(const double* partials, int nblocks, RedSpec spec, double* out, hipStream_t s);
 
-// model evaluation (Section 1 problem form, Section 4 derivative templates)
+// model evaluation (Section 1 problem form, Section 4 derivative templates).
+// A J value array holds 2 nnz_j entries: the values in J's row order, then
+// the same values in the transpose's order (written by launch_jac_eval and
+// launch_jv_copy, read by the products with J').
 void launch_jac_eval(const DevProblem& P, const double* x, double* jv, hipStream_t s);
+void launch_jv_copy(const DevProblem& P, double* jv, hipStream_t s);   // constant J (A)
 void launch_constraints(const DevProblem& P, const double* x, double* g, hipStream_t s);
 void launch_gradient(const DevProblem& P, const double* x, double* qx, double* gf, hipStream_t s);
 void launch_hess_eval(const DevProblem& P, const double* x, const double* lam, double* hv, hipStream_t s);
