@@ -42,6 +42,12 @@ def test_traffic_record_applies_only_to_its_source_and_launch_mix():
     assert bm.traffic_of("k_gemm_f32", "lp_block50_dual", alg) is None
     assert bm.traffic_of("k_gemm_f64", "lp_block200_dual", alg) is None
     assert bm.traffic_of("k_gemm_f32", "lp_block200_primal", alg) is None
+    # the FP64 GEMM's record, under the same rules
+    r64 = rec["k_gemm_f64@lp_block200_dual"]
+    alg64 = r64["algorithmic_bytes_per_launch"]
+    if r64["gemm_source_sha256"] == bm.gemm_source_digest():
+        assert bm.traffic_of("k_gemm_f64", "lp_block200_dual", alg64) == r64["bytes_per_launch"]
+    assert bm.traffic_of("k_gemm_f64", "lp_block200_dual", alg64 * 0.99) is None
 
 
 def test_traffic_record_is_consistent():
