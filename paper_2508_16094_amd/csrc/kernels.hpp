@@ -161,7 +161,5 @@ void launch_cg_step(int64_t n, double alpha, const double* p, const double* q, d
                     double* partials, hipStream_t s);
 void launch_xpby(int64_t n, const double* z, double beta, double* p, hipStream_t s);
 void launch_copy(int64_t n, double* dst, const double* src, hipStream_t s);
-void launch_f32_from_f64(int64_t n, float* dst, const double* src, hipStream_t s);
-void launch_f64_from_f32(int64_t n, double* dst, const float* src, hipStream_t s);
 
 }  // namespace pdipm
