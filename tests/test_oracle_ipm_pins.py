@@ -2,6 +2,8 @@
 mathematics fixes independently of it (test infrastructure).
 
 P1 vertex enumeration of tiny LPs (an LP optimum is attained at a vertex)
+P1b LP optima against an independent LP solver (HiGHS through scipy), at
+    sizes past enumeration, including the block-angular structure
 P2 closed-form QP optima (separable box QP; one-constraint diagonal QP)
 P3 NLP special cases (c = 0 gives x* = 0; small c leaves constraints
    inactive so x* solves x^3 + c + Lx = 0)
@@ -42,6 +44,32 @@ def test_p1_tiny_lp_vertex_enumeration(seed, form):
     r = ipm.solve(p, tol=1e-10, form=form)
     assert r["status"] == ipm.OK
     assert abs(r["f"] - f_star) <= 1e-7 * max(1.0, abs(f_star))
+
+
+def _highs_lp(p):
+    """min c'x over {Ax >= b, l <= x <= u} by HiGHS (scipy's linprog)."""
+    from scipy.optimize import linprog
+    r = linprog(p.c, A_ub=-p.A.to_scipy(), b_ub=-p.b, bounds=list(zip(p.xl, p.xu)), method="highs")
+    assert r.status == 0, r.message
+    return float(r.fun)
+
+
+_P1B_CASES = [("random", s) for s in range(3)] + [("block", s) for s in range(2)]
+
+
+@pytest.mark.parametrize("form", ["primal", "dual", "augmented"])
+@pytest.mark.parametrize("case", _P1B_CASES, ids=[f"{k}{s}" for k, s in _P1B_CASES])
+def test_p1b_lp_against_highs(case, form):
+    kind, seed = case
+    if kind == "random":
+        p = w.random_lp(60, 25, 4, 900 + seed)
+    else:   # 4 blocks of 10 x 20 with 3 linking rows, the benchmark LP's shape
+        p = w.lp_block(4, 10, 20, nnz_per_col=3, n_link_rows=3, link_nnz=3, link_cols_per_block=5,
+                       instance=seed)
+    f_star = _highs_lp(p)
+    r = ipm.solve(p, tol=1e-10, form=form)
+    assert r["status"] == ipm.OK
+    assert abs(r["f"] - f_star) <= 1e-8 * max(1.0, abs(f_star))
 
 
 class _P:
