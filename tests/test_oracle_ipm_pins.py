@@ -5,6 +5,9 @@ P1 vertex enumeration of tiny LPs (an LP optimum is attained at a vertex)
 P1b LP optima against an independent LP solver (HiGHS through scipy), at
     sizes past enumeration, including the block-angular structure
 P2 closed-form QP optima (separable box QP; one-constraint diagonal QP)
+P2b QP optima against scipy's trust-region constrained method, with Q
+    written out in the test (diagonal instances of the batch workload and a
+    grid-Laplacian Q)
 P3 NLP special cases (c = 0 gives x* = 0; small c leaves constraints
    inactive so x* solves x^3 + c + Lx = 0)
 P7 duality gap and interior invariants along the iteration
@@ -70,6 +73,54 @@ def test_p1b_lp_against_highs(case, form):
     r = ipm.solve(p, tol=1e-10, form=form)
     assert r["status"] == ipm.OK
     assert abs(r["f"] - f_star) <= 1e-8 * max(1.0, abs(f_star))
+
+
+def _trust_constr_qp(p, Q):
+    """min c'x + x'Qx/2 over {Ax >= b, l <= x <= u} by scipy's trust-region
+    constrained method, Q dense."""
+    from scipy.optimize import Bounds, LinearConstraint, minimize
+    A = p.A.to_scipy().toarray()
+    x0 = (p.xl + np.minimum(p.xu, p.xl + 1.0)) / 2
+    r = minimize(lambda x: p.c @ x + 0.5 * x @ Q @ x, x0, jac=lambda x: p.c + Q @ x, hess=lambda x: Q,
+                 method="trust-constr", constraints=[LinearConstraint(A, p.b, np.inf)],
+                 bounds=Bounds(p.xl, p.xu), options={"gtol": 1e-12, "xtol": 1e-14, "maxiter": 5000})
+    assert r.status in (1, 2), r.message
+    return float(r.fun)
+
+
+def _grid_q_dense(nx, ny, shift):
+    """4-neighbour grid Laplacian plus shift I, entry by entry (node (i, j) is
+    i ny + j)."""
+    n = nx * ny
+    Q = np.zeros((n, n))
+    for i in range(nx):
+        for j in range(ny):
+            k = i * ny + j
+            Q[k, k] = shift
+            for a, b in ((i + 1, j), (i - 1, j), (i, j + 1), (i, j - 1)):
+                if 0 <= a < nx and 0 <= b < ny:
+                    Q[k, k] += 1.0
+                    Q[k, a * ny + b] = -1.0
+    return Q
+
+
+@pytest.mark.parametrize("case", ["diag0", "diag1", "diag2", "grid"])
+def test_p2b_qp_against_trust_constr(case):
+    if case == "grid":
+        p = w.random_lp(30, 15, 3, 4242)
+        p.Q = w.grid_laplacian_lower(5, 6, shift=0.5)
+        Q = _grid_q_dense(5, 6, 0.5)
+        forms = ["primal", "augmented"]          # the dual system needs a diagonal Hessian
+    else:
+        p = w.qp_instance(30, int(case[-1]))
+        assert np.array_equal(p.Q.colind, np.arange(30))
+        Q = np.diag(p.Q.val)
+        forms = ["primal", "dual", "augmented"]
+    f_star = _trust_constr_qp(p, Q)
+    for form in forms:
+        r = ipm.solve(p, tol=1e-10, form=form)
+        assert r["status"] == ipm.OK, form
+        assert abs(r["f"] - f_star) <= 1e-7 * max(1.0, abs(f_star)), form
 
 
 class _P:
