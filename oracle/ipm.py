@@ -158,20 +158,18 @@ def solve(problem, tol=1e-6, max_iter=500, delta_p=1e-8, delta_d=1e-8,
             status = TIME_LIMIT
             break
         if fac is None:
-            Jc = J.tocsr()
+            # symbolic analysis once, on the fixed patterns of J and H
+            j_rp, j_ci = model.jacobian_pattern(problem)
+            h_rp, h_ci = model.hessian_lower_pattern(problem)
             if form == "augmented":
-                Hl = sp.tril(H).tocsr()
-                aug_sym = symbolic.analyze(symbolic.augmented_pattern(n, m, Jc.indptr, Jc.indices, Hl.indptr,
-                                                                      Hl.indices), n + m)
+                aug_sym = symbolic.analyze(symbolic.augmented_pattern(n, m, j_rp, j_ci, h_rp, h_ci), n + m)
                 fac = chol.SparseFactor(aug_sym["perm"], aug_sym["structs"])
                 fac.count = 0
                 block_sign = np.concatenate([np.ones(n), -np.ones(m)])[aug_sym["perm"]]
             elif form == "dual":
-                fac = Factorizer(m, lambda: symbolic.dual_pattern(m, n, Jc.indptr, Jc.indices), dense_max)
+                fac = Factorizer(m, lambda: symbolic.dual_pattern(m, n, j_rp, j_ci), dense_max)
             else:
-                Hl = sp.tril(H).tocsr()
-                fac = Factorizer(n, lambda: symbolic.kkt_pattern(n, Jc.indptr, Jc.indices, Hl.indptr,
-                                                                 Hl.indices), dense_max)
+                fac = Factorizer(n, lambda: symbolic.kkt_pattern(n, j_rp, j_ci, h_rp, h_ci), dense_max)
         sig_s, sig_x = kkt.sigmas(x, s, lam, zl, zu, xl, xu, il, iu, delta_d)
         delta_w = 0.0
         if form == "augmented":

@@ -59,6 +59,38 @@ def jacobian(problem, x):
     return (A - 2.0 * W @ sp.diags(x)).tocsr()
 
 
+def jacobian_pattern(problem):
+    """CSR structure (row pointers, column indices) of J's fixed pattern: the
+    union of the patterns of A and W, whatever the values of x (Section 4:
+    derivatives live on fixed sparsity patterns; Section 2: the symbolic
+    analysis is done once on that pattern).  Taken from the values of J at
+    one point instead, entries of W that vanish there (x_j = 0) would be
+    missing from the pattern."""
+    n, m = problem.n, problem.m
+    S = sp.csr_matrix((m, n))
+    for M in (problem.A, problem.W):
+        if M is not None and int(M.rowptr[-1]) > 0:
+            S = S + sp.csr_matrix((np.ones(int(M.rowptr[-1])), np.asarray(M.colind), np.asarray(M.rowptr)),
+                                  shape=(m, n))
+    S = S.tocsr()
+    S.sort_indices()
+    return S.indptr, S.indices
+
+
+def hessian_lower_pattern(problem):
+    """CSR structure of the lower triangle of H's fixed pattern: Q's lower
+    triangle plus the full diagonal (the q4 and W' lambda terms)."""
+    n = problem.n
+    S = sp.eye(n, format="csr")
+    if problem.Q is not None and int(problem.Q.rowptr[-1]) > 0:
+        Q = problem.Q
+        S = S + sp.csr_matrix((np.ones(int(Q.rowptr[-1])), np.asarray(Q.colind), np.asarray(Q.rowptr)),
+                              shape=(n, n))
+    S = sp.tril(S).tocsr()
+    S.sort_indices()
+    return S.indptr, S.indices
+
+
 def hessian(problem, x, lam):
     """Symmetric Lagrangian Hessian Q + diag(3 q4 x^2 + 2 W' lam)."""
     A, W, Q, q4 = parts(problem)

@@ -10,6 +10,8 @@ P2b QP optima against scipy's trust-region constrained method, with Q
     grid-Laplacian Q)
 P3 NLP special cases (c = 0 gives x* = 0; small c leaves constraints
    inactive so x* solves x^3 + c + Lx = 0)
+P3b NLP optima with active quadratic constraints against scipy's trust-region
+    constrained method, objective and constraints written out in the test
 P7 duality gap and interior invariants along the iteration
 """
 import itertools
@@ -121,6 +123,43 @@ def test_p2b_qp_against_trust_constr(case):
         r = ipm.solve(p, tol=1e-10, form=form)
         assert r["status"] == ipm.OK, form
         assert abs(r["f"] - f_star) <= 1e-7 * max(1.0, abs(f_star)), form
+
+
+def _grid_stencil_rows(nx, ny):
+    """Rows of the grid NLP's constraint weights: for every node (i, j) with
+    i + j even, 1/5 on the node and its in-grid 4-neighbours."""
+    rows = []
+    for i in range(nx):
+        for j in range(ny):
+            if (i + j) % 2 == 0:
+                rows.append([a * ny + b for a, b in ((i, j), (i - 1, j), (i + 1, j), (i, j - 1), (i, j + 1))
+                             if 0 <= a < nx and 0 <= b < ny])
+    S = np.zeros((len(rows), nx * ny))
+    for k, r in enumerate(rows):
+        S[k, r] = 0.2
+    return S
+
+
+@pytest.mark.parametrize("form", ["primal", "augmented"])
+@pytest.mark.parametrize("nx,ny,scale,inst", [(5, 6, 4.0, 0), (5, 6, 4.0, 1), (6, 6, 6.0, 2)])
+def test_p3b_nlp_active_constraints_against_trust_constr(nx, ny, scale, inst, form):
+    """min sum(x^4/4 + c x) + x'Lx/2 s.t. 1 - S (x o x) >= 0, with c scaled so
+    that some constraints are active at the optimum."""
+    from scipy.optimize import NonlinearConstraint, minimize
+    p = w.nlp_grid(nx, ny, inst)
+    p.c = p.c * scale
+    L = _grid_q_dense(nx, ny, 0.0)
+    S = _grid_stencil_rows(nx, ny)
+    con = NonlinearConstraint(lambda x: 1 - S @ (x * x), 0, np.inf, jac=lambda x: -2 * S * x[None, :],
+                              hess=lambda x, v: -2 * np.diag(S.T @ v))
+    ref = minimize(lambda x: np.sum(x ** 4) / 4 + p.c @ x + 0.5 * x @ L @ x, np.zeros(nx * ny),
+                   jac=lambda x: p.c + x ** 3 + L @ x, hess=lambda x: L + np.diag(3 * x ** 2),
+                   method="trust-constr", constraints=[con], options={"gtol": 1e-12, "xtol": 1e-14, "maxiter": 5000})
+    assert ref.status in (1, 2), ref.message
+    assert np.sum(1 - S @ (ref.x * ref.x) < 1e-6) >= 2      # constraints active at the optimum
+    r = ipm.solve(p, tol=1e-10, form=form)
+    assert r["status"] == ipm.OK
+    assert abs(r["f"] - ref.fun) <= 1e-7 * max(1.0, abs(ref.fun))
 
 
 class _P:
