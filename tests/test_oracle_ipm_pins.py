@@ -59,7 +59,8 @@ def _highs_lp(p):
     return float(r.fun)
 
 
-_P1B_CASES = [("random", s) for s in range(3)] + [("block", s) for s in range(2)]
+_P1B_CASES = ([("random", s) for s in range(3)] + [("block", s) for s in range(2)]
+              + [("one_sided", s) for s in range(3)])
 
 
 @pytest.mark.parametrize("form", ["primal", "dual", "augmented"])
@@ -68,6 +69,11 @@ def test_p1b_lp_against_highs(case, form):
     kind, seed = case
     if kind == "random":
         p = w.random_lp(60, 25, 4, 900 + seed)
+    elif kind == "one_sided":   # every other variable has no upper bound (and a cost >= 0)
+        p = w.random_lp(60, 25, 4, 950 + seed)
+        up_free = np.arange(p.n) % 2 == 0
+        p.xu = np.where(up_free, np.inf, p.xu)
+        p.c = np.where(up_free, np.abs(p.c), p.c)
     else:   # 4 blocks of 10 x 20 with 3 linking rows, the benchmark LP's shape
         p = w.lp_block(4, 10, 20, nnz_per_col=3, n_link_rows=3, link_nnz=3, link_cols_per_block=5,
                        instance=seed)
